@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of the single-variable update sweep on one MI355X.
+
+Default workload (the headline configuration): sparse Erdos-Renyi QUIO, N = 10,000 integer
+variables in [-50, 50], mean degree 8, heat bath, automatic schedule, 2000 sweeps, 256 reads.
+One step = one complete annealing run of all reads (random initial states, energy, every sweep,
+final states and energies) = one kernel launch on device-resident inputs.
+
+Prints ONE JSON line: metric/value (updates per second), roofline of the annealing kernel, and the
+CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+# FP64 flops per heat-bath weight w = exp(-beta * dE): one multiply, the exp evaluation and the
+# two additions of the blocked cumulative sum (running sum + block offset).  The exp evaluation
+# is counted as the FP64 operations the gfx950 exp sequence executes (FMA = 2 flops).
+FP64_FLOPS_PER_WEIGHT = 30.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis"])
+    ap.add_argument("--sweeps", type=int, default=0, help="override the number of sweeps")
+    ap.add_argument("--reads", type=int, default=0, help="override the number of reads")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reads", type=int, default=32)
+    ap.add_argument("--cpu-sweeps", type=int, default=100)
+    return ap.parse_args()
+
+
+def workload(args):
+    from paper_2511_17245_amd import inputs as I
+    if args.config == "cfg1":
+        w = I.cfg1_dense_quio()
+    elif args.config == "cfg2":
+        w = I.cfg2_sparse_quio()
+    else:
+        w = I.cfg3_huio(rule=args.config.split("-")[1])
+    if args.sweeps:
+        w.n_sweeps = args.sweeps
+        w.beta = None if w.beta is None else w.beta[: args.sweeps]
+    if args.reads:
+        w.n_reads = args.reads
+    return w
+
+
+def cpu_baseline(w, beta, n_reads, n_sweeps):
+    """The oracle (paper's coefficient-cache mode), as it stands, on a bounded sample."""
+    import numpy as np
+    import oracle
+    P = oracle.Poly(w.problem)
+    threads = oracle.default_threads()
+    b = np.ascontiguousarray(beta[:n_sweeps])
+    # the sample runs the first n_sweeps of the real schedule, so the high-temperature phase
+    # (most accepted moves, most coefficient updates) is represented
+    t0 = time.perf_counter()
+    P.anneal(w.rule, b, n_reads, w.seed, w.instance_id, cache_mode=1, n_threads=threads)
+    dt = time.perf_counter() - t0
+    upd = n_reads * n_sweeps * w.problem.n_vars
+    return {"value": upd / dt, "unit": "updates/s", "cores": min(threads, n_reads), "kind": "oracle",
+            "sample": f"{n_reads} reads x first {n_sweeps} of {w.n_sweeps} sweeps of the same workload "
+                      f"({upd:.3g} updates, {dt:.1f} s, coefficient-cache mode)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2511_17245_amd import sa
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = workload(args)
+    prob = w.problem
+    n, S, R = prob.n_vars, w.n_sweeps, w.n_reads
+    beta = w.beta if w.beta is not None else sa.auto_schedule(prob, S)
+    plan = sa.Plan(prob, w.rule)
+    info = plan.info()
+    z = torch.empty((R, n), dtype=torch.int32, device="cuda")
+    e = torch.empty(R, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.run_device(S, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
+                        instance_id=w.instance_id)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for i in range(args.steps):
+        step()
+        print(f"[bench] queued step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop) / args.steps   # one kernel per step on this stream
+    launch = plan.last_launch()
+    updates = R * S * n
+    value = updates / (ms / 1e3)
+
+    e_host = e.cpu().numpy()
+    W_mean = float(np.mean(prob.upper.astype(np.int64) - prob.lower + 1))
+    if w.rule == sa.HEAT_BATH:
+        flops = updates * W_mean * FP64_FLOPS_PER_WEIGHT
+        achieved = flops / (ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+    else:
+        # Metropolis / OTM: instance bytes streamed per update (incidence records + coefficients)
+        rec_bytes = info["n_incidences"] * (16 + 8) / n
+        achieved = updates * rec_bytes / (ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+
+    out = {
+        "metric": "single-variable updates/sec at 1 GPU",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_vars": n, "n_sweeps": S, "n_reads": R,
+                   "rule": sa.RULE_NAMES[w.rule], "n_terms": info["n_terms"],
+                   "n_incidences": info["n_incidences"], "launch": launch,
+                   "mean_final_energy": float(np.mean(e_host)), "min_final_energy": int(e_host.min()),
+                   "wall_s": wall},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, beta, min(args.cpu_reads, R), min(args.cpu_sweeps, S))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

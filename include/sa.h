@@ -1,0 +1,163 @@
+/*
+ * sa.h -- C ABI of libsa.so: direct simulated annealing of quadratic and higher-order
+ * unconstrained integer optimisation problems (QUIO / HUIO) on AMD Instinct MI355X (gfx950).
+ *
+ * Method: K. Suzuki, "Simulated Annealing for Quadratic and Higher-Order Unconstrained Integer
+ * Optimization", arXiv:2511.17245.  The library runs the paper's single-variable update sweep
+ * (Sec. 3.1) with the energy difference of Sec. 3.2 and the three transition rules of Sec. 3.3
+ * (Metropolis, heat bath, optimal-transition Metropolis) as HIP kernels, one replica (read) per
+ * 64-lane wavefront.
+ *
+ * Conventions shared by every entry point
+ *  - All functions return an int32_t status (SA_OK or a negative SA_E* code).  On failure no
+ *    output is written and sa_last_error() describes the cause.  No C++ exception crosses the ABI.
+ *  - Input arrays are borrowed for the duration of the call and copied; no pointer is retained,
+ *    except by the plan, batch and server objects, which copy what they need at creation.
+ *  - Output arrays are allocated by the caller.
+ *  - Every argument check (shapes, bounds, the int64 bound, rule support) happens on the host
+ *    before any device work is queued.
+ *  - The GPU work runs on the current HIP device of the calling thread.
+ *  - Entry points are safe to call from several threads; calls that share one plan, batch or
+ *    server object must be serialised by the caller (except the server's submit/poll/cancel).
+ *
+ * Results contract (what "the same result" means across launches, batches and the server):
+ * read r of instance id I with seed K follows the Philox4x32-10 stream with counter
+ * (variable k, sweep s, read r, I) and key (K mod 2^32, K / 2^32); the initial state uses sweep id
+ * 0xFFFFFFFF.  Energies are exact int64; FP64 is used only for acceptance and heat-bath weights.
+ */
+#ifndef SA_H
+#define SA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define SA_OK 0
+#define SA_EINVAL (-1)         /* malformed argument (shape, index, bound, schedule value) */
+#define SA_ERANGE (-2)         /* sum_t |J_t| prod_i max(|l_i|,|u_i|)^e >= 2^62: int64 not exact */
+#define SA_EUNSUPPORTED (-3)   /* e.g. optimal-transition rule with an exponent above 4 */
+#define SA_ENOMEM (-4)         /* host or device allocation failed, or a server budget is exceeded */
+#define SA_EDEVICE (-5)        /* a HIP call failed (no device, launch failure, fault) */
+#define SA_EBUSY (-6)          /* server: result not ready yet */
+#define SA_ECANCELED (-7)      /* server: the request was cancelled */
+
+/* ---- transition rules (Sec. 3.3) ---------------------------------------------------------- */
+#define SA_METROPOLIS 0        /* uniform nonzero change, accept min[1, exp(-dE/T)]   (Sec. 3.3.1) */
+#define SA_HEAT_BATH 1         /* draw the new value with probability exp(-dE/T)/sum  (Sec. 3.3.2) */
+#define SA_OPT_METROPOLIS 2    /* optimal transition with probability r = s/(S-1)     (Sec. 3.3.3) */
+
+/* ---- problem description (Sec. 2) ----------------------------------------------------------
+ * E(z) = sum_t coef[t] * prod_{f = term_ptr[t]}^{term_ptr[t+1]-1} z[factor_var[f]].
+ * A power z_i^m is written as index i repeated m times.  Terms with the same multiset of indices
+ * are merged and zero coefficients dropped (Sec. 2: unordered index tuples).  Every term has
+ * degree >= 1 (no constant terms). */
+typedef struct {
+    int32_t n_vars;             /* N >= 1 */
+    int64_t n_terms;            /* >= 0 */
+    const int64_t *term_ptr;    /* n_terms + 1 offsets, term_ptr[0] = 0, strictly increasing */
+    const int32_t *factor_var;  /* term_ptr[n_terms] indices in [0, N) */
+    const int64_t *coef;        /* n_terms integer coefficients J_t */
+} sa_instance;
+
+/* Integer box l_i <= z_i <= u_i (Sec. 2), with u_i - l_i <= 2^31 - 2.  l_i = u_i fixes z_i. */
+typedef struct {
+    const int32_t *lower;       /* N values */
+    const int32_t *upper;       /* N values */
+} sa_bounds;
+
+/* Inverse temperatures beta_s = 1/T_s, one per sweep.  beta == NULL selects the automatic
+ * schedule: T_init and T_final from Sec. 3.4 (a = 1/2, b = 0.001) with the geometric cooling of
+ * Sec. 3.1.  Every beta must be finite and >= 0. */
+typedef struct {
+    int32_t n_sweeps;           /* S >= 1 */
+    const double *beta;         /* S values (host memory), or NULL */
+} sa_schedule;
+
+/* ---- one-shot annealing ---------------------------------------------------------------------
+ * Runs n_reads independent chains of S sweeps from random initial states and writes the final
+ * states and their energies (the tracked energy, equal to E(final state)).
+ *   out_states   host int32[n_reads * N], row-major (read, variable)
+ *   out_energies host int64[n_reads] */
+int32_t sa_anneal(const sa_instance *inst, const sa_bounds *bounds, const sa_schedule *sched,
+                  int32_t rule, int32_t n_reads, uint64_t seed, int32_t *out_states,
+                  int64_t *out_energies);
+
+/* Options of the extended entry points.  Initialise with sa_opts_default(). */
+typedef struct {
+    uint32_t instance_id;       /* fourth Philox counter word (default 0) */
+    void *hip_stream;           /* hipStream_t to queue the work on (NULL: the null stream) */
+    int32_t device_buffers;     /* 1: out_states / out_energies / init_states are device pointers
+                                   on the current device; the call then returns once the work is
+                                   queued (no host synchronisation).  0: host pointers (default) */
+    int32_t sweep_begin;        /* run sweeps [sweep_begin, sweep_end) of the S-sweep schedule */
+    int32_t sweep_end;          /* <= 0 means S */
+    const int32_t *init_states; /* n_reads * N start states (resume), or NULL for random ones */
+    double otm_r;               /* < 0: r = s/(S-1) as in Sec. 3.3.3 (default); else a fixed r */
+} sa_opts;
+
+void sa_opts_default(sa_opts *opts);
+
+/* sa_anneal with options.  With sweep_begin/sweep_end and init_states a run can be split into
+ * pieces that reproduce the uninterrupted run exactly (the draws are counter-based). */
+int32_t sa_anneal_ex(const sa_instance *inst, const sa_bounds *bounds, const sa_schedule *sched,
+                     int32_t rule, int32_t n_reads, uint64_t seed, int32_t *out_states,
+                     int64_t *out_energies, const sa_opts *opts);
+
+/* ---- plans: a canonical instance packed once in device memory, run many times -------------- */
+typedef struct sa_plan sa_plan;
+
+/* Canonicalises, checks and uploads the instance for `rule` on the current device. */
+int32_t sa_plan_create(const sa_instance *inst, const sa_bounds *bounds, int32_t rule,
+                       sa_plan **out);
+/* Same contract as sa_anneal_ex on the plan's instance and rule. */
+int32_t sa_plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t seed,
+                    int32_t *out_states, int64_t *out_energies, const sa_opts *opts);
+void sa_plan_destroy(sa_plan *plan);
+
+/* Facts about a plan, for reports. */
+typedef struct {
+    int32_t n_vars;
+    int64_t n_terms;            /* canonical terms */
+    int64_t n_incidences;       /* sum_k |terms containing z_k| */
+    int64_t n_factor_slots;     /* other-factor indices stored for the incidences */
+    int32_t max_exponent;
+    int32_t max_width;          /* max_k (u_k - l_k + 1) */
+    int64_t device_bytes;       /* device memory held by the plan */
+    int32_t coef_bits;          /* 32 or 64: width of the stored coefficients */
+    int32_t arith_bits;         /* 32 or 64: integer width of energy differences in the kernel */
+} sa_plan_info;
+int32_t sa_plan_get_info(const sa_plan *plan, sa_plan_info *info);
+
+/* Launch geometry the last sa_plan_run used (for profiling reports). */
+typedef struct {
+    int32_t waves_per_group;    /* replicas per workgroup */
+    int32_t groups;             /* workgroups launched */
+    int32_t lds_bytes;          /* dynamic LDS per workgroup */
+    int32_t state_in_lds;       /* 1: replica states live in LDS, 0: in device memory */
+    int32_t kernel_variant;     /* internal id of the instantiated kernel */
+} sa_launch_info;
+int32_t sa_plan_last_launch(const sa_plan *plan, sa_launch_info *info);
+
+/* ---- utilities -------------------------------------------------------------------------------- */
+/* The automatic schedule of Sec. 3.4 (host arithmetic): beta_out[0..n_sweeps-1]. */
+int32_t sa_auto_schedule(const sa_instance *inst, const sa_bounds *bounds, int32_t n_sweeps,
+                         double *beta_out);
+
+/* Exact energies of n_states states (host int32[n_states * N]) computed on the GPU. */
+int32_t sa_energy(const sa_instance *inst, const sa_bounds *bounds, int32_t n_states,
+                  const int32_t *states, int64_t *out_energies);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *sa_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t sa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SA_H */

@@ -63,6 +63,9 @@ def lib():
         L.sao_anneal.argtypes = [p, C.c_int, p, i32, i32, i32, i32, u64, u32, dbl, C.c_int, C.c_int,
                                  p, p, p]
         L.sao_anneal.restype = C.c_int
+        L.sao_anneal_reads.argtypes = [p, C.c_int, p, i32, i32, i32, i32, p, u64, u32, dbl, C.c_int,
+                                       C.c_int, p, p, p]
+        L.sao_anneal_reads.restype = C.c_int
         L.sao_single_step.argtypes = [p, C.c_int, p, i32, i32, dbl, dbl, i32, u64, u32, p]
         L.sao_single_step.restype = C.c_int
         L.sao_default_threads.argtypes = []
@@ -169,6 +172,22 @@ class Poly:
                               float(otm_r), int(cache_mode), int(n_threads), _ptr(zi), _ptr(z), _ptr(e))
         if rc != OK:
             raise OracleError(rc, "anneal")
+        return z, e
+
+    def anneal_reads(self, rule, beta, read_ids, seed, instance_id=0, otm_r=-1.0, cache_mode=0,
+                     n_threads=0):
+        """Chains of the given read ids only (rows in the order of read_ids)."""
+        beta = np.ascontiguousarray(beta, np.float64)
+        ids = np.ascontiguousarray(read_ids, np.uint32)
+        n = int(ids.shape[0])
+        z = np.zeros((n, self.n), np.int32)
+        e = np.zeros(n, np.int64)
+        S = int(beta.shape[0])
+        rc = lib().sao_anneal_reads(self.h, int(rule), _ptr(beta), S, 0, S, n, _ptr(ids),
+                                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(instance_id) & 0xFFFFFFFF,
+                                    float(otm_r), int(cache_mode), int(n_threads), None, _ptr(z), _ptr(e))
+        if rc != OK:
+            raise OracleError(rc, "anneal_reads")
         return z, e
 
     def single_step(self, rule, z, k, s, beta, r_opt, n_reads, seed, instance_id=0):

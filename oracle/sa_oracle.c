@@ -548,6 +548,7 @@ typedef struct {
     double otm_r;
     int cache_mode;
     const int32_t *z_init;
+    const uint32_t *read_ids; /* NULL: row i is read i */
     int32_t *z_out;
     int64_t *e_out;
     int tid, nthreads;
@@ -598,14 +599,15 @@ static void *anneal_worker(void *arg) {
         free(z);
         return NULL;
     }
-    for (int32_t r = j->tid; r < j->n_reads; r += j->nthreads) {
+    for (int32_t row = j->tid; row < j->n_reads; row += j->nthreads) {
+        const uint32_t r = j->read_ids ? j->read_ids[row] : (uint32_t)row;
         if (j->z_init) {
-            memcpy(z, j->z_init + (int64_t)r * p->n, sizeof(int32_t) * p->n);
+            memcpy(z, j->z_init + (int64_t)row * p->n, sizeof(int32_t) * p->n);
         } else {
             /* random initial state (Sec. 3.1), uniform on each box */
             for (int32_t k = 0; k < p->n; ++k) {
                 uint32_t x[4];
-                draw((uint32_t)k, 0xFFFFFFFFu, (uint32_t)r, j->inst, c.key, x);
+                draw((uint32_t)k, 0xFFFFFFFFu, r, j->inst, c.key, x);
                 int64_t W = (int64_t)p->hi[k] - p->lo[k] + 1;
                 z[k] = (int32_t)(p->lo[k] + (int64_t)(((uint64_t)x[0] * (uint64_t)W) >> 32));
             }
@@ -618,15 +620,15 @@ static void *anneal_worker(void *arg) {
                            : (j->S > 1 ? (double)s / (double)(j->S - 1) : 0.0);
             for (int32_t k = 0; k < p->n; ++k) { /* index order (Sec. 3.1) */
                 int64_t d;
-                if (update_variable(&c, z, k, (uint32_t)s, (uint32_t)r, beta, r_opt, &d)) E += d;
+                if (update_variable(&c, z, k, (uint32_t)s, r, beta, r_opt, &d)) E += d;
             }
         }
         if (E != energy(p, z)) {
             j->status = SAO_EINTERNAL;
             break;
         }
-        memcpy(j->z_out + (int64_t)r * p->n, z, sizeof(int32_t) * p->n);
-        j->e_out[r] = E;
+        memcpy(j->z_out + (int64_t)row * p->n, z, sizeof(int32_t) * p->n);
+        j->e_out[row] = E;
     }
     ctx_free(&c);
     free(z);
@@ -714,6 +716,14 @@ int sao_anneal(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps
                int32_t s_begin, int32_t s_end, int32_t n_reads, uint64_t seed,
                uint32_t instance_id, double otm_r, int cache_mode, int n_threads,
                const int32_t *z_init, int32_t *z_out, int64_t *e_out) {
+    return sao_anneal_reads(p, rule, beta, n_sweeps, s_begin, s_end, n_reads, NULL, seed,
+                            instance_id, otm_r, cache_mode, n_threads, z_init, z_out, e_out);
+}
+
+int sao_anneal_reads(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps,
+                     int32_t s_begin, int32_t s_end, int32_t n_reads, const uint32_t *read_ids,
+                     uint64_t seed, uint32_t instance_id, double otm_r, int cache_mode,
+                     int n_threads, const int32_t *z_init, int32_t *z_out, int64_t *e_out) {
     if (!p || !beta || !z_out || !e_out || n_reads < 1 || n_sweeps < 1) return SAO_EINVAL;
     if (s_begin < 0 || s_end < s_begin || s_end > n_sweeps) return SAO_EINVAL;
     int rc = check_rule(p, rule);
@@ -739,6 +749,7 @@ int sao_anneal(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps
     j.otm_r = otm_r;
     j.cache_mode = cache_mode;
     j.z_init = z_init;
+    j.read_ids = read_ids;
     j.z_out = z_out;
     j.e_out = e_out;
     return run_jobs(&j, n_threads, anneal_worker);

@@ -77,6 +77,13 @@ int sao_anneal(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps
                uint32_t instance_id, double otm_r, int cache_mode, int n_threads,
                const int32_t *z_init, int32_t *z_out, int64_t *e_out);
 
+/* As sao_anneal, but output row i is the chain with read id read_ids[i] (so a sample of the
+ * reads of a large run can be reproduced one by one). */
+int sao_anneal_reads(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps,
+                     int32_t s_begin, int32_t s_end, int32_t n_reads, const uint32_t *read_ids,
+                     uint64_t seed, uint32_t instance_id, double otm_r, int cache_mode,
+                     int n_threads, const int32_t *z_init, int32_t *z_out, int64_t *e_out);
+
 /* For each read r in [0, n_reads): from the state z, perform the single update of variable
  * k at sweep index s with inverse temperature beta and OTM parameter r_opt, and report the
  * new value of z_k (read-keyed draws are independent samples of one transition). */

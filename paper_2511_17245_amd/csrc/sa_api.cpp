@@ -1,0 +1,442 @@
+// sa_api.cpp -- the C ABI of include/sa.h: plans (a canonical instance packed in device memory),
+// one-shot annealing, energies and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sa_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(SA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// One device allocation holding several arrays, each 256-byte aligned.
+struct DevArena {
+    void *base = nullptr;
+    size_t bytes = 0;
+    ~DevArena() {
+        if (base) (void)hipFree(base);
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct sa_plan {
+    int device = 0;
+    int rule = 0;
+    sa::DevProblem dp{};
+    DevArena arena;
+    sa_plan_info info{};
+    sa_launch_info last{};
+    std::vector<int32_t> lo, hi;  // host copy of the box (checks of host start states)
+    double t_init = 0.0, t_final = 0.0;
+    int auto_status = SA_OK;
+    std::string auto_error;
+    // device copy of the last schedule, reused while the schedule is unchanged
+    double *beta_dev = nullptr;
+    int32_t beta_cap = 0;
+    std::vector<double> beta_host;
+    ~sa_plan() {
+        if (beta_dev) (void)hipFree(beta_dev);
+    }
+};
+
+namespace {
+
+int upload_packed(const sa::Packed &pk, sa_plan *plan) {
+    struct Part {
+        const void *src;
+        size_t bytes;
+        size_t off;
+    };
+    std::vector<Part> parts = {
+        {pk.var.data(), pk.var.size() * sizeof(sa::VarRec), 0},
+        {pk.emask.data(), pk.emask.size() * sizeof(uint32_t), 0},
+        {pk.inc.data(), pk.inc.size() * sizeof(sa::IncRec), 0},
+        {pk.inc_coef.data(), pk.inc_coef.size() * sizeof(int64_t), 0},
+        {pk.overflow.data(), pk.overflow.size() * sizeof(int32_t), 0},
+        {pk.t_off.data(), pk.t_off.size() * sizeof(int32_t), 0},
+        {pk.t_var.data(), pk.t_var.size() * sizeof(int32_t), 0},
+        {pk.t_coef.data(), pk.t_coef.size() * sizeof(int64_t), 0},
+    };
+    size_t total = 0;
+    for (auto &p : parts) {
+        p.off = total;
+        total += align256(p.bytes > 0 ? p.bytes : 1);
+    }
+    hipError_t e = hipMalloc(&plan->arena.base, total);
+    if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
+    plan->arena.bytes = total;
+    std::vector<char> staging(total, 0);
+    for (auto &p : parts)
+        if (p.bytes) std::memcpy(staging.data() + p.off, p.src, p.bytes);
+    e = hipMemcpy(plan->arena.base, staging.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan)");
+    char *b = (char *)plan->arena.base;
+    sa::DevProblem &d = plan->dp;
+    d.n = pk.n;
+    d.n_terms = pk.n_terms;
+    d.var = (const sa::VarRec *)(b + parts[0].off);
+    d.emask = (const uint32_t *)(b + parts[1].off);
+    d.inc = (const sa::IncRec *)(b + parts[2].off);
+    d.inc_coef = (const int64_t *)(b + parts[3].off);
+    d.overflow = (const int32_t *)(b + parts[4].off);
+    d.t_off = (const int32_t *)(b + parts[5].off);
+    d.t_var = (const int32_t *)(b + parts[6].off);
+    d.t_coef = (const int64_t *)(b + parts[7].off);
+    return SA_OK;
+}
+
+int check_rule_support(int rule, int32_t max_exp) {
+    if (rule < SA_METROPOLIS || rule > SA_OPT_METROPOLIS) return fail(SA_EINVAL, "unknown rule");
+    if (rule == SA_OPT_METROPOLIS && max_exp > 4)
+        return fail(SA_EUNSUPPORTED,
+                    "optimal-transition Metropolis needs every exponent <= 4 (energy difference of "
+                    "degree <= 4)");
+    if (rule == SA_HEAT_BATH && max_exp > sa::kMaxExpPoly)
+        return fail(SA_EUNSUPPORTED, "heat bath supports exponents up to 16 on the GPU");
+    return SA_OK;
+}
+
+int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, sa_plan **out) {
+    if (!out) return fail(SA_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    std::string err;
+    sa::Canonical canon;
+    int rc = sa::canonicalize(inst, bounds, canon, err);
+    if (rc != SA_OK) return fail(rc, err);
+    double bound = 0.0;
+    rc = sa::check_int64_bound(canon, err, &bound);
+    if (rc != SA_OK) return fail(rc, err);
+    sa::Packed pk;
+    rc = sa::pack(canon, pk, err);
+    if (rc != SA_OK) return fail(rc, err);
+    rc = check_rule_support(rule, pk.max_exp);
+    if (rc != SA_OK) return rc;
+    std::unique_ptr<sa_plan> plan(new sa_plan());
+    hipError_t e = hipGetDevice(&plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    plan->rule = rule;
+    plan->lo = canon.lo;
+    plan->hi = canon.hi;
+    plan->auto_status = sa::auto_temperatures(canon, &plan->t_init, &plan->t_final, plan->auto_error);
+    rc = upload_packed(pk, plan.get());
+    if (rc != SA_OK) return rc;
+    sa_plan_info &in = plan->info;
+    in.n_vars = pk.n;
+    in.n_terms = pk.n_terms;
+    in.n_incidences = (int64_t)pk.inc.size();
+    int64_t slots = (int64_t)pk.overflow.size();
+    for (const auto &r : pk.inc) slots += std::min<int64_t>(r.meta >> 8, 3);
+    in.n_factor_slots = slots;
+    in.max_exponent = pk.max_exp;
+    in.max_width = pk.max_width;
+    in.device_bytes = (int64_t)plan->arena.bytes;
+    in.coef_bits = 64;
+    in.arith_bits = 64;
+    *out = plan.release();
+    return SA_OK;
+}
+
+int resolve_schedule(sa_plan *plan, const sa_schedule *sched, std::vector<double> &beta) {
+    if (!sched || sched->n_sweeps < 1) return fail(SA_EINVAL, "schedule with n_sweeps >= 1 is required");
+    beta.resize((size_t)sched->n_sweeps);
+    if (sched->beta) {
+        for (int32_t s = 0; s < sched->n_sweeps; ++s) {
+            double b = sched->beta[s];
+            if (!(b >= 0.0) || std::isinf(b)) return fail(SA_EINVAL, "beta must be finite and >= 0");
+            beta[s] = b;
+        }
+    } else {
+        if (plan->auto_status != SA_OK) return fail(plan->auto_status, plan->auto_error);
+        sa::geometric_betas(plan->t_init, plan->t_final, sched->n_sweeps, beta.data());
+    }
+    return SA_OK;
+}
+
+int stage_beta(sa_plan *plan, const std::vector<double> &beta, hipStream_t stream) {
+    const int32_t S = (int32_t)beta.size();
+    if (plan->beta_dev && plan->beta_host == beta) return SA_OK;
+    if (S > plan->beta_cap) {
+        if (plan->beta_dev) (void)hipFree(plan->beta_dev);
+        plan->beta_dev = nullptr;
+        plan->beta_cap = 0;
+        hipError_t e = hipMalloc(&plan->beta_dev, sizeof(double) * (size_t)S);
+        if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(beta): ") + hipGetErrorString(e));
+        plan->beta_cap = S;
+    }
+    hipError_t e = hipMemcpyAsync(plan->beta_dev, beta.data(), sizeof(double) * (size_t)S,
+                                  hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(beta)");
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(beta)");
+    plan->beta_host = beta;
+    return SA_OK;
+}
+
+int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t seed,
+             int32_t *out_states, int64_t *out_energies, const sa_opts *opts_in) {
+    if (!plan) return fail(SA_EINVAL, "plan is NULL");
+    sa_opts opts;
+    sa_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if (n_reads < 1) return fail(SA_EINVAL, "n_reads must be >= 1");
+    if (!out_states || !out_energies) return fail(SA_EINVAL, "output buffers are required");
+    std::vector<double> beta;
+    int rc = resolve_schedule(plan, sched, beta);
+    if (rc != SA_OK) return rc;
+    const int32_t S = sched->n_sweeps;
+    const int32_t s0 = opts.sweep_begin;
+    const int32_t s1 = opts.sweep_end <= 0 ? S : opts.sweep_end;
+    if (s0 < 0 || s1 < s0 || s1 > S) return fail(SA_EINVAL, "sweep range outside the schedule");
+    const int32_t n = plan->dp.n;
+    if (opts.init_states && !opts.device_buffers) {
+        // host start states are checked against the box before any device work
+        for (int64_t r = 0; r < n_reads; ++r)
+            for (int32_t k = 0; k < n; ++k) {
+                const int32_t v = opts.init_states[r * n + k];
+                if (v < plan->lo[k] || v > plan->hi[k]) return fail(SA_EINVAL, "init_states outside the bounds");
+            }
+    }
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != plan->device) return fail(SA_EINVAL, "plan was created on another device");
+    hipStream_t stream = (hipStream_t)opts.hip_stream;
+    rc = stage_beta(plan, beta, stream);
+    if (rc != SA_OK) return rc;
+
+    const size_t zbytes = (size_t)n_reads * (size_t)n * sizeof(int32_t);
+    const size_t ebytes = (size_t)n_reads * sizeof(int64_t);
+    int32_t *z_dev = out_states;
+    int64_t *e_dev = out_energies;
+    const int32_t *zi_dev = opts.init_states;
+    void *tmp = nullptr;
+    if (!opts.device_buffers) {
+        size_t need = align256(zbytes) + align256(ebytes) + (opts.init_states ? align256(zbytes) : 0);
+        e = hipMalloc(&tmp, need);
+        if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(run): ") + hipGetErrorString(e));
+        z_dev = (int32_t *)tmp;
+        e_dev = (int64_t *)((char *)tmp + align256(zbytes));
+        if (opts.init_states) {
+            int32_t *zi = (int32_t *)((char *)tmp + align256(zbytes) + align256(ebytes));
+            e = hipMemcpyAsync(zi, opts.init_states, zbytes, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) {
+                (void)hipFree(tmp);
+                return hip_fail(e, "hipMemcpyAsync(init)");
+            }
+            zi_dev = zi;
+        }
+    }
+    sa::AnnealArgs a{};
+    a.P = plan->dp;
+    a.beta = plan->beta_dev;
+    a.n_sweeps = S;
+    a.s_begin = s0;
+    a.s_end = s1;
+    a.n_reads = n_reads;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.instance_id = opts.instance_id;
+    a.otm_r = opts.otm_r;
+    a.z_init = zi_dev;
+    a.z_out = z_dev;
+    a.e_out = e_dev;
+    sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
+                                            plan->info.max_exponent, plan->device);
+    a.waves_per_group = lc.waves_per_group;
+    std::string err;
+    rc = sa::launch_anneal(plan->rule, a, lc, stream, err);
+    if (rc != SA_OK) {
+        if (tmp) (void)hipFree(tmp);
+        return fail(rc, err);
+    }
+    plan->last.waves_per_group = lc.waves_per_group;
+    plan->last.groups = lc.groups;
+    plan->last.lds_bytes = lc.lds_bytes;
+    plan->last.state_in_lds = lc.state_in_lds ? 1 : 0;
+    plan->last.kernel_variant = lc.variant;
+    if (!opts.device_buffers) {
+        e = hipMemcpyAsync(out_states, z_dev, zbytes, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out_energies, e_dev, ebytes, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return hip_fail(e, "annealing run");
+    }
+    return SA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sa_opts_default(sa_opts *opts) {
+    if (!opts) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->otm_r = -1.0;
+}
+
+int32_t sa_plan_create(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, sa_plan **out) {
+    g_last_error.clear();
+    try {
+        return build_plan(inst, bounds, rule, out);
+    } catch (const std::bad_alloc &) {
+        return fail(SA_ENOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(SA_EINVAL, ex.what());
+    }
+}
+
+int32_t sa_plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t seed,
+                    int32_t *out_states, int64_t *out_energies, const sa_opts *opts) {
+    g_last_error.clear();
+    try {
+        return plan_run(plan, sched, n_reads, seed, out_states, out_energies, opts);
+    } catch (const std::bad_alloc &) {
+        return fail(SA_ENOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(SA_EINVAL, ex.what());
+    }
+}
+
+void sa_plan_destroy(sa_plan *plan) { delete plan; }
+
+int32_t sa_plan_get_info(const sa_plan *plan, sa_plan_info *info) {
+    if (!plan || !info) return fail(SA_EINVAL, "plan and info are required");
+    *info = plan->info;
+    return SA_OK;
+}
+
+int32_t sa_plan_last_launch(const sa_plan *plan, sa_launch_info *info) {
+    if (!plan || !info) return fail(SA_EINVAL, "plan and info are required");
+    *info = plan->last;
+    return SA_OK;
+}
+
+int32_t sa_anneal_ex(const sa_instance *inst, const sa_bounds *bounds, const sa_schedule *sched,
+                     int32_t rule, int32_t n_reads, uint64_t seed, int32_t *out_states,
+                     int64_t *out_energies, const sa_opts *opts) {
+    g_last_error.clear();
+    // argument checks that need no canonical form come first
+    if (n_reads < 1) return fail(SA_EINVAL, "n_reads must be >= 1");
+    if (!sched || sched->n_sweeps < 1) return fail(SA_EINVAL, "schedule with n_sweeps >= 1 is required");
+    if (!out_states || !out_energies) return fail(SA_EINVAL, "output buffers are required");
+    if (sched->beta)
+        for (int32_t s = 0; s < sched->n_sweeps; ++s)
+            if (!(sched->beta[s] >= 0.0) || std::isinf(sched->beta[s]))
+                return fail(SA_EINVAL, "beta must be finite and >= 0");
+    if (opts) {
+        const int32_t s1 = opts->sweep_end <= 0 ? sched->n_sweeps : opts->sweep_end;
+        if (opts->sweep_begin < 0 || s1 < opts->sweep_begin || s1 > sched->n_sweeps)
+            return fail(SA_EINVAL, "sweep range outside the schedule");
+    }
+    if (opts && opts->init_states && !opts->device_buffers && inst && bounds && bounds->lower &&
+        bounds->upper && inst->n_vars > 0) {
+        for (int64_t r = 0; r < n_reads; ++r)
+            for (int32_t k = 0; k < inst->n_vars; ++k) {
+                int32_t v = opts->init_states[r * inst->n_vars + k];
+                if (v < bounds->lower[k] || v > bounds->upper[k])
+                    return fail(SA_EINVAL, "init_states outside the bounds");
+            }
+    }
+    sa_plan *plan = nullptr;
+    int32_t rc = sa_plan_create(inst, bounds, rule, &plan);
+    if (rc != SA_OK) return rc;
+    rc = sa_plan_run(plan, sched, n_reads, seed, out_states, out_energies, opts);
+    if (rc == SA_OK && opts && opts->device_buffers) {
+        // the plan's device memory must outlive the queued kernel
+        hipError_t e = hipStreamSynchronize((hipStream_t)opts->hip_stream);
+        if (e != hipSuccess) rc = hip_fail(e, "annealing run");
+    }
+    sa_plan_destroy(plan);
+    return rc;
+}
+
+int32_t sa_anneal(const sa_instance *inst, const sa_bounds *bounds, const sa_schedule *sched,
+                  int32_t rule, int32_t n_reads, uint64_t seed, int32_t *out_states,
+                  int64_t *out_energies) {
+    return sa_anneal_ex(inst, bounds, sched, rule, n_reads, seed, out_states, out_energies, nullptr);
+}
+
+int32_t sa_auto_schedule(const sa_instance *inst, const sa_bounds *bounds, int32_t n_sweeps,
+                         double *beta_out) {
+    g_last_error.clear();
+    if (n_sweeps < 1 || !beta_out) return fail(SA_EINVAL, "n_sweeps >= 1 and beta_out are required");
+    try {
+        std::string err;
+        sa::Canonical canon;
+        int rc = sa::canonicalize(inst, bounds, canon, err);
+        if (rc != SA_OK) return fail(rc, err);
+        double ti = 0, tf = 0;
+        rc = sa::auto_temperatures(canon, &ti, &tf, err);
+        if (rc != SA_OK) return fail(rc, err);
+        sa::geometric_betas(ti, tf, n_sweeps, beta_out);
+        return SA_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(SA_ENOMEM, "host allocation failed");
+    }
+}
+
+int32_t sa_energy(const sa_instance *inst, const sa_bounds *bounds, int32_t n_states,
+                  const int32_t *states, int64_t *out_energies) {
+    g_last_error.clear();
+    if (n_states < 1 || !states || !out_energies) return fail(SA_EINVAL, "states and outputs are required");
+    sa_plan *plan = nullptr;
+    int32_t rc = sa_plan_create(inst, bounds, SA_METROPOLIS, &plan);
+    if (rc != SA_OK) return rc;
+    const int32_t n = plan->dp.n;
+    for (int64_t i = 0; i < (int64_t)n_states * n; ++i) {
+        int32_t k = (int32_t)(i % n);
+        if (states[i] < bounds->lower[k] || states[i] > bounds->upper[k]) {
+            sa_plan_destroy(plan);
+            return fail(SA_EINVAL, "state outside the bounds");
+        }
+    }
+    const size_t zb = (size_t)n_states * n * sizeof(int32_t), eb = (size_t)n_states * sizeof(int64_t);
+    void *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, align256(zb) + eb);
+    if (e != hipSuccess) {
+        sa_plan_destroy(plan);
+        return fail(SA_ENOMEM, "hipMalloc(energy)");
+    }
+    int32_t *zd = (int32_t *)tmp;
+    int64_t *ed = (int64_t *)((char *)tmp + align256(zb));
+    e = hipMemcpy(zd, states, zb, hipMemcpyHostToDevice);
+    std::string err;
+    if (e == hipSuccess) {
+        rc = sa::launch_energy(plan->dp, zd, n_states, ed, nullptr, err);
+        if (rc == SA_OK) {
+            e = hipMemcpy(out_energies, ed, eb, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) rc = hip_fail(e, "energy copy");
+        } else {
+            fail(rc, err);
+        }
+    } else {
+        rc = hip_fail(e, "hipMemcpy(states)");
+    }
+    (void)hipFree(tmp);
+    sa_plan_destroy(plan);
+    return rc;
+}
+
+const char *sa_last_error(void) { return g_last_error.c_str(); }
+
+int32_t sa_version(void) { return 100; }
+
+}  // extern "C"

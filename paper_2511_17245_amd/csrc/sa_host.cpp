@@ -1,0 +1,302 @@
+// sa_host.cpp -- host-side preparation of a problem for the annealing kernels:
+// validation, canonicalisation (Sec. 2), the int64 exactness bound, the automatic temperature
+// range (Sec. 3.4) and the variable-major packing the kernels read.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "sa_internal.h"
+
+namespace sa {
+
+namespace {
+
+bool fits_i64(__int128 v) { return v >= -(__int128)INT64_MAX && v <= (__int128)INT64_MAX; }
+
+}  // namespace
+
+int canonicalize(const sa_instance *inst, const sa_bounds *bounds, Canonical &out, std::string &err) {
+    if (!inst || !bounds) {
+        err = "instance and bounds are required";
+        return SA_EINVAL;
+    }
+    const int32_t n = inst->n_vars;
+    const int64_t nt = inst->n_terms;
+    if (n < 1) {
+        err = "n_vars must be >= 1";
+        return SA_EINVAL;
+    }
+    if (nt < 0) {
+        err = "n_terms must be >= 0";
+        return SA_EINVAL;
+    }
+    if (!bounds->lower || !bounds->upper) {
+        err = "bounds.lower and bounds.upper are required";
+        return SA_EINVAL;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t l = bounds->lower[i], u = bounds->upper[i];
+        if (l > u) {
+            err = "lower bound above upper bound for variable " + std::to_string(i);
+            return SA_EINVAL;
+        }
+        if (u - l > 2147483646LL) {
+            err = "range u - l exceeds 2^31 - 2 for variable " + std::to_string(i);
+            return SA_EINVAL;
+        }
+    }
+    if (nt > 0 && (!inst->term_ptr || !inst->factor_var || !inst->coef)) {
+        err = "term_ptr, factor_var and coef are required when n_terms > 0";
+        return SA_EINVAL;
+    }
+    const int64_t *tp = inst->term_ptr;
+    if (nt > 0 && tp[0] != 0) {
+        err = "term_ptr[0] must be 0";
+        return SA_EINVAL;
+    }
+    for (int64_t t = 0; t < nt; ++t) {
+        if (tp[t + 1] <= tp[t]) {
+            err = "term " + std::to_string(t) + " has degree < 1 (constant terms are not allowed)";
+            return SA_EINVAL;
+        }
+    }
+    const int64_t nf = nt > 0 ? tp[nt] : 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t v = inst->factor_var[f];
+        if (v < 0 || v >= n) {
+            err = "factor index out of range at position " + std::to_string(f);
+            return SA_EINVAL;
+        }
+    }
+
+    // Sort the factors of every term, then order terms by (degree, factors) and merge equal ones.
+    // Terms of degree <= 2 use a packed 64-bit key (the common case for QUIO); longer terms are
+    // compared factor by factor.
+    std::vector<int32_t> fac(inst->factor_var, inst->factor_var + nf);
+    struct ShortKey {
+        uint64_t key;
+        int64_t coef;
+    };
+    std::vector<ShortKey> shorts;
+    std::vector<int64_t> longs;
+    shorts.reserve((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t a = tp[t], b = tp[t + 1];
+        std::sort(fac.begin() + a, fac.begin() + b);
+        if (b - a == 1) {
+            shorts.push_back({((uint64_t)1 << 62) | (uint64_t)fac[a], inst->coef[t]});
+        } else if (b - a == 2) {
+            shorts.push_back({((uint64_t)2 << 62) | ((uint64_t)fac[a] << 31) | (uint64_t)fac[a + 1],
+                              inst->coef[t]});
+        } else {
+            longs.push_back(t);
+        }
+    }
+    std::sort(shorts.begin(), shorts.end(),
+              [](const ShortKey &x, const ShortKey &y) { return x.key < y.key; });
+    auto long_less = [&](int64_t x, int64_t y) {
+        int64_t lx = tp[x + 1] - tp[x], ly = tp[y + 1] - tp[y];
+        if (lx != ly) return lx < ly;
+        return std::lexicographical_compare(fac.begin() + tp[x], fac.begin() + tp[x + 1],
+                                            fac.begin() + tp[y], fac.begin() + tp[y + 1]);
+    };
+    std::sort(longs.begin(), longs.end(), long_less);
+
+    out = Canonical();
+    out.n = n;
+    out.lo.assign(bounds->lower, bounds->lower + n);
+    out.hi.assign(bounds->upper, bounds->upper + n);
+    out.t_off.push_back(0);
+    for (size_t a = 0; a < shorts.size();) {
+        size_t b = a;
+        __int128 sum = 0;
+        while (b < shorts.size() && shorts[b].key == shorts[a].key) sum += shorts[b++].coef;
+        if (!fits_i64(sum)) {
+            err = "merged coefficient overflows int64";
+            return SA_ERANGE;
+        }
+        if (sum != 0) {
+            uint64_t key = shorts[a].key;
+            if ((key >> 62) == 1) {
+                out.t_var.push_back((int32_t)(key & 0x7FFFFFFFu));
+            } else {
+                out.t_var.push_back((int32_t)((key >> 31) & 0x7FFFFFFFu));
+                out.t_var.push_back((int32_t)(key & 0x7FFFFFFFu));
+            }
+            out.t_coef.push_back((int64_t)sum);
+            out.t_off.push_back((int64_t)out.t_var.size());
+        }
+        a = b;
+    }
+    for (size_t a = 0; a < longs.size();) {
+        size_t b = a;
+        __int128 sum = 0;
+        while (b < longs.size() && !long_less(longs[a], longs[b]) && !long_less(longs[b], longs[a]))
+            sum += inst->coef[longs[b++]];
+        if (!fits_i64(sum)) {
+            err = "merged coefficient overflows int64";
+            return SA_ERANGE;
+        }
+        if (sum != 0) {
+            int64_t t = longs[a];
+            out.t_var.insert(out.t_var.end(), fac.begin() + tp[t], fac.begin() + tp[t + 1]);
+            out.t_coef.push_back((int64_t)sum);
+            out.t_off.push_back((int64_t)out.t_var.size());
+        }
+        a = b;
+    }
+    return SA_OK;
+}
+
+int check_int64_bound(const Canonical &c, std::string &err, double *bound_out) {
+    const __int128 limit = (__int128)1 << 62;
+    __int128 total = 0;
+    for (int64_t t = 0; t < c.n_terms(); ++t) {
+        __int128 term = c.t_coef[t] < 0 ? -(__int128)c.t_coef[t] : (__int128)c.t_coef[t];
+        for (int64_t f = c.t_off[t]; f < c.t_off[t + 1] && term < limit; ++f) {
+            int32_t i = c.t_var[f];
+            int64_t zm = std::max(std::llabs((long long)c.lo[i]), std::llabs((long long)c.hi[i]));
+            term *= zm;
+        }
+        total += term;
+        if (total >= limit) {
+            err = "sum_t |J_t| prod max(|l|,|u|)^e reaches 2^62: energies would not be exact in int64";
+            return SA_ERANGE;
+        }
+    }
+    if (bound_out) *bound_out = (double)total;
+    return SA_OK;
+}
+
+int auto_temperatures(const Canonical &c, double *t_init, double *t_final, std::string &err) {
+    // dE_max ~ max_k sum over terms holding z_k^m of |J| * prod_{other factors} zmax^e * (u_k - l_k)^m
+    // dE_min ~ min |J| over the (merged, nonzero) coefficients.
+    const int32_t n = c.n;
+    std::vector<double> per_var(n, 0.0);
+    double min_abs = INFINITY;
+    for (int64_t t = 0; t < c.n_terms(); ++t) {
+        const double absj = std::fabs((double)c.t_coef[t]);
+        min_abs = std::min(min_abs, absj);
+        const int64_t a = c.t_off[t], b = c.t_off[t + 1];
+        // walk the distinct variables of the term (factors are sorted, powers are runs)
+        for (int64_t f = a; f < b;) {
+            int64_t g = f;
+            while (g < b && c.t_var[g] == c.t_var[f]) ++g;
+            const int32_t k = c.t_var[f];
+            const double m = (double)(g - f);
+            double prod = absj;
+            for (int64_t h = a; h < b;) {
+                int64_t q = h;
+                while (q < b && c.t_var[q] == c.t_var[h]) ++q;
+                if (c.t_var[h] != k) {
+                    const int32_t i = c.t_var[h];
+                    const double zmax = std::max(std::fabs((double)c.lo[i]), std::fabs((double)c.hi[i]));
+                    prod *= std::pow(zmax, (double)(q - h));
+                }
+                h = q;
+            }
+            per_var[k] += prod * std::pow((double)c.hi[k] - (double)c.lo[k], m);
+            f = g;
+        }
+    }
+    double de_max = 0.0;
+    for (double v : per_var) de_max = std::max(de_max, v);
+    if (!(de_max > 0.0) || !std::isfinite(min_abs)) {
+        err = "automatic schedule needs a term on a variable with a nonempty range";
+        return SA_EINVAL;
+    }
+    *t_init = -de_max / std::log(0.5);
+    *t_final = -min_abs / std::log(0.001);
+    return SA_OK;
+}
+
+void geometric_betas(double t_init, double t_final, int32_t n_sweeps, double *beta_out) {
+    for (int32_t s = 0; s < n_sweeps; ++s) {
+        double T = n_sweeps > 1
+                       ? t_init * std::pow(t_final / t_init, (double)s / (double)(n_sweeps - 1))
+                       : t_init;
+        beta_out[s] = 1.0 / T;
+    }
+}
+
+int pack(const Canonical &c, Packed &p, std::string &err) {
+    const int32_t n = c.n;
+    const int64_t nt = c.n_terms();
+    if (nt > INT32_MAX - 1 || (int64_t)c.t_var.size() > INT32_MAX - 1) {
+        err = "problem too large for 32-bit term offsets";
+        return SA_EINVAL;
+    }
+    p = Packed();
+    p.n = n;
+    p.n_terms = (int32_t)nt;
+    p.var.resize(n);
+    p.emask.assign(n, 0u);
+    // count incidences (distinct variables per term)
+    std::vector<int64_t> deg(n, 0);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int64_t f = c.t_off[t]; f < c.t_off[t + 1]; ++f)
+            if (f == c.t_off[t] || c.t_var[f] != c.t_var[f - 1]) deg[c.t_var[f]]++;
+    int64_t total = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        if (total > INT32_MAX || deg[k] > INT32_MAX) {
+            err = "too many term incidences for 32-bit offsets";
+            return SA_EINVAL;
+        }
+        int64_t w = (int64_t)c.hi[k] - c.lo[k] + 1;
+        p.var[k] = VarRec{c.lo[k], (int32_t)w, (int32_t)total, (int32_t)deg[k]};
+        p.max_width = std::max<int32_t>(p.max_width, (int32_t)w);
+        total += deg[k];
+    }
+    if (total > INT32_MAX) {
+        err = "too many term incidences for 32-bit offsets";
+        return SA_EINVAL;
+    }
+    p.inc.resize((size_t)total);
+    p.inc_coef.resize((size_t)total);
+    std::vector<int64_t> fill(n);
+    for (int32_t k = 0; k < n; ++k) fill[k] = p.var[k].row;
+    std::vector<int32_t> others;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = c.t_off[t], b = c.t_off[t + 1];
+        for (int64_t f = a; f < b;) {
+            int64_t g = f;
+            while (g < b && c.t_var[g] == c.t_var[f]) ++g;
+            const int32_t k = c.t_var[f];
+            const int64_t e = g - f;
+            if (e > kMaxExpStored) {
+                err = "exponent above 255 is not supported";
+                return SA_EUNSUPPORTED;
+            }
+            others.clear();
+            for (int64_t h = a; h < b; ++h)
+                if (c.t_var[h] != k) others.push_back(c.t_var[h]);
+            IncRec r{};
+            r.meta = (uint32_t)e | ((uint32_t)others.size() << 8);
+            if (others.size() <= 3) {
+                for (size_t q = 0; q < 3; ++q) r.o[q] = q < others.size() ? others[q] : 0;
+            } else {
+                if (others.size() >= (1u << 24) || p.overflow.size() > (size_t)INT32_MAX - others.size()) {
+                    err = "term too long";
+                    return SA_EINVAL;
+                }
+                r.o[0] = (int32_t)p.overflow.size();
+                r.o[1] = r.o[2] = 0;
+                p.overflow.insert(p.overflow.end(), others.begin(), others.end());
+            }
+            const int64_t slot = fill[k]++;
+            p.inc[slot] = r;
+            p.inc_coef[slot] = c.t_coef[t];
+            p.emask[k] |= 1u << std::min<int64_t>(e, 31);
+            p.max_exp = std::max<int32_t>(p.max_exp, (int32_t)e);
+            f = g;
+        }
+    }
+    p.t_off.resize((size_t)nt + 1);
+    for (int64_t t = 0; t <= nt; ++t) p.t_off[t] = (int32_t)c.t_off[t];
+    p.t_var = c.t_var;
+    p.t_coef = c.t_coef;
+    return SA_OK;
+}
+
+}  // namespace sa

@@ -1,0 +1,121 @@
+// sa_internal.h -- contract between the host packer (sa_host.cpp), the C ABI (sa_api.cpp) and the
+// HIP kernels (sa_kernels.hip).  Not installed; include/sa.h is the public interface.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sa.h"
+
+namespace sa {
+
+// Largest exponent of one variable inside one term that the heat-bath and optimal-transition
+// kernels accept (their per-variable polynomial dE(v) = sum_m a_m (v^m - z^m) keeps m <= this).
+constexpr int kMaxExpPoly = 16;
+// Largest exponent stored at all (8-bit field of the incidence record).
+constexpr int kMaxExpStored = 255;
+// Heat-bath weights kept in registers when ceil(W/64) <= this; wider ranges recompute them.
+constexpr int kHeatBathRegChunk = 32;
+
+// Canonical polynomial: merged terms, nonzero coefficients, factors sorted (a power is a
+// repeated index).
+struct Canonical {
+    int32_t n = 0;
+    std::vector<int64_t> t_off;   // n_terms + 1 offsets into t_var
+    std::vector<int32_t> t_var;   // factor indices, ascending inside a term
+    std::vector<int64_t> t_coef;  // nonzero coefficients
+    std::vector<int32_t> lo, hi;  // integer box
+    int64_t n_terms() const { return (int64_t)t_coef.size(); }
+};
+
+// Validates and canonicalises; returns an SA_* status and fills err on failure.
+int canonicalize(const sa_instance *inst, const sa_bounds *bounds, Canonical &out, std::string &err);
+// SA_ERANGE when sum_t |J_t| prod zmax^e >= 2^62.  Also reports the largest |dE| bound.
+int check_int64_bound(const Canonical &c, std::string &err, double *bound_out);
+// Sec. 3.4 temperature range (T_init, T_final); SA_EINVAL if the problem has no energy scale.
+int auto_temperatures(const Canonical &c, double *t_init, double *t_final, std::string &err);
+// Geometric cooling of Sec. 3.1 between the two temperatures, as inverse temperatures.
+void geometric_betas(double t_init, double t_final, int32_t n_sweeps, double *beta_out);
+
+// Variable record: {lower bound, width W = u - l + 1, first incidence, number of incidences}.
+struct VarRec {
+    int32_t lo, width, row, deg;
+};
+// Incidence record of variable k in term t: meta = e_k(t) | (n_other << 8); the other factors
+// (indices repeated by exponent) inline in o[0..2] when n_other <= 3, else o[0] is the offset of
+// n_other indices in the overflow array.
+struct IncRec {
+    uint32_t meta;
+    int32_t o[3];
+};
+
+// Host-side packed image of a plan (uploaded as one device allocation).
+struct Packed {
+    int32_t n = 0;
+    int32_t n_terms = 0;
+    std::vector<VarRec> var;
+    std::vector<uint32_t> emask;    // bit m set: some term holds z_k^m (m = 1..31; 31 = ">= 31")
+    std::vector<IncRec> inc;
+    std::vector<int64_t> inc_coef;
+    std::vector<int32_t> overflow;  // other-factor indices of incidences with > 3 others
+    std::vector<int32_t> t_off;     // term-major copy for energies
+    std::vector<int32_t> t_var;
+    std::vector<int64_t> t_coef;
+    int32_t max_exp = 0;
+    int32_t max_width = 1;
+};
+int pack(const Canonical &c, Packed &out, std::string &err);
+
+// Device view of a packed plan.
+struct DevProblem {
+    int32_t n;
+    int32_t n_terms;
+    const VarRec *var;
+    const uint32_t *emask;
+    const IncRec *inc;
+    const int64_t *inc_coef;
+    const int32_t *overflow;
+    const int32_t *t_off;
+    const int32_t *t_var;
+    const int64_t *t_coef;
+};
+
+// Kernel arguments of one annealing launch.
+struct AnnealArgs {
+    DevProblem P;
+    const double *beta;      // S inverse temperatures (device)
+    int32_t n_sweeps;        // S
+    int32_t s_begin, s_end;  // sweeps to run
+    int32_t n_reads;
+    int32_t waves_per_group;
+    uint32_t key0, key1;     // Philox key (seed)
+    uint32_t instance_id;
+    double otm_r;            // < 0: r = s/(S-1)
+    const int32_t *z_init;   // device, n_reads * n, or nullptr
+    int32_t *z_out;          // device, n_reads * n (also the working state when not in LDS)
+    int64_t *e_out;          // device, n_reads
+};
+
+struct LaunchChoice {
+    int waves_per_group = 1;
+    int groups = 1;
+    int lds_bytes = 0;
+    bool state_in_lds = true;
+    bool reg_weights = false;  // heat bath: weights kept in registers
+    int maxe_class = 1;        // kernel's largest exponent (1, 2, 4 or 16)
+    int variant = 0;
+};
+
+// Launches one annealing pass (defined in sa_kernels.hip).  Returns an SA_* status.
+int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
+                  std::string &err);
+// Picks the launch geometry for n_reads replicas of an n-variable problem on `device`.
+LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
+                           int device);
+// Energies of n_states device-resident states (one wavefront per state).
+int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, int64_t *out,
+                  void *stream, std::string &err);
+
+}  // namespace sa

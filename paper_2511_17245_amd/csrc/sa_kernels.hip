@@ -1,0 +1,503 @@
+// sa_kernels.hip -- gfx950 kernels of the single-variable update sweep (Sec. 3.1) for QUIO/HUIO.
+//
+// Mapping: one replica (read) per 64-lane wavefront; the waves of a workgroup are independent
+// replicas of the same instance (no workgroup barriers).  A replica's state z lives in LDS when it
+// fits, else in its row of the output buffer.  For the visited variable k the lanes split the
+// terms containing z_k (each lane forms one term's product of the other factors) and, for the heat
+// bath and the optimal transition, the candidate values v in [l_k, u_k].  Energies and energy
+// differences are exact integers (two's-complement wrap-around arithmetic, exact whenever the true
+// value fits int64, which the host checks); FP64 is used only for exp() in the acceptance test
+// and the heat-bath weights.
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter (k, s, read, instance) and key
+// = seed; the lanes compute the blocks of 64 consecutive variables at once and the update of
+// variable k reads its block from lane k mod 64.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "sa_internal.h"
+
+namespace sa {
+namespace {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------------------------------------
+// Philox4x32-10 block function.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                              uint32_t &c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        const uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
+        const uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Wavefront collectives.  Integer reductions are order-independent (wrap-around sums, min), so any
+// exchange pattern gives the same value.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t uni32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+__device__ __forceinline__ uint32_t lane_read32(uint32_t x, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) x += __shfl_xor(x, off);
+    return uni64(x);
+}
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t x) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t y = __shfl_xor(x, off);
+        x = y < x ? y : x;
+    }
+    return (int64_t)uni64((uint64_t)x);
+}
+
+__device__ __forceinline__ int32_t wave_min_i32(int32_t x) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y = __shfl_xor(x, off);
+        x = y < x ? y : x;
+    }
+    return (int32_t)uni32((uint32_t)x);
+}
+
+// Orders a lane's LDS/global state write before later reads by other lanes of the same wave.
+template <bool kStateInLds>
+__device__ __forceinline__ void state_write_fence() {
+    if (kStateInLds) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
+// x^e with wrap-around
+__device__ __forceinline__ uint64_t upow(uint64_t x, int e) {
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+// J_t times the product of the term's other factors, for incidence `idx` of the row being visited.
+// Sets e to the exponent of the visited variable in the term.
+__device__ __forceinline__ uint64_t incidence_product(const DevProblem &P, const int32_t *z,
+                                                      int32_t idx, int &e) {
+    const IncRec r = P.inc[idx];
+    e = (int)(r.meta & 0xFFu);
+    const int no = (int)(r.meta >> 8);
+    uint64_t prod = (uint64_t)P.inc_coef[idx];
+    if (no <= 3) {
+        if (no > 0) prod *= (uint64_t)(int64_t)z[r.o[0]];
+        if (no > 1) prod *= (uint64_t)(int64_t)z[r.o[1]];
+        if (no > 2) prod *= (uint64_t)(int64_t)z[r.o[2]];
+    } else {
+        const int32_t *o = P.overflow + r.o[0];
+        for (int f = 0; f < no; ++f) prod *= (uint64_t)(int64_t)z[o[f]];
+    }
+    return prod;
+}
+
+// Uniform coefficients a_k^(m) (Sec. 3.2, T_k = sum_m a_k^(m) z_k^m) for m = 1..kMaxE; every
+// index is static so the coefficients stay in registers.
+template <int kMaxE>
+struct Coeffs {
+    uint64_t a[kMaxE + 1];
+};
+
+template <int kMaxE>
+__device__ __forceinline__ void row_coeffs(const DevProblem &P, const int32_t *z, int32_t row,
+                                           int32_t deg, uint32_t emask, int lane, Coeffs<kMaxE> &C) {
+    uint64_t part[kMaxE + 1];
+#pragma unroll
+    for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
+    for (int32_t c0 = 0; c0 < deg; c0 += kWave) {
+        if (lane < deg - c0) {
+            int e;
+            const uint64_t prod = incidence_product(P, z, row + c0 + lane, e);
+#pragma unroll
+            for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : 0ull;
+        }
+    }
+    C.a[0] = 0;
+#pragma unroll
+    for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? wave_sum_u64(part[m]) : 0ull;
+}
+
+// dE(v) = sum_m a^(m) (v^m - z_k^m)  (Sec. 3.2)
+template <int kMaxE>
+__device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE> &C, int64_t zk, int64_t v) {
+    uint64_t d = C.a[1] * (uint64_t)(v - zk), vp = (uint64_t)v, zp = (uint64_t)zk;
+#pragma unroll
+    for (int m = 2; m <= kMaxE; ++m) {
+        vp *= (uint64_t)v;
+        zp *= (uint64_t)zk;
+        d += C.a[m] * (vp - zp);
+    }
+    return (int64_t)d;
+}
+
+// dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
+__device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const int32_t *z, int32_t row,
+                                                int32_t deg, int64_t zk, int64_t v, int lane) {
+    uint64_t acc = 0;
+    for (int32_t c0 = 0; c0 < deg; c0 += kWave) {
+        if (lane < deg - c0) {
+            int e;
+            const uint64_t prod = incidence_product(P, z, row + c0 + lane, e);
+            acc += prod * (upow((uint64_t)v, e) - upow((uint64_t)zk, e));
+        }
+    }
+    return (int64_t)wave_sum_u64(acc);
+}
+
+// Metropolis acceptance min[1, exp(-dE/T)] (Sec. 3.3.1), T = 1/beta; U in [0,1).
+__device__ __forceinline__ bool metropolis_accept(int64_t d, double beta, double U) {
+    if (d <= 0) return true;
+    return U < exp(-(beta * (double)d));
+}
+
+// Heat-bath choice (Sec. 3.3.2) among all W values, with the fixed summation order: value j of the
+// range belongs to lane j / c (c = ceil(W/64)); lane sums are left to right; the lanes' sums are
+// combined by a Kogge-Stone inclusive scan (strides 1..32); the first value whose cumulative weight
+// exceeds U * total is drawn (the last value if rounding leaves none).
+template <int kRegChunk, int kMaxE>
+__device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_t lo, int64_t W,
+                                                  int64_t zk, double beta, double U, int lane) {
+    const int64_t c = (W + kWave - 1) / kWave;
+    const int64_t j0 = (int64_t)lane * c;
+    // minimum energy difference over all values (weights are taken relative to it)
+    int64_t dmin = INT64_MAX;
+    for (int64_t i = 0; i < c; ++i) {
+        const int64_t j = j0 + i;
+        if (j < W) {
+            const int64_t d = poly_delta(C, zk, lo + j);
+            dmin = d < dmin ? d : dmin;
+        }
+    }
+    dmin = wave_min_i64(dmin);
+
+    double w[kRegChunk > 0 ? kRegChunk : 1];
+    double lane_sum = 0.0;
+    if (kRegChunk > 0) {
+#pragma unroll
+        for (int i = 0; i < (kRegChunk > 0 ? kRegChunk : 1); ++i) {
+            if (i < c) {
+                const int64_t j = j0 + i;
+                double wi = 0.0;
+                if (j < W) wi = exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
+                w[i] = wi;
+                lane_sum += wi;
+            }
+        }
+    } else {
+        for (int64_t i = 0; i < c; ++i) {
+            const int64_t j = j0 + i;
+            if (j < W) lane_sum += exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
+        }
+    }
+    double incl = lane_sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double y = __shfl_up(incl, off);
+        if (lane >= off) incl = incl + y;
+    }
+    const double total = __shfl(incl, kWave - 1);
+    double before = __shfl_up(incl, 1);
+    if (lane == 0) before = 0.0;
+    const double thr = U * total;
+
+    int64_t hit = -1;
+    double run = 0.0;
+    if (kRegChunk > 0) {
+#pragma unroll
+        for (int i = 0; i < (kRegChunk > 0 ? kRegChunk : 1); ++i) {
+            if (i < c) {
+                if (j0 + i < W) {
+                    run += w[i];
+                    if (hit < 0 && before + run > thr) hit = i;
+                }
+            }
+        }
+    } else {
+        for (int64_t i = 0; i < c; ++i) {
+            const int64_t j = j0 + i;
+            if (j < W) {
+                run += exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
+                if (before + run > thr) {
+                    hit = i;
+                    break;
+                }
+            }
+        }
+    }
+    const uint64_t mask = __ballot(hit >= 0);
+    if (mask == 0) return lo + W - 1;
+    const int src = __ffsll((unsigned long long)mask) - 1;
+    const int64_t hit_at = (int64_t)(((uint64_t)lane_read32((uint32_t)((uint64_t)hit >> 32), src) << 32) |
+                                     lane_read32((uint32_t)hit, src));
+    return lo + (int64_t)src * c + hit_at;
+}
+
+// Optimal transition (Sec. 3.3.3): the nonzero change of smallest dE, ties to the smallest value.
+template <int kMaxE>
+__device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE> &C, int64_t lo, int64_t W,
+                                                  int64_t zk, int lane, int64_t &dbest) {
+    int64_t best = INT64_MAX;
+    int32_t bv = INT32_MAX;
+    for (int64_t i = lane; i < W; i += kWave) {
+        const int64_t v = lo + i;
+        if (v == zk) continue;
+        const int64_t d = poly_delta(C, zk, v);
+        if (d < best) {
+            best = d;
+            bv = (int32_t)v;
+        }
+    }
+    dbest = wave_min_i64(best);
+    return wave_min_i32(best == dbest ? bv : INT32_MAX);
+}
+
+// ------------------------------------------------------------------------------------------------
+// The annealing kernel.
+// ------------------------------------------------------------------------------------------------
+template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE>
+__global__ void __launch_bounds__(256) anneal_kernel(AnnealArgs A) {
+    extern __shared__ int32_t lds_state[];
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    const int read = (int)blockIdx.x * A.waves_per_group + wave;
+    if (read >= A.n_reads) return;  // whole wavefront leaves; no workgroup barriers follow
+    const DevProblem &P = A.P;
+    const int32_t n = P.n;
+    int32_t *z = kStateInLds ? lds_state + (size_t)wave * n : A.z_out + (size_t)read * n;
+    const uint32_t rd = (uint32_t)read;
+
+    // initial state: given (resume) or uniform on each box (Sec. 3.1)
+    if (A.z_init) {
+        const int32_t *zi = A.z_init + (size_t)read * n;
+        if (zi != z)
+            for (int32_t k = lane; k < n; k += kWave) z[k] = zi[k];
+    } else {
+        for (int32_t k = lane; k < n; k += kWave) {
+            uint32_t x0 = (uint32_t)k, x1 = 0xFFFFFFFFu, x2 = rd, x3 = A.instance_id;
+            philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+            const VarRec vr = P.var[k];
+            z[k] = vr.lo + (int32_t)(((uint64_t)x0 * (uint64_t)(uint32_t)vr.width) >> 32);
+        }
+    }
+    state_write_fence<kStateInLds>();
+
+    // E(z) = sum_t J_t prod z (term-major, lanes split the terms)
+    uint64_t eacc = 0;
+    for (int32_t t = lane; t < P.n_terms; t += kWave) {
+        uint64_t prod = (uint64_t)P.t_coef[t];
+        for (int32_t f = P.t_off[t]; f < P.t_off[t + 1]; ++f) prod *= (uint64_t)(int64_t)z[P.t_var[f]];
+        eacc += prod;
+    }
+    int64_t E = (int64_t)wave_sum_u64(eacc);
+
+    for (int32_t s = A.s_begin; s < A.s_end; ++s) {
+        const double beta = A.beta[s];
+        const double r_opt =
+            A.otm_r >= 0.0 ? A.otm_r : (A.n_sweeps > 1 ? (double)s / (double)(A.n_sweeps - 1) : 0.0);
+        for (int32_t kb = 0; kb < n; kb += kWave) {
+            // draws of the next 64 variables, one block per lane
+            uint32_t x0 = (uint32_t)(kb + lane), x1 = (uint32_t)s, x2 = rd, x3 = A.instance_id;
+            philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+            const int32_t kend = n - kb < kWave ? n - kb : kWave;
+            for (int32_t j = 0; j < kend; ++j) {
+                const int32_t k = kb + j;
+                const VarRec vr = P.var[k];
+                if (vr.width == 1) continue;  // fixed variable
+                const uint32_t r0 = lane_read32(x0, j), r1 = lane_read32(x1, j);
+                const uint32_t r2 = lane_read32(x2, j), r3 = lane_read32(x3, j);
+                const double U = (double)((((uint64_t)r2 << 32) | r3) >> 11) * 0x1p-53;
+                const int64_t lo = vr.lo, W = vr.width;
+                const int64_t zk = (int64_t)(int32_t)uni32((uint32_t)z[k]);
+                int64_t v, d;
+                bool accept;
+                if (kRule == SA_METROPOLIS) {
+                    v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
+                    if (v >= zk) v += 1;
+                    d = direct_delta(P, z, vr.row, vr.deg, zk, v, lane);
+                    accept = metropolis_accept(d, beta, U);
+                } else if (kRule == SA_HEAT_BATH) {
+                    Coeffs<kMaxE> C;
+                    row_coeffs<kMaxE>(P, z, vr.row, vr.deg, P.emask[k], lane, C);
+                    v = heat_bath_pick<kRegChunk, kMaxE>(C, lo, W, zk, beta, U, lane);
+                    d = poly_delta(C, zk, v);
+                    accept = true;
+                } else {
+                    if ((double)r0 * 0x1p-32 < r_opt) {
+                        Coeffs<kMaxE> C;
+                        row_coeffs<kMaxE>(P, z, vr.row, vr.deg, P.emask[k], lane, C);
+                        v = argmin_nonzero<kMaxE>(C, lo, W, zk, lane, d);
+                    } else {
+                        v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
+                        if (v >= zk) v += 1;
+                        d = direct_delta(P, z, vr.row, vr.deg, zk, v, lane);
+                    }
+                    accept = metropolis_accept(d, beta, U);
+                }
+                if (accept && v != zk) {
+                    z[k] = (int32_t)v;  // every lane stores the same value
+                    E += d;
+                    state_write_fence<kStateInLds>();
+                }
+            }
+        }
+    }
+
+    if (kStateInLds) {
+        int32_t *zo = A.z_out + (size_t)read * n;
+        for (int32_t k = lane; k < n; k += kWave) zo[k] = z[k];
+    }
+    if (lane == 0) A.e_out[read] = E;
+}
+
+// Energies of stored states, one wavefront per state.
+__global__ void __launch_bounds__(256) energy_kernel(DevProblem P, const int32_t *states,
+                                                     int32_t n_states, int64_t *out) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int idx = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    if (idx >= n_states) return;
+    const int32_t *z = states + (size_t)idx * P.n;
+    uint64_t acc = 0;
+    for (int32_t t = lane; t < P.n_terms; t += kWave) {
+        uint64_t prod = (uint64_t)P.t_coef[t];
+        for (int32_t f = P.t_off[t]; f < P.t_off[t + 1]; ++f) prod *= (uint64_t)(int64_t)z[P.t_var[f]];
+        acc += prod;
+    }
+    const uint64_t E = wave_sum_u64(acc);
+    if (lane == 0) out[idx] = (int64_t)E;
+}
+
+using KernelFn = void (*)(AnnealArgs);
+
+template <int kRule, int kMaxE>
+KernelFn pick_lds_reg(bool in_lds, bool reg) {
+    if (reg) return in_lds ? anneal_kernel<kRule, true, kHeatBathRegChunk, kMaxE>
+                           : anneal_kernel<kRule, false, kHeatBathRegChunk, kMaxE>;
+    return in_lds ? anneal_kernel<kRule, true, 0, kMaxE> : anneal_kernel<kRule, false, 0, kMaxE>;
+}
+
+// Kernel variants: rule x state placement x (heat bath) weights in registers x exponent class.
+KernelFn pick_kernel(int rule, bool in_lds, bool reg, int maxe_class) {
+    if (rule == SA_METROPOLIS)
+        return in_lds ? anneal_kernel<SA_METROPOLIS, true, 0, 1> : anneal_kernel<SA_METROPOLIS, false, 0, 1>;
+    if (rule == SA_HEAT_BATH) {
+        switch (maxe_class) {
+            case 1: return pick_lds_reg<SA_HEAT_BATH, 1>(in_lds, reg);
+            case 2: return pick_lds_reg<SA_HEAT_BATH, 2>(in_lds, reg);
+            case 4: return pick_lds_reg<SA_HEAT_BATH, 4>(in_lds, reg);
+            default: return pick_lds_reg<SA_HEAT_BATH, kMaxExpPoly>(in_lds, reg);
+        }
+    }
+    if (rule == SA_OPT_METROPOLIS) {
+        switch (maxe_class) {
+            case 1: return pick_lds_reg<SA_OPT_METROPOLIS, 1>(in_lds, false);
+            case 2: return pick_lds_reg<SA_OPT_METROPOLIS, 2>(in_lds, false);
+            default: return pick_lds_reg<SA_OPT_METROPOLIS, 4>(in_lds, false);
+        }
+    }
+    return nullptr;
+}
+
+int maxe_class_of(int32_t max_exp) {
+    if (max_exp <= 1) return 1;
+    if (max_exp <= 2) return 2;
+    if (max_exp <= 4) return 4;
+    return kMaxExpPoly;
+}
+
+}  // namespace
+
+LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
+                           int device) {
+    LaunchChoice lc;
+    int cus = 256, max_lds = 65536;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    // spread replicas over all compute units first, then stack them (up to 4 waves per group)
+    int wpg = n_reads / (cus > 0 ? cus : 1);
+    wpg = wpg < 1 ? 1 : (wpg > 4 ? 4 : wpg);
+    const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
+    while (wpg > 1 && per_wave * wpg > max_lds) --wpg;
+    lc.state_in_lds = per_wave * wpg <= max_lds;
+    lc.waves_per_group = wpg;
+    lc.groups = (n_reads + wpg - 1) / wpg;
+    lc.lds_bytes = lc.state_in_lds ? (int)(per_wave * wpg) : 0;
+    const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
+    const int reg = (rule == SA_HEAT_BATH && chunk <= kHeatBathRegChunk) ? 1 : 0;
+    lc.maxe_class = maxe_class_of(max_exp);
+    lc.reg_weights = reg != 0;
+    lc.variant = rule * 1000 + lc.maxe_class * 10 + (lc.state_in_lds ? 2 : 0) + reg;
+    return lc;
+}
+
+int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
+                  std::string &err) {
+    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_weights, lc.maxe_class);
+    if (!fn) {
+        err = "unknown rule";
+        return SA_EINVAL;
+    }
+    if (lc.lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           lc.lds_bytes);
+        if (e != hipSuccess) {
+            err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
+            return SA_EDEVICE;
+        }
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)lc.groups), dim3((unsigned)(lc.waves_per_group * kWave)),
+                       (size_t)lc.lds_bytes, (hipStream_t)stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return SA_EDEVICE;
+    }
+    return SA_OK;
+}
+
+int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, int64_t *out,
+                  void *stream, std::string &err) {
+    const int per_group = 4;
+    const int groups = (n_states + per_group - 1) / per_group;
+    hipLaunchKernelGGL(energy_kernel, dim3((unsigned)groups), dim3(per_group * kWave), 0,
+                       (hipStream_t)stream, P, states, n_states, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return SA_EDEVICE;
+    }
+    return SA_OK;
+}
+
+}  // namespace sa

@@ -1,0 +1,240 @@
+"""Thin ctypes binding of libsa.so (include/sa.h).
+
+Argument marshalling only: every step of the annealing runs in the library's HIP kernels.  PyTorch
+is used for device memory (output tensors) and streams.  Importing this module does not load the
+library; the first call does, and raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsa.so")
+
+OK, EINVAL, ERANGE, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+METROPOLIS, HEAT_BATH, OPT_METROPOLIS = 0, 1, 2
+RULE_NAMES = {METROPOLIS: "metropolis", HEAT_BATH: "heat_bath", OPT_METROPOLIS: "otm"}
+
+
+class SAError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libsa status {code}: {message}")
+        self.code = code
+
+
+class sa_instance(C.Structure):
+    _fields_ = [("n_vars", C.c_int32), ("n_terms", C.c_int64), ("term_ptr", C.c_void_p),
+                ("factor_var", C.c_void_p), ("coef", C.c_void_p)]
+
+
+class sa_bounds(C.Structure):
+    _fields_ = [("lower", C.c_void_p), ("upper", C.c_void_p)]
+
+
+class sa_schedule(C.Structure):
+    _fields_ = [("n_sweeps", C.c_int32), ("beta", C.c_void_p)]
+
+
+class sa_opts(C.Structure):
+    _fields_ = [("instance_id", C.c_uint32), ("hip_stream", C.c_void_p), ("device_buffers", C.c_int32),
+                ("sweep_begin", C.c_int32), ("sweep_end", C.c_int32), ("init_states", C.c_void_p),
+                ("otm_r", C.c_double)]
+
+
+class sa_plan_info(C.Structure):
+    _fields_ = [("n_vars", C.c_int32), ("n_terms", C.c_int64), ("n_incidences", C.c_int64),
+                ("n_factor_slots", C.c_int64), ("max_exponent", C.c_int32), ("max_width", C.c_int32),
+                ("device_bytes", C.c_int64), ("coef_bits", C.c_int32), ("arith_bits", C.c_int32)]
+
+
+class sa_launch_info(C.Structure):
+    _fields_ = [("waves_per_group", C.c_int32), ("groups", C.c_int32), ("lds_bytes", C.c_int32),
+                ("state_in_lds", C.c_int32), ("kernel_variant", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsa.so; raises if it was not built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_uint32
+        P = C.POINTER
+        L.sa_anneal.argtypes = [P(sa_instance), P(sa_bounds), P(sa_schedule), i32, i32, u64, vp, vp]
+        L.sa_anneal_ex.argtypes = L.sa_anneal.argtypes + [P(sa_opts)]
+        L.sa_opts_default.argtypes = [P(sa_opts)]
+        L.sa_opts_default.restype = None
+        L.sa_plan_create.argtypes = [P(sa_instance), P(sa_bounds), i32, P(vp)]
+        L.sa_plan_run.argtypes = [vp, P(sa_schedule), i32, u64, vp, vp, P(sa_opts)]
+        L.sa_plan_destroy.argtypes = [vp]
+        L.sa_plan_destroy.restype = None
+        L.sa_plan_get_info.argtypes = [vp, P(sa_plan_info)]
+        L.sa_plan_last_launch.argtypes = [vp, P(sa_launch_info)]
+        L.sa_auto_schedule.argtypes = [P(sa_instance), P(sa_bounds), i32, vp]
+        L.sa_energy.argtypes = [P(sa_instance), P(sa_bounds), i32, vp, vp]
+        L.sa_last_error.argtypes = []
+        L.sa_last_error.restype = C.c_char_p
+        L.sa_version.argtypes = []
+        for name in ("sa_anneal", "sa_anneal_ex", "sa_plan_create", "sa_plan_run", "sa_plan_get_info",
+                     "sa_plan_last_launch", "sa_auto_schedule", "sa_energy", "sa_version"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().sa_last_error().decode(errors="replace")
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise SAError(rc, f"{what}: {last_error()}")
+
+
+def _p(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())  # torch tensor
+
+
+class _Marshalled:
+    """Keeps the numpy arrays of a problem alive while the C structs point at them."""
+
+    def __init__(self, problem):
+        self.tp = np.ascontiguousarray(problem.term_ptr, np.int64)
+        self.fv = np.ascontiguousarray(problem.factor_var, np.int32)
+        self.cf = np.ascontiguousarray(problem.coef, np.int64)
+        self.lo = np.ascontiguousarray(problem.lower, np.int32)
+        self.up = np.ascontiguousarray(problem.upper, np.int32)
+        self.n = int(problem.n_vars)
+        self.inst = sa_instance(self.n, int(self.cf.shape[0]), _p(self.tp), _p(self.fv), _p(self.cf))
+        self.bounds = sa_bounds(_p(self.lo), _p(self.up))
+
+
+def _schedule(n_sweeps: int, beta):
+    if beta is None:
+        return sa_schedule(int(n_sweeps), None), None
+    b = np.ascontiguousarray(beta, np.float64)
+    if int(n_sweeps) != b.shape[0]:
+        raise ValueError("len(beta) must equal n_sweeps")
+    return sa_schedule(int(b.shape[0]), _p(b)), b
+
+
+def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, sweep_end=0,
+              init_states=None, otm_r=-1.0) -> sa_opts:
+    o = sa_opts()
+    lib().sa_opts_default(C.byref(o))
+    o.instance_id = int(instance_id) & 0xFFFFFFFF
+    o.hip_stream = stream
+    o.device_buffers = 1 if device_buffers else 0
+    o.sweep_begin = int(sweep_begin)
+    o.sweep_end = int(sweep_end)
+    o.init_states = _p(init_states)
+    o.otm_r = float(otm_r)
+    return o
+
+
+def anneal(problem, rule: int, n_sweeps: int, n_reads: int, seed: int, beta=None, instance_id=0,
+           sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0):
+    """One-shot annealing with host buffers; returns (states int32[n_reads, N], energies int64)."""
+    m = _Marshalled(problem)
+    sched, keep = _schedule(n_sweeps, beta)
+    z = np.zeros((n_reads, m.n), np.int32)
+    e = np.zeros(n_reads, np.int64)
+    zi = None if init_states is None else np.ascontiguousarray(init_states, np.int32)
+    opts = make_opts(instance_id, None, False, sweep_begin, sweep_end, zi, otm_r)
+    rc = lib().sa_anneal_ex(C.byref(m.inst), C.byref(m.bounds), C.byref(sched), int(rule), int(n_reads),
+                            int(seed) & 0xFFFFFFFFFFFFFFFF, _p(z), _p(e), C.byref(opts))
+    _check(rc, "sa_anneal_ex")
+    return z, e
+
+
+def auto_schedule(problem, n_sweeps: int) -> np.ndarray:
+    m = _Marshalled(problem)
+    beta = np.zeros(n_sweeps, np.float64)
+    _check(lib().sa_auto_schedule(C.byref(m.inst), C.byref(m.bounds), int(n_sweeps), _p(beta)),
+           "sa_auto_schedule")
+    return beta
+
+
+def energy(problem, states) -> np.ndarray:
+    m = _Marshalled(problem)
+    z = np.ascontiguousarray(states, np.int32).reshape(-1, m.n)
+    out = np.zeros(z.shape[0], np.int64)
+    _check(lib().sa_energy(C.byref(m.inst), C.byref(m.bounds), int(z.shape[0]), _p(z), _p(out)),
+           "sa_energy")
+    return out
+
+
+class Plan:
+    """A canonical instance packed in device memory for one rule (sa_plan)."""
+
+    def __init__(self, problem, rule: int):
+        m = _Marshalled(problem)
+        h = C.c_void_p()
+        _check(lib().sa_plan_create(C.byref(m.inst), C.byref(m.bounds), int(rule), C.byref(h)),
+               "sa_plan_create")
+        self.h = h
+        self.n = m.n
+        self.rule = int(rule)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.sa_plan_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def info(self) -> dict:
+        i = sa_plan_info()
+        _check(lib().sa_plan_get_info(self.h, C.byref(i)), "sa_plan_get_info")
+        return {f: getattr(i, f) for f, _ in sa_plan_info._fields_}
+
+    def last_launch(self) -> dict:
+        i = sa_launch_info()
+        _check(lib().sa_plan_last_launch(self.h, C.byref(i)), "sa_plan_last_launch")
+        return {f: getattr(i, f) for f, _ in sa_launch_info._fields_}
+
+    def run_device(self, n_sweeps, n_reads, seed, z_out, e_out, beta=None, stream=None,
+                   instance_id=0, sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0):
+        """Queue a run writing into device tensors z_out (int32 [n_reads, N]) and e_out (int64)."""
+        assert z_out.is_cuda and e_out.is_cuda
+        assert z_out.dtype.itemsize == 4 and e_out.dtype.itemsize == 8
+        assert z_out.numel() == n_reads * self.n and e_out.numel() == n_reads
+        assert z_out.is_contiguous() and e_out.is_contiguous()
+        if init_states is not None:
+            assert init_states.is_cuda and init_states.numel() == n_reads * self.n
+        sched, keep = _schedule(n_sweeps, beta)
+        opts = make_opts(instance_id, stream, True, sweep_begin, sweep_end, init_states, otm_r)
+        rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               _p(z_out), _p(e_out), C.byref(opts))
+        _check(rc, "sa_plan_run")
+
+    def run(self, n_sweeps, n_reads, seed, beta=None, instance_id=0, sweep_begin=0, sweep_end=0,
+            init_states=None, otm_r=-1.0):
+        """Run with host buffers; returns (states, energies)."""
+        sched, keep = _schedule(n_sweeps, beta)
+        z = np.zeros((n_reads, self.n), np.int32)
+        e = np.zeros(n_reads, np.int64)
+        zi = None if init_states is None else np.ascontiguousarray(init_states, np.int32)
+        opts = make_opts(instance_id, None, False, sweep_begin, sweep_end, zi, otm_r)
+        rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               _p(z), _p(e), C.byref(opts))
+        _check(rc, "sa_plan_run")
+        return z, e
+
+
+EXPORTED = ["sa_anneal", "sa_anneal_ex", "sa_opts_default", "sa_plan_create", "sa_plan_run",
+            "sa_plan_destroy", "sa_plan_get_info", "sa_plan_last_launch", "sa_auto_schedule",
+            "sa_energy", "sa_last_error", "sa_version"]

@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+The bar is bit-exactness of every compared read's final state and int64 energy: both sides follow
+the same Philox stream, exact integer energy differences and the same FP64 formulas, so any
+difference is a defect (or an exp() ulp difference at an acceptance threshold, which the failure
+message would show as a single diverging read).  Small cases compare every read; the measured
+configurations are run at full size on the GPU, in the launch configuration the benchmark uses,
+and a seeded sample of their reads is recomputed by the oracle one by one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_17245_amd import inputs as I
+from paper_2511_17245_amd import sa
+
+pytestmark = pytest.mark.gpu
+
+RULES = [sa.METROPOLIS, sa.HEAT_BATH, sa.OPT_METROPOLIS]
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=None, s0=0, s1=0):
+    import torch
+    plan = sa.Plan(prob, rule)
+    z = torch.empty((n_reads, prob.n_vars), dtype=torch.int32, device="cuda")
+    e = torch.empty(n_reads, dtype=torch.int64, device="cuda")
+    zi = None if init is None else torch.as_tensor(np.ascontiguousarray(init, np.int32), device="cuda")
+    plan.run_device(len(beta), n_reads, seed, z, e, beta=beta,
+                    stream=torch.cuda.current_stream().cuda_stream, instance_id=instance_id,
+                    otm_r=otm_r, init_states=zi, sweep_begin=s0, sweep_end=s1)
+    torch.cuda.synchronize()
+    launch = plan.last_launch()
+    plan.close()
+    return z.cpu().numpy(), e.cpu().numpy(), launch
+
+
+def assert_same(zg, eg, zo, eo, label):
+    bad = [i for i in range(len(eo)) if eg[i] != eo[i] or not np.array_equal(zg[i], zo[i])]
+    if bad:
+        i = bad[0]
+        diff = np.nonzero(zg[i] != zo[i])[0][:8]
+        pytest.fail(f"{label}: {len(bad)}/{len(eo)} reads differ; first read {i}: E gpu {eg[i]} "
+                    f"oracle {eo[i]}; first differing variables {diff.tolist()}")
+
+
+def small_cases():
+    r = rng(42)
+    yield "huio_powers_n150", I.random_huio(150, 900, [1, 2, 3, 4], -7, 9, 5, r), 60, 48, RULES
+    yield "cfg1_dense_n100_s200", I.cfg1_dense_quio().problem, 200, 16, RULES
+    yield "cfg2_like_n1000", I.cfg2_sparse_quio(n=1000).problem, 40, 64, RULES
+    yield "cfg3_like_n300", I.cfg3_huio(n=300, m=3000).problem, 100, 128, RULES
+    yield "ml_p30_u1_long_terms", I.multilinear(100, 30, 1), 50, 16, RULES
+    yield "fc_p8_u2_high_power", I.fully_connected(30, 8, 2), 60, 16, [sa.METROPOLIS, sa.HEAT_BATH]
+    yield "binary_qubo_n200", I.dense_quio(200, 0, 1, 5, 5, r), 40, 32, RULES
+    yield "wide_w2001_regs", I.erdos_renyi_quio(64, 6.0, -1000, 1000, 10, 10, r), 12, 8, RULES
+    yield "wide_w5001_recompute", I.dense_quio(40, -2500, 2500, 3, 3, r), 6, 4, [sa.HEAT_BATH]
+    fixed = I.random_huio(90, 300, [1, 2, 3], -4, 4, 4, r)
+    fixed.lower[::7] = 2
+    fixed.upper[::7] = 2
+    yield "fixed_and_unused_vars", I.Problem(fixed.n_vars + 5, fixed.term_ptr, fixed.factor_var,
+                                             fixed.coef, np.r_[fixed.lower, [-3] * 5],
+                                             np.r_[fixed.upper, [3] * 5]), 30, 16, RULES
+    yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 50, 64, RULES
+    yield "many_reads_n50", I.random_huio(50, 200, [2, 3], -3, 3, 3, r), 20, 2048, RULES
+
+
+@pytest.mark.parametrize("case", list(small_cases()), ids=lambda c: c[0])
+def test_small_instances_all_reads(case):
+    name, prob, sweeps, reads, rules = case
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(sweeps)
+    for rule in rules:
+        say(name, sa.RULE_NAMES[rule], f"N={prob.n_vars} S={sweeps} R={reads}")
+        zg, eg, launch = gpu_run(prob, rule, beta, reads, seed=1234 + rule, instance_id=3)
+        zo, eo = P.anneal(rule, beta, reads, seed=1234 + rule, instance_id=3)
+        assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]} {launch}")
+
+
+def test_cfg1_full_all_reads():
+    w = I.cfg1_dense_quio()
+    P = oracle.Poly(w.problem)
+    say("cfg1 full", w.name)
+    zg, eg, _ = gpu_run(w.problem, w.rule, w.beta, w.n_reads, w.seed)
+    zo, eo = P.anneal(w.rule, w.beta, w.n_reads, w.seed)
+    assert_same(zg, eg, zo, eo, "cfg1")
+
+
+def test_state_outside_lds():
+    # N * 4 bytes above the 160 KiB LDS of a CU: states live in device memory
+    prob = I.erdos_renyi_quio(45_000, 3.0, -5, 5, 10, 10, rng(9))
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(3)
+    for rule in RULES:
+        say("state_outside_lds", sa.RULE_NAMES[rule])
+        zg, eg, launch = gpu_run(prob, rule, beta, 4, seed=5)
+        assert launch["state_in_lds"] == 0
+        zo, eo = P.anneal(rule, beta, 4, seed=5)
+        assert_same(zg, eg, zo, eo, f"outside-LDS/{sa.RULE_NAMES[rule]}")
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_resume_from_device_states(rule):
+    prob = I.cfg3_huio(n=200, m=2000).problem
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(30)
+    say("resume", sa.RULE_NAMES[rule])
+    z_full, e_full, _ = gpu_run(prob, rule, beta, 32, seed=8)
+    z_a, _, _ = gpu_run(prob, rule, beta, 32, seed=8, s1=11)
+    z_b, e_b, _ = gpu_run(prob, rule, beta, 32, seed=8, init=z_a, s0=11)
+    assert_same(z_b, e_b, z_full, e_full, "resume vs uninterrupted")
+    zo, eo = P.anneal(rule, beta, 32, seed=8)
+    assert_same(z_full, e_full, zo, eo, "uninterrupted vs oracle")
+
+
+def test_otm_fixed_r():
+    prob = I.cfg3_huio(n=250, m=2500).problem
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(25)
+    say("otm r override")
+    z0, e0, _ = gpu_run(prob, sa.OPT_METROPOLIS, beta, 32, seed=2, otm_r=0.0)
+    zm, em, _ = gpu_run(prob, sa.METROPOLIS, beta, 32, seed=2)
+    assert_same(z0, e0, zm, em, "OTM r=0 vs Metropolis")
+    for r in (0.5, 1.0):
+        zg, eg, _ = gpu_run(prob, sa.OPT_METROPOLIS, beta, 32, seed=2, otm_r=r)
+        zo, eo = P.anneal(sa.OPT_METROPOLIS, beta, 32, seed=2, otm_r=r)
+        assert_same(zg, eg, zo, eo, f"OTM r={r}")
+
+
+def test_energy_kernel_and_one_shot_api():
+    prob = I.cfg3_huio(n=400, m=4000).problem
+    P = oracle.Poly(prob)
+    r = rng(3)
+    states = r.integers(prob.lower, prob.upper + 1, size=(37, prob.n_vars)).astype(np.int32)
+    say("sa_energy")
+    e = sa.energy(prob, states)
+    assert [int(x) for x in e] == [P.energy(s) for s in states]
+    beta, _, _ = P.schedule(20)
+    say("sa_anneal host buffers")
+    z, en = sa.anneal(prob, sa.HEAT_BATH, 20, 24, seed=6, beta=beta, instance_id=9)
+    zo, eo = P.anneal(sa.HEAT_BATH, beta, 24, seed=6, instance_id=9)
+    assert_same(z, en, zo, eo, "one-shot")
+    za, ea = sa.anneal(prob, sa.OPT_METROPOLIS, 20, 8, seed=6)   # automatic schedule
+    zo, eo = P.anneal(sa.OPT_METROPOLIS, P.schedule(20)[0], 8, seed=6)
+    assert_same(za, ea, zo, eo, "one-shot auto schedule")
+
+
+def test_repeat_runs_are_identical():
+    prob = I.cfg2_sparse_quio(n=2000).problem
+    beta = sa.auto_schedule(prob, 30)
+    say("determinism")
+    a = gpu_run(prob, sa.HEAT_BATH, beta, 64, seed=11)
+    b = gpu_run(prob, sa.HEAT_BATH, beta, 64, seed=11)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------------------------------------
+# Full-size measured configurations: every read checked for E == E(z); a seeded sample of reads
+# recomputed by the oracle.
+# ------------------------------------------------------------------------------------------------
+
+def full_size(w, n_sample, label):
+    P = oracle.Poly(w.problem)
+    beta = w.beta if w.beta is not None else P.schedule(w.n_sweeps)[0]
+    say(label, "GPU full run", w.name)
+    zg, eg, launch = gpu_run(w.problem, w.rule, beta, w.n_reads, w.seed, w.instance_id)
+    say(label, "launch", launch)
+    for i in range(0, w.n_reads, max(1, w.n_reads // 64)):
+        assert int(eg[i]) == P.energy(zg[i]), f"{label}: tracked energy of read {i} is not E(z)"
+    ids = np.sort(rng(77).choice(w.n_reads, size=n_sample, replace=False)).astype(np.uint32)
+    say(label, "oracle sample", ids.tolist())
+    zo, eo = P.anneal_reads(w.rule, beta, ids, w.seed, w.instance_id)
+    assert_same(zg[ids], eg[ids], zo, eo, f"{label} sampled reads")
+
+
+def test_cfg2_full_size_sampled():
+    full_size(I.cfg2_sparse_quio(), 8, "cfg2")
+
+
+@pytest.mark.parametrize("rule", ["otm", "metropolis"])
+def test_cfg3_full_size_sampled(rule):
+    full_size(I.cfg3_huio(rule=rule), 24, f"cfg3-{rule}")

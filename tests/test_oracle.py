@@ -489,3 +489,13 @@ def test_initial_state_is_uniform_on_each_box():
         assert len(counts) == hi - lo + 1
         assert brute.chi2_pvalue(counts, np.full(hi - lo + 1, 1.0 / (hi - lo + 1))) > 1e-4
     assert all(int(en) == brute.energy_raw(p, row) for row, en in zip(z[:50], e[:50]))
+
+
+def test_sampled_reads_reproduce_full_run():
+    p = I.cfg3_huio(n=120, m=1000).problem
+    P = oracle.Poly(p)
+    beta, _, _ = P.schedule(15)
+    z, e = P.anneal(oracle.OPT_METROPOLIS, beta, 20, seed=4)
+    ids = [19, 0, 7, 7, 12]
+    zs, es = P.anneal_reads(oracle.OPT_METROPOLIS, beta, ids, seed=4)
+    assert np.array_equal(zs, z[ids]) and np.array_equal(es, e[ids])
