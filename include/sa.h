@@ -97,6 +97,9 @@ typedef struct {
     int32_t sweep_end;          /* <= 0 means S */
     const int32_t *init_states; /* n_reads * N start states (resume), or NULL for random ones */
     double otm_r;               /* < 0: r = s/(S-1) as in Sec. 3.3.3 (default); else a fixed r */
+    int32_t waves_per_replica;  /* 0: automatic.  G > 1 lets G wavefronts of one replica update G
+                                   consecutive variables that share no term at the same time (the
+                                   result is identical to the sequential sweep); 1, 2 or 4 */
 } sa_opts;
 
 void sa_opts_default(sa_opts *opts);
@@ -139,6 +142,8 @@ typedef struct {
     int32_t lds_bytes;          /* dynamic LDS per workgroup */
     int32_t state_in_lds;       /* 1: replica states live in LDS, 0: in device memory */
     int32_t kernel_variant;     /* internal id of the instantiated kernel */
+    int32_t waves_per_replica;  /* G: wavefronts cooperating on one replica */
+    int32_t n_windows;          /* windows per sweep in the schedule (N for G = 1 without fixed vars) */
 } sa_launch_info;
 int32_t sa_plan_last_launch(const sa_plan *plan, sa_launch_info *info);
 

@@ -52,8 +52,18 @@ struct sa_plan {
     double *beta_dev = nullptr;
     int32_t beta_cap = 0;
     std::vector<double> beta_host;
+    // host packing (kept to build sweep schedules) and the device schedules built so far, by G
+    sa::Packed packed;
+    struct Sched {
+        sa::SchedRec *dev = nullptr;
+        int32_t n_win = 0;
+        int32_t n_active = 0;  // variables that are not fixed
+    };
+    Sched sched[5];
     ~sa_plan() {
         if (beta_dev) (void)hipFree(beta_dev);
+        for (auto &sc : sched)
+            if (sc.dev) (void)hipFree(sc.dev);
     }
 };
 
@@ -150,6 +160,7 @@ int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, s
     in.device_bytes = (int64_t)plan->arena.bytes;
     in.coef_bits = 64;
     in.arith_bits = 64;
+    plan->packed = std::move(pk);
     *out = plan.release();
     return SA_OK;
 }
@@ -188,6 +199,49 @@ int stage_beta(sa_plan *plan, const std::vector<double> &beta, hipStream_t strea
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(beta)");
     plan->beta_host = beta;
     return SA_OK;
+}
+
+// The sweep schedule for G waves per replica (built on first use and kept on the device).
+int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out) {
+    sa_plan::Sched &sc = plan->sched[G];
+    if (!sc.dev) {
+        std::vector<sa::SchedRec> host;
+        const int32_t n_win = sa::build_schedule(plan->packed, G, host);
+        int32_t active = 0;
+        for (const auto &vr : plan->packed.var) active += vr.width > 1 ? 1 : 0;
+        const size_t bytes = std::max<size_t>(host.size(), 1) * sizeof(sa::SchedRec);
+        hipError_t e = hipMalloc(&sc.dev, bytes);
+        if (e != hipSuccess) {
+            sc.dev = nullptr;
+            return fail(SA_ENOMEM, std::string("hipMalloc(schedule): ") + hipGetErrorString(e));
+        }
+        if (!host.empty()) {
+            e = hipMemcpy(sc.dev, host.data(), host.size() * sizeof(sa::SchedRec), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy(schedule)");
+        }
+        sc.n_win = n_win;
+        sc.n_active = active;
+    }
+    *out = &sc;
+    return SA_OK;
+}
+
+// Waves per replica: enough replicas' waves to cover the 1024 SIMDs, as long as the windows are
+// wide enough to pay for the barriers and the shared state fits in LDS.
+int auto_waves_per_replica(sa_plan *plan, int32_t n_reads, int device) {
+    int cus = 256, max_lds = 65536;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    int G = 1;
+    while (G < 4 && (int64_t)n_reads * G < (int64_t)cus * 4) G *= 2;
+    while (G > 1) {
+        sa_plan::Sched *sc = nullptr;
+        if (sa::shared_state_bytes(plan->dp.n, G) <= max_lds && get_schedule(plan, G, &sc) == SA_OK &&
+            sc->n_win > 0 && (double)sc->n_active / (double)sc->n_win >= 1.25 * G / 2.0)
+            break;
+        G /= 2;
+    }
+    return G;
 }
 
 int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t seed,
@@ -258,8 +312,23 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     a.z_init = zi_dev;
     a.z_out = z_dev;
     a.e_out = e_dev;
+    int G = opts.waves_per_replica;
+    if (G != 0 && G != 1 && G != 2 && G != 4) {
+        if (tmp) (void)hipFree(tmp);
+        return fail(SA_EINVAL, "waves_per_replica must be 0, 1, 2 or 4");
+    }
+    if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
     sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
-                                            plan->info.max_exponent, plan->device);
+                                            plan->info.max_exponent, plan->device, G);
+    sa_plan::Sched *sc = nullptr;
+    rc = get_schedule(plan, lc.win_waves, &sc);
+    if (rc != SA_OK) {
+        if (tmp) (void)hipFree(tmp);
+        return rc;
+    }
+    a.sched = sc->dev;
+    a.n_win = sc->n_win;
+    a.win_waves = lc.win_waves;
     a.waves_per_group = lc.waves_per_group;
     std::string err;
     rc = sa::launch_anneal(plan->rule, a, lc, stream, err);
@@ -272,6 +341,8 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     plan->last.lds_bytes = lc.lds_bytes;
     plan->last.state_in_lds = lc.state_in_lds ? 1 : 0;
     plan->last.kernel_variant = lc.variant;
+    plan->last.waves_per_replica = lc.win_waves;
+    plan->last.n_windows = sc->n_win;
     if (!opts.device_buffers) {
         e = hipMemcpyAsync(out_states, z_dev, zbytes, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(out_energies, e_dev, ebytes, hipMemcpyDeviceToHost, stream);

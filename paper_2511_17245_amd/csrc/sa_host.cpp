@@ -299,4 +299,45 @@ int pack(const Canonical &c, Packed &p, std::string &err) {
     return SA_OK;
 }
 
+int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out) {
+    const int32_t n = p.n;
+    std::vector<int32_t> stamp(n, -1);
+    std::vector<int32_t> starts;   // window w holds members[starts[w] .. starts[w+1])
+    std::vector<int32_t> members;
+    int32_t win = -1, count = G;
+    for (int32_t k = 0; k < n; ++k) {
+        const VarRec &vr = p.var[k];
+        if (vr.width == 1) continue;
+        if (count == G || stamp[k] == win) {
+            ++win;
+            count = 0;
+            starts.push_back((int32_t)members.size());
+        }
+        members.push_back(k);
+        ++count;
+        // every variable sharing a term with k conflicts with this window
+        for (int32_t q = vr.row; q < vr.row + vr.deg; ++q) {
+            const IncRec &r = p.inc[q];
+            const uint32_t no = r.meta >> 8;
+            if (no <= 3) {
+                for (uint32_t f = 0; f < no; ++f) stamp[r.o[f]] = win;
+            } else {
+                for (uint32_t f = 0; f < no; ++f) stamp[p.overflow[(size_t)r.o[0] + f]] = win;
+            }
+        }
+    }
+    const int32_t n_win = (int32_t)starts.size();
+    starts.push_back((int32_t)members.size());
+    out.assign((size_t)n_win * G, SchedRec{-1, 0, 1, 0, 0, 0u, {0, 0}});
+    for (int32_t w = 0; w < n_win; ++w) {
+        for (int32_t i = starts[w]; i < starts[w + 1]; ++i) {
+            const int g = i - starts[w];
+            const int32_t k = members[i];
+            const VarRec &vr = p.var[k];
+            out[(size_t)g * n_win + w] = SchedRec{k, vr.lo, vr.width, vr.row, vr.deg, p.emask[k], {0, 0}};
+        }
+    }
+    return n_win;
+}
+
 }  // namespace sa

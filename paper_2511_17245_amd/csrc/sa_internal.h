@@ -68,6 +68,20 @@ struct Packed {
 };
 int pack(const Canonical &c, Packed &out, std::string &err);
 
+// One slot of the sweep schedule: in window w, wave g of a replica updates variable k (k = -1:
+// the wave idles in that window).  Variables of one window share no term, so their updates
+// commute and may run at the same time; windows follow the index order of the sweep (Sec. 3.1)
+// and fixed variables (l = u) are left out.
+struct SchedRec {
+    int32_t k;
+    int32_t lo, width, row, deg;
+    uint32_t emask;
+    int32_t pad[2];
+};
+// Greedy windows of at most G mutually non-interacting variables, stored wave-major
+// (slot g * n_win + w).  Returns the number of windows.
+int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out);
+
 // Device view of a packed plan.
 struct DevProblem {
     int32_t n;
@@ -93,17 +107,21 @@ struct AnnealArgs {
     uint32_t key0, key1;     // Philox key (seed)
     uint32_t instance_id;
     double otm_r;            // < 0: r = s/(S-1)
+    const SchedRec *sched;   // G * n_win schedule slots (device)
+    int32_t n_win;           // windows per sweep
+    int32_t win_waves;       // G: waves per replica (1: each wave is an independent replica)
     const int32_t *z_init;   // device, n_reads * n, or nullptr
     int32_t *z_out;          // device, n_reads * n (also the working state when not in LDS)
     int64_t *e_out;          // device, n_reads
 };
 
 struct LaunchChoice {
+    int win_waves = 1;         // waves per replica (window width)
     int waves_per_group = 1;
     int groups = 1;
     int lds_bytes = 0;
     bool state_in_lds = true;
-    bool reg_weights = false;  // heat bath: weights kept in registers
+    int reg_chunk = 0;         // heat bath: weights per lane kept in registers (0: recomputed)
     int maxe_class = 1;        // kernel's largest exponent (1, 2, 4 or 16)
     int variant = 0;
 };
@@ -113,7 +131,9 @@ int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *s
                   std::string &err);
 // Picks the launch geometry for n_reads replicas of an n-variable problem on `device`.
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device);
+                           int device, int win_waves);
+// LDS bytes of one replica's state when its G waves share it (state + per-wave energy slots).
+int64_t shared_state_bytes(int32_t n, int G);
 // Energies of n_states device-resident states (one wavefront per state).
 int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, int64_t *out,
                   void *stream, std::string &err);

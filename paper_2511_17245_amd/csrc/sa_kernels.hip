@@ -59,28 +59,78 @@ __device__ __forceinline__ uint32_t lane_read32(uint32_t x, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) x += __shfl_xor(x, off);
-    return uni64(x);
+__device__ __forceinline__ uint64_t lane_read64(uint64_t x, int lane) {
+    return ((uint64_t)lane_read32((uint32_t)(x >> 32), lane) << 32) | lane_read32((uint32_t)x, lane);
 }
+
+// DPP move of a 64-bit value (two 32-bit halves); lanes without a valid source take `identity`.
+template <int kCtrl, int kRowMask, int kBankMask>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x, uint64_t identity) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)identity, (int)(uint32_t)x,
+                                                              kCtrl, kRowMask, kBankMask, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(identity >> 32),
+                                                              (int)(uint32_t)(x >> 32), kCtrl, kRowMask,
+                                                              kBankMask, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int kCtrl, int kRowMask, int kBankMask>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t identity) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, kCtrl, kRowMask, kBankMask, false);
+}
+
+// GFX9 DPP controls: row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143,
+// wave_shr:1 = 0x138.  The six steps below form an inclusive scan whose lane 63 holds the
+// reduction of all 64 lanes (rows of 16 lanes, then the row broadcasts).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+    x += dpp64<0x111, 0xf, 0xf>(x, 0);
+    x += dpp64<0x112, 0xf, 0xf>(x, 0);
+    x += dpp64<0x114, 0xf, 0xf>(x, 0);
+    x += dpp64<0x118, 0xf, 0xf>(x, 0);
+    x += dpp64<0x142, 0xa, 0xf>(x, 0);
+    x += dpp64<0x143, 0xc, 0xf>(x, 0);
+    return lane_read64(x, kWave - 1);
+}
+
+__device__ __forceinline__ int64_t min64(int64_t a, uint64_t b) { return (int64_t)b < a ? (int64_t)b : a; }
 
 __device__ __forceinline__ int64_t wave_min_i64(int64_t x) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int64_t y = __shfl_xor(x, off);
-        x = y < x ? y : x;
-    }
-    return (int64_t)uni64((uint64_t)x);
+    const uint64_t id = (uint64_t)INT64_MAX;
+    x = min64(x, dpp64<0x111, 0xf, 0xf>((uint64_t)x, id));
+    x = min64(x, dpp64<0x112, 0xf, 0xf>((uint64_t)x, id));
+    x = min64(x, dpp64<0x114, 0xf, 0xf>((uint64_t)x, id));
+    x = min64(x, dpp64<0x118, 0xf, 0xf>((uint64_t)x, id));
+    x = min64(x, dpp64<0x142, 0xa, 0xf>((uint64_t)x, id));
+    x = min64(x, dpp64<0x143, 0xc, 0xf>((uint64_t)x, id));
+    return (int64_t)lane_read64((uint64_t)x, kWave - 1);
 }
 
+__device__ __forceinline__ int32_t min32(int32_t a, uint32_t b) { return (int32_t)b < a ? (int32_t)b : a; }
+
 __device__ __forceinline__ int32_t wave_min_i32(int32_t x) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int32_t y = __shfl_xor(x, off);
-        x = y < x ? y : x;
-    }
-    return (int32_t)uni32((uint32_t)x);
+    const uint32_t id = (uint32_t)INT32_MAX;
+    x = min32(x, dpp32<0x111, 0xf, 0xf>((uint32_t)x, id));
+    x = min32(x, dpp32<0x112, 0xf, 0xf>((uint32_t)x, id));
+    x = min32(x, dpp32<0x114, 0xf, 0xf>((uint32_t)x, id));
+    x = min32(x, dpp32<0x118, 0xf, 0xf>((uint32_t)x, id));
+    x = min32(x, dpp32<0x142, 0xa, 0xf>((uint32_t)x, id));
+    x = min32(x, dpp32<0x143, 0xc, 0xf>((uint32_t)x, id));
+    return (int32_t)lane_read32((uint32_t)x, kWave - 1);
+}
+
+// Lane l receives lane l-1's value (lane 0 receives `first`): DPP wave_shr:1.
+__device__ __forceinline__ double wave_shift_up1(double x, double first) {
+    const uint64_t b = dpp64<0x138, 0xf, 0xf>((uint64_t)__double_as_longlong(x),
+                                              (uint64_t)__double_as_longlong(first));
+    return __longlong_as_double((long long)b);
+}
+
+// Lane l receives lane (l - d)'s value for l >= d, else its own (ds_bpermute).
+__device__ __forceinline__ double wave_shift_up(double x, int d, int lane) {
+    const int src = lane >= d ? lane - d : lane;
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Orders a lane's LDS/global state write before later reads by other lanes of the same wave.
@@ -104,23 +154,38 @@ __device__ __forceinline__ uint64_t upow(uint64_t x, int e) {
     return r;
 }
 
-// J_t times the product of the term's other factors, for incidence `idx` of the row being visited.
-// Sets e to the exponent of the visited variable in the term.
-__device__ __forceinline__ uint64_t incidence_product(const DevProblem &P, const int32_t *z,
-                                                      int32_t idx, int &e) {
-    const IncRec r = P.inc[idx];
+// J_t times the product of the term's other factors, for one incidence record of the row being
+// visited.  Sets e to the exponent of the visited variable in the term.  A zero record (meta = 0,
+// coef = 0) contributes nothing, so lanes beyond the row hold one.
+__device__ __forceinline__ uint64_t record_product(const DevProblem &P, const int32_t *z,
+                                                   const IncRec &r, uint64_t coef, int &e) {
     e = (int)(r.meta & 0xFFu);
     const int no = (int)(r.meta >> 8);
-    uint64_t prod = (uint64_t)P.inc_coef[idx];
+    uint64_t prod = coef;
     if (no <= 3) {
-        if (no > 0) prod *= (uint64_t)(int64_t)z[r.o[0]];
-        if (no > 1) prod *= (uint64_t)(int64_t)z[r.o[1]];
-        if (no > 2) prod *= (uint64_t)(int64_t)z[r.o[2]];
+        // all three reads issued together (unused slots hold index 0, a valid variable)
+        const int64_t z0 = z[r.o[0]], z1 = z[r.o[1]], z2 = z[r.o[2]];
+        prod *= no > 0 ? (uint64_t)z0 : 1ull;
+        prod *= no > 1 ? (uint64_t)z1 : 1ull;
+        prod *= no > 2 ? (uint64_t)z2 : 1ull;
     } else {
         const int32_t *o = P.overflow + r.o[0];
         for (int f = 0; f < no; ++f) prod *= (uint64_t)(int64_t)z[o[f]];
     }
     return prod;
+}
+
+// Loads this lane's record of chunk [c0, c0 + 64) of a row (a zero record past the row's end).
+__device__ __forceinline__ void load_record(const DevProblem &P, int32_t row, int32_t deg, int32_t c0,
+                                            int lane, IncRec &r, uint64_t &coef) {
+    if (lane < deg - c0) {
+        r = P.inc[row + c0 + lane];
+        coef = (uint64_t)P.inc_coef[row + c0 + lane];
+    } else {
+        r.meta = 0;
+        r.o[0] = r.o[1] = r.o[2] = 0;
+        coef = 0;
+    }
 }
 
 // Uniform coefficients a_k^(m) (Sec. 3.2, T_k = sum_m a_k^(m) z_k^m) for m = 1..kMaxE; every
@@ -132,17 +197,25 @@ struct Coeffs {
 
 template <int kMaxE>
 __device__ __forceinline__ void row_coeffs(const DevProblem &P, const int32_t *z, int32_t row,
-                                           int32_t deg, uint32_t emask, int lane, Coeffs<kMaxE> &C) {
+                                           int32_t deg, uint32_t emask, int lane, const IncRec &r0,
+                                           uint64_t coef0, Coeffs<kMaxE> &C) {
     uint64_t part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
-    for (int32_t c0 = 0; c0 < deg; c0 += kWave) {
-        if (lane < deg - c0) {
-            int e;
-            const uint64_t prod = incidence_product(P, z, row + c0 + lane, e);
+    {
+        int e;
+        const uint64_t prod = record_product(P, z, r0, coef0, e);
 #pragma unroll
-            for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : 0ull;
-        }
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : 0ull;
+    }
+    for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
+        IncRec r;
+        uint64_t coef;
+        load_record(P, row, deg, c0, lane, r, coef);
+        int e;
+        const uint64_t prod = record_product(P, z, r, coef, e);
+#pragma unroll
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : 0ull;
     }
     C.a[0] = 0;
 #pragma unroll
@@ -164,14 +237,17 @@ __device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE> &C, int64_t zk
 
 // dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
 __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const int32_t *z, int32_t row,
-                                                int32_t deg, int64_t zk, int64_t v, int lane) {
-    uint64_t acc = 0;
-    for (int32_t c0 = 0; c0 < deg; c0 += kWave) {
-        if (lane < deg - c0) {
-            int e;
-            const uint64_t prod = incidence_product(P, z, row + c0 + lane, e);
-            acc += prod * (upow((uint64_t)v, e) - upow((uint64_t)zk, e));
-        }
+                                                int32_t deg, int64_t zk, int64_t v, int lane,
+                                                const IncRec &r0, uint64_t coef0) {
+    int e;
+    uint64_t prod = record_product(P, z, r0, coef0, e);
+    uint64_t acc = prod * (upow((uint64_t)v, e) - upow((uint64_t)zk, e));
+    for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
+        IncRec r;
+        uint64_t coef;
+        load_record(P, row, deg, c0, lane, r, coef);
+        prod = record_product(P, z, r, coef, e);
+        acc += prod * (upow((uint64_t)v, e) - upow((uint64_t)zk, e));
     }
     return (int64_t)wave_sum_u64(acc);
 }
@@ -192,15 +268,22 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
     const int64_t c = (W + kWave - 1) / kWave;
     const int64_t j0 = (int64_t)lane * c;
     // minimum energy difference over all values (weights are taken relative to it)
-    int64_t dmin = INT64_MAX;
-    for (int64_t i = 0; i < c; ++i) {
-        const int64_t j = j0 + i;
-        if (j < W) {
-            const int64_t d = poly_delta(C, zk, lo + j);
-            dmin = d < dmin ? d : dmin;
+    int64_t dmin;
+    if (kMaxE == 1) {
+        // dE(v) = a1 (v - z_k) is linear: its minimum over [lo, hi] is at an end of the range
+        const int64_t a1 = (int64_t)C.a[1];
+        dmin = (int64_t)(C.a[1] * (uint64_t)((a1 >= 0 ? lo : lo + W - 1) - zk));
+    } else {
+        dmin = INT64_MAX;
+        for (int64_t i = 0; i < c; ++i) {
+            const int64_t j = j0 + i;
+            if (j < W) {
+                const int64_t d = poly_delta(C, zk, lo + j);
+                dmin = d < dmin ? d : dmin;
+            }
         }
+        dmin = wave_min_i64(dmin);
     }
-    dmin = wave_min_i64(dmin);
 
     double w[kRegChunk > 0 ? kRegChunk : 1];
     double lane_sum = 0.0;
@@ -221,18 +304,22 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
             if (j < W) lane_sum += exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
         }
     }
+    // Kogge-Stone inclusive scan, strides 1, 2, 4, 8, 16, 32: incl_l += incl_(l-d) for l >= d
     double incl = lane_sum;
+    {
+        const double y = wave_shift_up1(incl, 0.0);
+        if (lane >= 1) incl = incl + y;
+    }
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double y = __shfl_up(incl, off);
+    for (int off = 2; off < kWave; off <<= 1) {
+        const double y = wave_shift_up(incl, off, lane);
         if (lane >= off) incl = incl + y;
     }
-    const double total = __shfl(incl, kWave - 1);
-    double before = __shfl_up(incl, 1);
-    if (lane == 0) before = 0.0;
+    const double total = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(incl), kWave - 1));
+    const double before = wave_shift_up1(incl, 0.0);
     const double thr = U * total;
 
-    int64_t hit = -1;
+    int32_t hit = -1;
     double run = 0.0;
     if (kRegChunk > 0) {
 #pragma unroll
@@ -250,7 +337,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
             if (j < W) {
                 run += exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
                 if (before + run > thr) {
-                    hit = i;
+                    hit = (int32_t)i;
                     break;
                 }
             }
@@ -259,9 +346,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
     const uint64_t mask = __ballot(hit >= 0);
     if (mask == 0) return lo + W - 1;
     const int src = __ffsll((unsigned long long)mask) - 1;
-    const int64_t hit_at = (int64_t)(((uint64_t)lane_read32((uint32_t)((uint64_t)hit >> 32), src) << 32) |
-                                     lane_read32((uint32_t)hit, src));
-    return lo + (int64_t)src * c + hit_at;
+    return lo + (int64_t)src * c + (int64_t)(int32_t)lane_read32((uint32_t)hit, src);
 }
 
 // Optimal transition (Sec. 3.3.3): the nonzero change of smallest dE, ties to the smallest value.
@@ -285,100 +370,155 @@ __device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE> &C, int64_
 
 // ------------------------------------------------------------------------------------------------
 // The annealing kernel.
+//
+// G = A.win_waves waves per replica.  G = 1: every wave of the workgroup is an independent replica.
+// G > 1: the workgroup is one replica whose state is shared in LDS; in each window of the schedule
+// wave g updates the window's g-th variable, and a barrier closes the window.  The variables of a
+// window share no term, so this equals the sequential index-order sweep exactly.
 // ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void window_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE>
 __global__ void __launch_bounds__(256) anneal_kernel(AnnealArgs A) {
     extern __shared__ int32_t lds_state[];
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
-    const int read = (int)blockIdx.x * A.waves_per_group + wave;
-    if (read >= A.n_reads) return;  // whole wavefront leaves; no workgroup barriers follow
+    const int G = A.win_waves;
+    const bool shared = G > 1;
+    const int read = shared ? (int)blockIdx.x : (int)blockIdx.x * A.waves_per_group + wave;
+    const int g = shared ? wave : 0;
+    if (read >= A.n_reads) return;  // uniform over the replica's waves; no barrier is skipped
     const DevProblem &P = A.P;
     const int32_t n = P.n;
-    int32_t *z = kStateInLds ? lds_state + (size_t)wave * n : A.z_out + (size_t)read * n;
+    int32_t *z = kStateInLds ? lds_state + (shared ? 0 : (size_t)wave * n) : A.z_out + (size_t)read * n;
     const uint32_t rd = (uint32_t)read;
+    const int tid = g * kWave + lane, nthr = G * kWave;  // threads of this replica
 
     // initial state: given (resume) or uniform on each box (Sec. 3.1)
     if (A.z_init) {
         const int32_t *zi = A.z_init + (size_t)read * n;
         if (zi != z)
-            for (int32_t k = lane; k < n; k += kWave) z[k] = zi[k];
+            for (int32_t k = tid; k < n; k += nthr) z[k] = zi[k];
     } else {
-        for (int32_t k = lane; k < n; k += kWave) {
+        for (int32_t k = tid; k < n; k += nthr) {
             uint32_t x0 = (uint32_t)k, x1 = 0xFFFFFFFFu, x2 = rd, x3 = A.instance_id;
             philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
             const VarRec vr = P.var[k];
             z[k] = vr.lo + (int32_t)(((uint64_t)x0 * (uint64_t)(uint32_t)vr.width) >> 32);
         }
     }
-    state_write_fence<kStateInLds>();
+    if (shared) window_barrier();
+    else state_write_fence<kStateInLds>();
 
-    // E(z) = sum_t J_t prod z (term-major, lanes split the terms)
+    // E(z) = sum_t J_t prod z (term-major, the replica's threads split the terms); each wave keeps
+    // its partial sum plus the energy changes of its own updates
     uint64_t eacc = 0;
-    for (int32_t t = lane; t < P.n_terms; t += kWave) {
+    for (int32_t t = tid; t < P.n_terms; t += nthr) {
         uint64_t prod = (uint64_t)P.t_coef[t];
         for (int32_t f = P.t_off[t]; f < P.t_off[t + 1]; ++f) prod *= (uint64_t)(int64_t)z[P.t_var[f]];
         eacc += prod;
     }
     int64_t E = (int64_t)wave_sum_u64(eacc);
 
+    const int32_t n_win = A.n_win;
+    const SchedRec *mine = A.sched + (size_t)g * n_win;
     for (int32_t s = A.s_begin; s < A.s_end; ++s) {
         const double beta = A.beta[s];
         const double r_opt =
             A.otm_r >= 0.0 ? A.otm_r : (A.n_sweeps > 1 ? (double)s / (double)(A.n_sweeps - 1) : 0.0);
-        for (int32_t kb = 0; kb < n; kb += kWave) {
-            // draws of the next 64 variables, one block per lane
-            uint32_t x0 = (uint32_t)(kb + lane), x1 = (uint32_t)s, x2 = rd, x3 = A.instance_id;
+        for (int32_t wb = 0; wb < n_win; wb += kWave) {
+            // per block of 64 windows: lane j holds this wave's slot of window wb+j and its draws
+            const int32_t wl = wb + lane;
+            SchedRec sl;
+            if (wl < n_win) {
+                sl = mine[wl];
+            } else {
+                sl.k = -1;
+                sl.lo = 0;
+                sl.width = 1;
+                sl.row = 0;
+                sl.deg = 0;
+                sl.emask = 0;
+            }
+            uint32_t x0 = (uint32_t)sl.k, x1 = (uint32_t)s, x2 = rd, x3 = A.instance_id;
             philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
-            const int32_t kend = n - kb < kWave ? n - kb : kWave;
-            for (int32_t j = 0; j < kend; ++j) {
-                const int32_t k = kb + j;
-                const VarRec vr = P.var[k];
-                if (vr.width == 1) continue;  // fixed variable
-                const uint32_t r0 = lane_read32(x0, j), r1 = lane_read32(x1, j);
-                const uint32_t r2 = lane_read32(x2, j), r3 = lane_read32(x3, j);
-                const double U = (double)((((uint64_t)r2 << 32) | r3) >> 11) * 0x1p-53;
-                const int64_t lo = vr.lo, W = vr.width;
-                const int64_t zk = (int64_t)(int32_t)uni32((uint32_t)z[k]);
-                int64_t v, d;
-                bool accept;
-                if (kRule == SA_METROPOLIS) {
-                    v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
-                    if (v >= zk) v += 1;
-                    d = direct_delta(P, z, vr.row, vr.deg, zk, v, lane);
-                    accept = metropolis_accept(d, beta, U);
-                } else if (kRule == SA_HEAT_BATH) {
-                    Coeffs<kMaxE> C;
-                    row_coeffs<kMaxE>(P, z, vr.row, vr.deg, P.emask[k], lane, C);
-                    v = heat_bath_pick<kRegChunk, kMaxE>(C, lo, W, zk, beta, U, lane);
-                    d = poly_delta(C, zk, v);
-                    accept = true;
-                } else {
-                    if ((double)r0 * 0x1p-32 < r_opt) {
-                        Coeffs<kMaxE> C;
-                        row_coeffs<kMaxE>(P, z, vr.row, vr.deg, P.emask[k], lane, C);
-                        v = argmin_nonzero<kMaxE>(C, lo, W, zk, lane, d);
-                    } else {
+            const int32_t wend = n_win - wb < kWave ? n_win - wb : kWave;
+            // first chunk of the next slot's incidence records, loaded one window ahead
+            IncRec nrec;
+            uint64_t ncoef;
+            load_record(P, (int32_t)lane_read32((uint32_t)sl.row, 0), (int32_t)lane_read32((uint32_t)sl.deg, 0),
+                        0, lane, nrec, ncoef);
+            for (int32_t j = 0; j < wend; ++j) {
+                const int32_t k = (int32_t)lane_read32((uint32_t)sl.k, j);
+                const IncRec crec = nrec;
+                const uint64_t ccoef = ncoef;
+                if (j + 1 < wend)
+                    load_record(P, (int32_t)lane_read32((uint32_t)sl.row, j + 1),
+                                (int32_t)lane_read32((uint32_t)sl.deg, j + 1), 0, lane, nrec, ncoef);
+                if (k >= 0) {
+                    const int64_t lo = (int32_t)lane_read32((uint32_t)sl.lo, j);
+                    const int64_t W = (int32_t)lane_read32((uint32_t)sl.width, j);
+                    const int32_t row = (int32_t)lane_read32((uint32_t)sl.row, j);
+                    const int32_t deg = (int32_t)lane_read32((uint32_t)sl.deg, j);
+                    const uint32_t r0 = lane_read32(x0, j), r1 = lane_read32(x1, j);
+                    const uint32_t r2 = lane_read32(x2, j), r3 = lane_read32(x3, j);
+                    const double U = (double)((((uint64_t)r2 << 32) | r3) >> 11) * 0x1p-53;
+                    const int64_t zk = (int64_t)(int32_t)uni32((uint32_t)z[k]);
+                    int64_t v, d;
+                    bool accept;
+                    if (kRule == SA_METROPOLIS) {
                         v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                         if (v >= zk) v += 1;
-                        d = direct_delta(P, z, vr.row, vr.deg, zk, v, lane);
+                        d = direct_delta(P, z, row, deg, zk, v, lane, crec, ccoef);
+                        accept = metropolis_accept(d, beta, U);
+                    } else if (kRule == SA_HEAT_BATH) {
+                        Coeffs<kMaxE> C;
+                        row_coeffs<kMaxE>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                        v = heat_bath_pick<kRegChunk, kMaxE>(C, lo, W, zk, beta, U, lane);
+                        d = poly_delta(C, zk, v);
+                        accept = true;
+                    } else {
+                        if ((double)r0 * 0x1p-32 < r_opt) {
+                            Coeffs<kMaxE> C;
+                            row_coeffs<kMaxE>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                            v = argmin_nonzero<kMaxE>(C, lo, W, zk, lane, d);
+                        } else {
+                            v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
+                            if (v >= zk) v += 1;
+                            d = direct_delta(P, z, row, deg, zk, v, lane, crec, ccoef);
+                        }
+                        accept = metropolis_accept(d, beta, U);
                     }
-                    accept = metropolis_accept(d, beta, U);
+                    if (accept && v != zk) {
+                        z[k] = (int32_t)v;  // every lane stores the same value
+                        E += d;
+                        if (!shared) state_write_fence<kStateInLds>();
+                    }
                 }
-                if (accept && v != zk) {
-                    z[k] = (int32_t)v;  // every lane stores the same value
-                    E += d;
-                    state_write_fence<kStateInLds>();
-                }
+                if (shared) window_barrier();
             }
         }
     }
 
+    if (shared) {
+        // combine the waves' energy parts; LDS slots follow the state
+        int64_t *parts = (int64_t *)(lds_state + (((size_t)n + 1) & ~(size_t)1));
+        if (lane == 0) parts[g] = E;
+        window_barrier();
+        if (g == 0) {
+            E = 0;
+            for (int q = 0; q < G; ++q) E += parts[q];
+        }
+    }
     if (kStateInLds) {
         int32_t *zo = A.z_out + (size_t)read * n;
-        for (int32_t k = lane; k < n; k += kWave) zo[k] = z[k];
+        for (int32_t k = tid; k < n; k += nthr) zo[k] = z[k];
     }
-    if (lane == 0) A.e_out[read] = E;
+    if (g == 0 && lane == 0) A.e_out[read] = E;
 }
 
 // Energies of stored states, one wavefront per state.
@@ -400,30 +540,39 @@ __global__ void __launch_bounds__(256) energy_kernel(DevProblem P, const int32_t
 
 using KernelFn = void (*)(AnnealArgs);
 
-template <int kRule, int kMaxE>
-KernelFn pick_lds_reg(bool in_lds, bool reg) {
-    if (reg) return in_lds ? anneal_kernel<kRule, true, kHeatBathRegChunk, kMaxE>
-                           : anneal_kernel<kRule, false, kHeatBathRegChunk, kMaxE>;
-    return in_lds ? anneal_kernel<kRule, true, 0, kMaxE> : anneal_kernel<kRule, false, 0, kMaxE>;
+// Heat bath: the weights of ceil(W/64) <= kRegChunk values per lane stay in registers (the
+// unrolled loops then cost kRegChunk steps); wider ranges recompute them (kRegChunk = 0).
+template <int kMaxE>
+KernelFn pick_heat_bath_lds(int reg_chunk) {
+    switch (reg_chunk) {
+        case 1: return anneal_kernel<SA_HEAT_BATH, true, 1, kMaxE>;
+        case 2: return anneal_kernel<SA_HEAT_BATH, true, 2, kMaxE>;
+        case 8: return anneal_kernel<SA_HEAT_BATH, true, 8, kMaxE>;
+        case 32: return anneal_kernel<SA_HEAT_BATH, true, 32, kMaxE>;
+        default: return anneal_kernel<SA_HEAT_BATH, true, 0, kMaxE>;
+    }
 }
 
-// Kernel variants: rule x state placement x (heat bath) weights in registers x exponent class.
-KernelFn pick_kernel(int rule, bool in_lds, bool reg, int maxe_class) {
+// Kernel variants: rule x exponent class x (heat bath) register chunk, for states in LDS; states
+// in device memory (very large N) use one generic variant per rule.
+KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class) {
     if (rule == SA_METROPOLIS)
         return in_lds ? anneal_kernel<SA_METROPOLIS, true, 0, 1> : anneal_kernel<SA_METROPOLIS, false, 0, 1>;
     if (rule == SA_HEAT_BATH) {
+        if (!in_lds) return anneal_kernel<SA_HEAT_BATH, false, 0, kMaxExpPoly>;
         switch (maxe_class) {
-            case 1: return pick_lds_reg<SA_HEAT_BATH, 1>(in_lds, reg);
-            case 2: return pick_lds_reg<SA_HEAT_BATH, 2>(in_lds, reg);
-            case 4: return pick_lds_reg<SA_HEAT_BATH, 4>(in_lds, reg);
-            default: return pick_lds_reg<SA_HEAT_BATH, kMaxExpPoly>(in_lds, reg);
+            case 1: return pick_heat_bath_lds<1>(reg_chunk);
+            case 2: return pick_heat_bath_lds<2>(reg_chunk);
+            case 4: return pick_heat_bath_lds<4>(reg_chunk);
+            default: return pick_heat_bath_lds<kMaxExpPoly>(reg_chunk);
         }
     }
     if (rule == SA_OPT_METROPOLIS) {
+        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 0, 4>;
         switch (maxe_class) {
-            case 1: return pick_lds_reg<SA_OPT_METROPOLIS, 1>(in_lds, false);
-            case 2: return pick_lds_reg<SA_OPT_METROPOLIS, 2>(in_lds, false);
-            default: return pick_lds_reg<SA_OPT_METROPOLIS, 4>(in_lds, false);
+            case 1: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1>;
+            case 2: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2>;
+            default: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 4>;
         }
     }
     return nullptr;
@@ -438,32 +587,49 @@ int maxe_class_of(int32_t max_exp) {
 
 }  // namespace
 
+int64_t shared_state_bytes(int32_t n, int G) {
+    return (((int64_t)n + 1) & ~(int64_t)1) * (int64_t)sizeof(int32_t) + (int64_t)G * (int64_t)sizeof(int64_t);
+}
+
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device) {
+                           int device, int win_waves) {
     LaunchChoice lc;
     int cus = 256, max_lds = 65536;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    // spread replicas over all compute units first, then stack them (up to 4 waves per group)
-    int wpg = n_reads / (cus > 0 ? cus : 1);
-    wpg = wpg < 1 ? 1 : (wpg > 4 ? 4 : wpg);
     const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
-    while (wpg > 1 && per_wave * wpg > max_lds) --wpg;
-    lc.state_in_lds = per_wave * wpg <= max_lds;
-    lc.waves_per_group = wpg;
-    lc.groups = (n_reads + wpg - 1) / wpg;
-    lc.lds_bytes = lc.state_in_lds ? (int)(per_wave * wpg) : 0;
+    if (win_waves > 1 && shared_state_bytes(n, win_waves) <= max_lds) {
+        // one replica per workgroup, its G waves share the state
+        lc.win_waves = win_waves;
+        lc.waves_per_group = win_waves;
+        lc.groups = n_reads;
+        lc.state_in_lds = true;
+        lc.lds_bytes = (int)shared_state_bytes(n, win_waves);
+    } else {
+        // spread replicas over all compute units first, then stack them (up to 4 waves per group)
+        int wpg = n_reads / (cus > 0 ? cus : 1);
+        wpg = wpg < 1 ? 1 : (wpg > 4 ? 4 : wpg);
+        while (wpg > 1 && per_wave * wpg > max_lds) --wpg;
+        lc.win_waves = 1;
+        lc.state_in_lds = per_wave * wpg <= max_lds;
+        lc.waves_per_group = wpg;
+        lc.groups = (n_reads + wpg - 1) / wpg;
+        lc.lds_bytes = lc.state_in_lds ? (int)(per_wave * wpg) : 0;
+    }
     const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
-    const int reg = (rule == SA_HEAT_BATH && chunk <= kHeatBathRegChunk) ? 1 : 0;
-    lc.maxe_class = maxe_class_of(max_exp);
-    lc.reg_weights = reg != 0;
-    lc.variant = rule * 1000 + lc.maxe_class * 10 + (lc.state_in_lds ? 2 : 0) + reg;
+    int reg = 0;
+    if (rule == SA_HEAT_BATH && lc.state_in_lds)
+        reg = chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0;
+    lc.maxe_class = lc.state_in_lds ? maxe_class_of(max_exp)
+                                    : (rule == SA_HEAT_BATH ? kMaxExpPoly : rule == SA_OPT_METROPOLIS ? 4 : 1);
+    lc.reg_chunk = reg;
+    lc.variant = rule * 10000 + lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
     return lc;
 }
 
 int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
                   std::string &err) {
-    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_weights, lc.maxe_class);
+    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class);
     if (!fn) {
         err = "unknown rule";
         return SA_EINVAL;

@@ -42,7 +42,7 @@ class sa_schedule(C.Structure):
 class sa_opts(C.Structure):
     _fields_ = [("instance_id", C.c_uint32), ("hip_stream", C.c_void_p), ("device_buffers", C.c_int32),
                 ("sweep_begin", C.c_int32), ("sweep_end", C.c_int32), ("init_states", C.c_void_p),
-                ("otm_r", C.c_double)]
+                ("otm_r", C.c_double), ("waves_per_replica", C.c_int32)]
 
 
 class sa_plan_info(C.Structure):
@@ -53,7 +53,8 @@ class sa_plan_info(C.Structure):
 
 class sa_launch_info(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("groups", C.c_int32), ("lds_bytes", C.c_int32),
-                ("state_in_lds", C.c_int32), ("kernel_variant", C.c_int32)]
+                ("state_in_lds", C.c_int32), ("kernel_variant", C.c_int32),
+                ("waves_per_replica", C.c_int32), ("n_windows", C.c_int32)]
 
 
 _lib = None
@@ -132,7 +133,7 @@ def _schedule(n_sweeps: int, beta):
 
 
 def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, sweep_end=0,
-              init_states=None, otm_r=-1.0) -> sa_opts:
+              init_states=None, otm_r=-1.0, waves_per_replica=0) -> sa_opts:
     o = sa_opts()
     lib().sa_opts_default(C.byref(o))
     o.instance_id = int(instance_id) & 0xFFFFFFFF
@@ -142,6 +143,7 @@ def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, s
     o.sweep_end = int(sweep_end)
     o.init_states = _p(init_states)
     o.otm_r = float(otm_r)
+    o.waves_per_replica = int(waves_per_replica)
     return o
 
 
@@ -207,7 +209,8 @@ class Plan:
         return {f: getattr(i, f) for f, _ in sa_launch_info._fields_}
 
     def run_device(self, n_sweeps, n_reads, seed, z_out, e_out, beta=None, stream=None,
-                   instance_id=0, sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0):
+                   instance_id=0, sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0,
+                   waves_per_replica=0):
         """Queue a run writing into device tensors z_out (int32 [n_reads, N]) and e_out (int64)."""
         assert z_out.is_cuda and e_out.is_cuda
         assert z_out.dtype.itemsize == 4 and e_out.dtype.itemsize == 8
@@ -216,19 +219,20 @@ class Plan:
         if init_states is not None:
             assert init_states.is_cuda and init_states.numel() == n_reads * self.n
         sched, keep = _schedule(n_sweeps, beta)
-        opts = make_opts(instance_id, stream, True, sweep_begin, sweep_end, init_states, otm_r)
+        opts = make_opts(instance_id, stream, True, sweep_begin, sweep_end, init_states, otm_r,
+                         waves_per_replica)
         rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                _p(z_out), _p(e_out), C.byref(opts))
         _check(rc, "sa_plan_run")
 
     def run(self, n_sweeps, n_reads, seed, beta=None, instance_id=0, sweep_begin=0, sweep_end=0,
-            init_states=None, otm_r=-1.0):
+            init_states=None, otm_r=-1.0, waves_per_replica=0):
         """Run with host buffers; returns (states, energies)."""
         sched, keep = _schedule(n_sweeps, beta)
         z = np.zeros((n_reads, self.n), np.int32)
         e = np.zeros(n_reads, np.int64)
         zi = None if init_states is None else np.ascontiguousarray(init_states, np.int32)
-        opts = make_opts(instance_id, None, False, sweep_begin, sweep_end, zi, otm_r)
+        opts = make_opts(instance_id, None, False, sweep_begin, sweep_end, zi, otm_r, waves_per_replica)
         rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                _p(z), _p(e), C.byref(opts))
         _check(rc, "sa_plan_run")

@@ -27,7 +27,7 @@ def rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=None, s0=0, s1=0):
+def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=None, s0=0, s1=0, G=0):
     import torch
     plan = sa.Plan(prob, rule)
     z = torch.empty((n_reads, prob.n_vars), dtype=torch.int32, device="cuda")
@@ -35,7 +35,7 @@ def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=Non
     zi = None if init is None else torch.as_tensor(np.ascontiguousarray(init, np.int32), device="cuda")
     plan.run_device(len(beta), n_reads, seed, z, e, beta=beta,
                     stream=torch.cuda.current_stream().cuda_stream, instance_id=instance_id,
-                    otm_r=otm_r, init_states=zi, sweep_begin=s0, sweep_end=s1)
+                    otm_r=otm_r, init_states=zi, sweep_begin=s0, sweep_end=s1, waves_per_replica=G)
     torch.cuda.synchronize()
     launch = plan.last_launch()
     plan.close()
@@ -82,6 +82,25 @@ def test_small_instances_all_reads(case):
         zg, eg, launch = gpu_run(prob, rule, beta, reads, seed=1234 + rule, instance_id=3)
         zo, eo = P.anneal(rule, beta, reads, seed=1234 + rule, instance_id=3)
         assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]} {launch}")
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_cooperating_waves_match_sequential_sweep(rule):
+    # G waves per replica update the variables of a window (no shared term) at the same time;
+    # the result must equal the sequential index-order sweep for every G
+    r = rng(55)
+    cases = [("er_quio", I.erdos_renyi_quio(700, 5.0, -20, 20, 10, 10, r)),
+             ("huio_powers", I.random_huio(400, 1200, [1, 2, 3, 4], -6, 6, 4, r)),
+             ("ml_long", I.multilinear(150, 7, 2))]
+    for name, prob in cases:
+        P = oracle.Poly(prob)
+        beta, _, _ = P.schedule(25)
+        zo, eo = P.anneal(rule, beta, 12, seed=31)
+        for G in (1, 2, 4):
+            say("windows", name, sa.RULE_NAMES[rule], "G", G)
+            zg, eg, launch = gpu_run(prob, rule, beta, 12, seed=31, G=G)
+            assert launch["waves_per_replica"] == G
+            assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]}/G={G} {launch}")
 
 
 def test_cfg1_full_all_reads():
