@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis"])
     ap.add_argument("--sweeps", type=int, default=0, help="override the number of sweeps")
     ap.add_argument("--reads", type=int, default=0, help="override the number of reads")
+    ap.add_argument("--waves-per-replica", type=int, default=0,
+                    help="wavefronts cooperating on one replica (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reads", type=int, default=32)
     ap.add_argument("--cpu-sweeps", type=int, default=100)
@@ -99,7 +101,7 @@ def main():
 
     def step():
         plan.run_device(S, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
-                        instance_id=w.instance_id)
+                        instance_id=w.instance_id, waves_per_replica=args.waves_per_replica)
 
     for _ in range(args.warmup):
         step()

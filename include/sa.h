@@ -99,7 +99,7 @@ typedef struct {
     double otm_r;               /* < 0: r = s/(S-1) as in Sec. 3.3.3 (default); else a fixed r */
     int32_t waves_per_replica;  /* 0: automatic.  G > 1 lets G wavefronts of one replica update G
                                    consecutive variables that share no term at the same time (the
-                                   result is identical to the sequential sweep); 1, 2 or 4 */
+                                   result is identical to the sequential sweep); 1, 2, 4 or 8 */
 } sa_opts;
 
 void sa_opts_default(sa_opts *opts);

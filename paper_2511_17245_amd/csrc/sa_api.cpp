@@ -45,6 +45,7 @@ struct sa_plan {
     sa_plan_info info{};
     sa_launch_info last{};
     std::vector<int32_t> lo, hi;  // host copy of the box (checks of host start states)
+    bool narrow_ok = false;       // every |dE| < 2^30: 32-bit integer kernels are exact
     double t_init = 0.0, t_final = 0.0;
     int auto_status = SA_OK;
     std::string auto_error;
@@ -59,7 +60,7 @@ struct sa_plan {
         int32_t n_win = 0;
         int32_t n_active = 0;  // variables that are not fixed
     };
-    Sched sched[5];
+    Sched sched[9];
     ~sa_plan() {
         if (beta_dev) (void)hipFree(beta_dev);
         for (auto &sc : sched)
@@ -145,6 +146,7 @@ int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, s
     plan->rule = rule;
     plan->lo = canon.lo;
     plan->hi = canon.hi;
+    plan->narrow_ok = sa::dE_fits_32(canon);
     plan->auto_status = sa::auto_temperatures(canon, &plan->t_init, &plan->t_final, plan->auto_error);
     rc = upload_packed(pk, plan.get());
     if (rc != SA_OK) return rc;
@@ -159,7 +161,7 @@ int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, s
     in.max_width = pk.max_width;
     in.device_bytes = (int64_t)plan->arena.bytes;
     in.coef_bits = 64;
-    in.arith_bits = 64;
+    in.arith_bits = plan->narrow_ok && pk.max_exp <= 2 ? 32 : 64;
     plan->packed = std::move(pk);
     *out = plan.release();
     return SA_OK;
@@ -226,22 +228,22 @@ int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out) {
     return SA_OK;
 }
 
-// Waves per replica: enough replicas' waves to cover the 1024 SIMDs, as long as the windows are
-// wide enough to pay for the barriers and the shared state fits in LDS.
+// Waves per replica.  The sweep is latency-bound (one dependent chain per replica), so the widest
+// window G in {8, 4, 2} is taken whose waves stay busy (mean window size >= 0.6 G), whose shared
+// state fits in LDS and which keeps at most 8 waves per SIMD in flight; otherwise G = 1.
 int auto_waves_per_replica(sa_plan *plan, int32_t n_reads, int device) {
     int cus = 256, max_lds = 65536;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    int G = 1;
-    while (G < 4 && (int64_t)n_reads * G < (int64_t)cus * 4) G *= 2;
-    while (G > 1) {
+    const int64_t max_waves = (int64_t)cus * 4 * 8;
+    for (int G = 8; G > 1; G /= 2) {
+        if ((int64_t)n_reads * G > max_waves) continue;
+        if (sa::shared_state_bytes(plan->dp.n, G) > max_lds) continue;
         sa_plan::Sched *sc = nullptr;
-        if (sa::shared_state_bytes(plan->dp.n, G) <= max_lds && get_schedule(plan, G, &sc) == SA_OK &&
-            sc->n_win > 0 && (double)sc->n_active / (double)sc->n_win >= 1.25 * G / 2.0)
-            break;
-        G /= 2;
+        if (get_schedule(plan, G, &sc) != SA_OK || sc->n_win == 0) continue;
+        if ((double)sc->n_active / (double)sc->n_win >= 0.6 * G) return G;
     }
-    return G;
+    return 1;
 }
 
 int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t seed,
@@ -313,13 +315,13 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     a.z_out = z_dev;
     a.e_out = e_dev;
     int G = opts.waves_per_replica;
-    if (G != 0 && G != 1 && G != 2 && G != 4) {
+    if (G != 0 && G != 1 && G != 2 && G != 4 && G != 8) {
         if (tmp) (void)hipFree(tmp);
-        return fail(SA_EINVAL, "waves_per_replica must be 0, 1, 2 or 4");
+        return fail(SA_EINVAL, "waves_per_replica must be 0, 1, 2, 4 or 8");
     }
     if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
     sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
-                                            plan->info.max_exponent, plan->device, G);
+                                            plan->info.max_exponent, plan->device, G, plan->narrow_ok);
     sa_plan::Sched *sc = nullptr;
     rc = get_schedule(plan, lc.win_waves, &sc);
     if (rc != SA_OK) {

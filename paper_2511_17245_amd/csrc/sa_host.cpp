@@ -169,6 +169,25 @@ int check_int64_bound(const Canonical &c, std::string &err, double *bound_out) {
     return SA_OK;
 }
 
+bool dE_fits_32(const Canonical &c) {
+    const __int128 limit = (__int128)1 << 29;
+    std::vector<__int128> per_var(c.n, 0);
+    for (int64_t t = 0; t < c.n_terms(); ++t) {
+        __int128 term = c.t_coef[t] < 0 ? -(__int128)c.t_coef[t] : (__int128)c.t_coef[t];
+        for (int64_t f = c.t_off[t]; f < c.t_off[t + 1] && term < limit; ++f) {
+            const int32_t i = c.t_var[f];
+            term *= std::max(std::llabs((long long)c.lo[i]), std::llabs((long long)c.hi[i]));
+        }
+        if (term >= limit) return false;
+        for (int64_t f = c.t_off[t]; f < c.t_off[t + 1]; ++f) {
+            if (f > c.t_off[t] && c.t_var[f] == c.t_var[f - 1]) continue;
+            per_var[c.t_var[f]] += term;
+            if (per_var[c.t_var[f]] >= limit) return false;
+        }
+    }
+    return true;
+}
+
 int auto_temperatures(const Canonical &c, double *t_init, double *t_final, std::string &err) {
     // dE_max ~ max_k sum over terms holding z_k^m of |J| * prod_{other factors} zmax^e * (u_k - l_k)^m
     // dE_min ~ min |J| over the (merged, nonzero) coefficients.

@@ -34,6 +34,9 @@ struct Canonical {
 int canonicalize(const sa_instance *inst, const sa_bounds *bounds, Canonical &out, std::string &err);
 // SA_ERANGE when sum_t |J_t| prod zmax^e >= 2^62.  Also reports the largest |dE| bound.
 int check_int64_bound(const Canonical &c, std::string &err, double *bound_out);
+// True when max_k sum_{t containing k} |J_t| prod_{factors} zmax^e < 2^29, so every energy
+// difference |dE| < 2^30 and the difference of two of them fit 32-bit signed arithmetic.
+bool dE_fits_32(const Canonical &c);
 // Sec. 3.4 temperature range (T_init, T_final); SA_EINVAL if the problem has no energy scale.
 int auto_temperatures(const Canonical &c, double *t_init, double *t_final, std::string &err);
 // Geometric cooling of Sec. 3.1 between the two temperatures, as inverse temperatures.
@@ -123,6 +126,7 @@ struct LaunchChoice {
     bool state_in_lds = true;
     int reg_chunk = 0;         // heat bath: weights per lane kept in registers (0: recomputed)
     int maxe_class = 1;        // kernel's largest exponent (1, 2, 4 or 16)
+    bool narrow = false;       // energy differences in 32-bit arithmetic
     int variant = 0;
 };
 
@@ -131,7 +135,7 @@ int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *s
                   std::string &err);
 // Picks the launch geometry for n_reads replicas of an n-variable problem on `device`.
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device, int win_waves);
+                           int device, int win_waves, bool narrow_ok);
 // LDS bytes of one replica's state when its G waves share it (state + per-wave energy slots).
 int64_t shared_state_bytes(int32_t n, int G);
 // Energies of n_states device-resident states (one wavefront per state).

@@ -147,9 +147,36 @@ __device__ __forceinline__ void state_write_fence() {
     }
 }
 
+// Integer arithmetic of energy differences is done modulo 2^32 (Acc = uint32_t) or 2^64
+// (Acc = uint64_t).  Sums and products of a ring are exact modulo its size, so a result whose
+// true value fits the signed range is exact whatever the intermediate wrap-arounds; the host
+// picks 32 bits only when every |dE| of the problem is below 2^30 (differences of two values
+// then fit too).
+template <typename Acc>
+__device__ __forceinline__ int64_t to_i64(Acc x) {
+    if (sizeof(Acc) == 4) return (int64_t)(int32_t)(uint32_t)x;
+    return (int64_t)(uint64_t)x;
+}
+
+template <typename Acc>
+__device__ __forceinline__ Acc wave_sum(Acc x);
+template <>
+__device__ __forceinline__ uint64_t wave_sum<uint64_t>(uint64_t x) { return wave_sum_u64(x); }
+template <>
+__device__ __forceinline__ uint32_t wave_sum<uint32_t>(uint32_t x) {
+    x += dpp32<0x111, 0xf, 0xf>(x, 0);
+    x += dpp32<0x112, 0xf, 0xf>(x, 0);
+    x += dpp32<0x114, 0xf, 0xf>(x, 0);
+    x += dpp32<0x118, 0xf, 0xf>(x, 0);
+    x += dpp32<0x142, 0xa, 0xf>(x, 0);
+    x += dpp32<0x143, 0xc, 0xf>(x, 0);
+    return lane_read32(x, kWave - 1);
+}
+
 // x^e with wrap-around
-__device__ __forceinline__ uint64_t upow(uint64_t x, int e) {
-    uint64_t r = 1;
+template <typename Acc>
+__device__ __forceinline__ Acc upow(Acc x, int e) {
+    Acc r = 1;
     for (int i = 0; i < e; ++i) r *= x;
     return r;
 }
@@ -157,20 +184,21 @@ __device__ __forceinline__ uint64_t upow(uint64_t x, int e) {
 // J_t times the product of the term's other factors, for one incidence record of the row being
 // visited.  Sets e to the exponent of the visited variable in the term.  A zero record (meta = 0,
 // coef = 0) contributes nothing, so lanes beyond the row hold one.
-__device__ __forceinline__ uint64_t record_product(const DevProblem &P, const int32_t *z,
-                                                   const IncRec &r, uint64_t coef, int &e) {
+template <typename Acc>
+__device__ __forceinline__ Acc record_product(const DevProblem &P, const int32_t *z, const IncRec &r,
+                                              uint64_t coef, int &e) {
     e = (int)(r.meta & 0xFFu);
     const int no = (int)(r.meta >> 8);
-    uint64_t prod = coef;
+    Acc prod = (Acc)coef;
     if (no <= 3) {
         // all three reads issued together (unused slots hold index 0, a valid variable)
         const int64_t z0 = z[r.o[0]], z1 = z[r.o[1]], z2 = z[r.o[2]];
-        prod *= no > 0 ? (uint64_t)z0 : 1ull;
-        prod *= no > 1 ? (uint64_t)z1 : 1ull;
-        prod *= no > 2 ? (uint64_t)z2 : 1ull;
+        prod *= no > 0 ? (Acc)z0 : (Acc)1;
+        prod *= no > 1 ? (Acc)z1 : (Acc)1;
+        prod *= no > 2 ? (Acc)z2 : (Acc)1;
     } else {
         const int32_t *o = P.overflow + r.o[0];
-        for (int f = 0; f < no; ++f) prod *= (uint64_t)(int64_t)z[o[f]];
+        for (int f = 0; f < no; ++f) prod *= (Acc)(int64_t)z[o[f]];
     }
     return prod;
 }
@@ -190,66 +218,67 @@ __device__ __forceinline__ void load_record(const DevProblem &P, int32_t row, in
 
 // Uniform coefficients a_k^(m) (Sec. 3.2, T_k = sum_m a_k^(m) z_k^m) for m = 1..kMaxE; every
 // index is static so the coefficients stay in registers.
-template <int kMaxE>
+template <int kMaxE, typename Acc>
 struct Coeffs {
-    uint64_t a[kMaxE + 1];
+    Acc a[kMaxE + 1];
 };
 
-template <int kMaxE>
+template <int kMaxE, typename Acc>
 __device__ __forceinline__ void row_coeffs(const DevProblem &P, const int32_t *z, int32_t row,
                                            int32_t deg, uint32_t emask, int lane, const IncRec &r0,
-                                           uint64_t coef0, Coeffs<kMaxE> &C) {
-    uint64_t part[kMaxE + 1];
+                                           uint64_t coef0, Coeffs<kMaxE, Acc> &C) {
+    Acc part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
     {
         int e;
-        const uint64_t prod = record_product(P, z, r0, coef0, e);
+        const Acc prod = record_product<Acc>(P, z, r0, coef0, e);
 #pragma unroll
-        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : 0ull;
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
     }
     for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
         IncRec r;
         uint64_t coef;
         load_record(P, row, deg, c0, lane, r, coef);
         int e;
-        const uint64_t prod = record_product(P, z, r, coef, e);
+        const Acc prod = record_product<Acc>(P, z, r, coef, e);
 #pragma unroll
-        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : 0ull;
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
     }
     C.a[0] = 0;
 #pragma unroll
-    for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? wave_sum_u64(part[m]) : 0ull;
+    for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? wave_sum<Acc>(part[m]) : (Acc)0;
 }
 
 // dE(v) = sum_m a^(m) (v^m - z_k^m)  (Sec. 3.2)
-template <int kMaxE>
-__device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE> &C, int64_t zk, int64_t v) {
-    uint64_t d = C.a[1] * (uint64_t)(v - zk), vp = (uint64_t)v, zp = (uint64_t)zk;
+template <int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE, Acc> &C, int64_t zk, int64_t v) {
+    Acc d = C.a[1] * (Acc)(v - zk), vp = (Acc)v, zp = (Acc)zk;
 #pragma unroll
     for (int m = 2; m <= kMaxE; ++m) {
-        vp *= (uint64_t)v;
-        zp *= (uint64_t)zk;
+        vp *= (Acc)v;
+        zp *= (Acc)zk;
         d += C.a[m] * (vp - zp);
     }
-    return (int64_t)d;
+    return to_i64<Acc>(d);
 }
 
 // dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
+template <typename Acc>
 __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const int32_t *z, int32_t row,
                                                 int32_t deg, int64_t zk, int64_t v, int lane,
                                                 const IncRec &r0, uint64_t coef0) {
     int e;
-    uint64_t prod = record_product(P, z, r0, coef0, e);
-    uint64_t acc = prod * (upow((uint64_t)v, e) - upow((uint64_t)zk, e));
+    Acc prod = record_product<Acc>(P, z, r0, coef0, e);
+    Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
     for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
         IncRec r;
         uint64_t coef;
         load_record(P, row, deg, c0, lane, r, coef);
-        prod = record_product(P, z, r, coef, e);
-        acc += prod * (upow((uint64_t)v, e) - upow((uint64_t)zk, e));
+        prod = record_product<Acc>(P, z, r, coef, e);
+        acc += prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
     }
-    return (int64_t)wave_sum_u64(acc);
+    return to_i64<Acc>(wave_sum<Acc>(acc));
 }
 
 // Metropolis acceptance min[1, exp(-dE/T)] (Sec. 3.3.1), T = 1/beta; U in [0,1).
@@ -262,8 +291,8 @@ __device__ __forceinline__ bool metropolis_accept(int64_t d, double beta, double
 // range belongs to lane j / c (c = ceil(W/64)); lane sums are left to right; the lanes' sums are
 // combined by a Kogge-Stone inclusive scan (strides 1..32); the first value whose cumulative weight
 // exceeds U * total is drawn (the last value if rounding leaves none).
-template <int kRegChunk, int kMaxE>
-__device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_t lo, int64_t W,
+template <int kRegChunk, int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
                                                   int64_t zk, double beta, double U, int lane) {
     const int64_t c = (W + kWave - 1) / kWave;
     const int64_t j0 = (int64_t)lane * c;
@@ -271,8 +300,8 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
     int64_t dmin;
     if (kMaxE == 1) {
         // dE(v) = a1 (v - z_k) is linear: its minimum over [lo, hi] is at an end of the range
-        const int64_t a1 = (int64_t)C.a[1];
-        dmin = (int64_t)(C.a[1] * (uint64_t)((a1 >= 0 ? lo : lo + W - 1) - zk));
+        const int64_t a1 = to_i64<Acc>(C.a[1]);
+        dmin = to_i64<Acc>(C.a[1] * (Acc)((a1 >= 0 ? lo : lo + W - 1) - zk));
     } else {
         dmin = INT64_MAX;
         for (int64_t i = 0; i < c; ++i) {
@@ -284,6 +313,13 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
         }
         dmin = wave_min_i64(dmin);
     }
+    // exp(-beta * (dE - dmin)); in 32-bit mode the difference is formed in 32 bits (it fits)
+    auto weight = [&](int64_t j) -> double {
+        const int64_t d = poly_delta(C, zk, lo + j);
+        const double x = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)d - (uint32_t)dmin)
+                                          : (double)(d - dmin);
+        return exp(-(beta * x));
+    };
 
     double w[kRegChunk > 0 ? kRegChunk : 1];
     double lane_sum = 0.0;
@@ -292,8 +328,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
         for (int i = 0; i < (kRegChunk > 0 ? kRegChunk : 1); ++i) {
             if (i < c) {
                 const int64_t j = j0 + i;
-                double wi = 0.0;
-                if (j < W) wi = exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
+                const double wi = j < W ? weight(j) : 0.0;
                 w[i] = wi;
                 lane_sum += wi;
             }
@@ -301,7 +336,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
     } else {
         for (int64_t i = 0; i < c; ++i) {
             const int64_t j = j0 + i;
-            if (j < W) lane_sum += exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
+            if (j < W) lane_sum += weight(j);
         }
     }
     // Kogge-Stone inclusive scan, strides 1, 2, 4, 8, 16, 32: incl_l += incl_(l-d) for l >= d
@@ -335,7 +370,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
         for (int64_t i = 0; i < c; ++i) {
             const int64_t j = j0 + i;
             if (j < W) {
-                run += exp(-(beta * (double)(poly_delta(C, zk, lo + j) - dmin)));
+                run += weight(j);
                 if (before + run > thr) {
                     hit = (int32_t)i;
                     break;
@@ -350,8 +385,8 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE> &C, int64_
 }
 
 // Optimal transition (Sec. 3.3.3): the nonzero change of smallest dE, ties to the smallest value.
-template <int kMaxE>
-__device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE> &C, int64_t lo, int64_t W,
+template <int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
                                                   int64_t zk, int lane, int64_t &dbest) {
     int64_t best = INT64_MAX;
     int32_t bv = INT32_MAX;
@@ -382,8 +417,8 @@ __device__ __forceinline__ void window_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE>
-__global__ void __launch_bounds__(256) anneal_kernel(AnnealArgs A) {
+template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc>
+__global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
     extern __shared__ int32_t lds_state[];
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
@@ -473,23 +508,23 @@ __global__ void __launch_bounds__(256) anneal_kernel(AnnealArgs A) {
                     if (kRule == SA_METROPOLIS) {
                         v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                         if (v >= zk) v += 1;
-                        d = direct_delta(P, z, row, deg, zk, v, lane, crec, ccoef);
+                        d = direct_delta<Acc>(P, z, row, deg, zk, v, lane, crec, ccoef);
                         accept = metropolis_accept(d, beta, U);
                     } else if (kRule == SA_HEAT_BATH) {
-                        Coeffs<kMaxE> C;
-                        row_coeffs<kMaxE>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
-                        v = heat_bath_pick<kRegChunk, kMaxE>(C, lo, W, zk, beta, U, lane);
+                        Coeffs<kMaxE, Acc> C;
+                        row_coeffs<kMaxE, Acc>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                        v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane);
                         d = poly_delta(C, zk, v);
                         accept = true;
                     } else {
                         if ((double)r0 * 0x1p-32 < r_opt) {
-                            Coeffs<kMaxE> C;
-                            row_coeffs<kMaxE>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
-                            v = argmin_nonzero<kMaxE>(C, lo, W, zk, lane, d);
+                            Coeffs<kMaxE, Acc> C;
+                            row_coeffs<kMaxE, Acc>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                            v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;
-                            d = direct_delta(P, z, row, deg, zk, v, lane, crec, ccoef);
+                            d = direct_delta<Acc>(P, z, row, deg, zk, v, lane, crec, ccoef);
                         }
                         accept = metropolis_accept(d, beta, U);
                     }
@@ -542,37 +577,43 @@ using KernelFn = void (*)(AnnealArgs);
 
 // Heat bath: the weights of ceil(W/64) <= kRegChunk values per lane stay in registers (the
 // unrolled loops then cost kRegChunk steps); wider ranges recompute them (kRegChunk = 0).
-template <int kMaxE>
+template <int kMaxE, typename Acc>
 KernelFn pick_heat_bath_lds(int reg_chunk) {
     switch (reg_chunk) {
-        case 1: return anneal_kernel<SA_HEAT_BATH, true, 1, kMaxE>;
-        case 2: return anneal_kernel<SA_HEAT_BATH, true, 2, kMaxE>;
-        case 8: return anneal_kernel<SA_HEAT_BATH, true, 8, kMaxE>;
-        case 32: return anneal_kernel<SA_HEAT_BATH, true, 32, kMaxE>;
-        default: return anneal_kernel<SA_HEAT_BATH, true, 0, kMaxE>;
+        case 1: return anneal_kernel<SA_HEAT_BATH, true, 1, kMaxE, Acc>;
+        case 2: return anneal_kernel<SA_HEAT_BATH, true, 2, kMaxE, Acc>;
+        case 8: return anneal_kernel<SA_HEAT_BATH, true, 8, kMaxE, Acc>;
+        case 32: return anneal_kernel<SA_HEAT_BATH, true, 32, kMaxE, Acc>;
+        default: return anneal_kernel<SA_HEAT_BATH, true, 0, kMaxE, Acc>;
     }
 }
 
-// Kernel variants: rule x exponent class x (heat bath) register chunk, for states in LDS; states
-// in device memory (very large N) use one generic variant per rule.
-KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class) {
-    if (rule == SA_METROPOLIS)
-        return in_lds ? anneal_kernel<SA_METROPOLIS, true, 0, 1> : anneal_kernel<SA_METROPOLIS, false, 0, 1>;
+// Kernel variants: rule x exponent class x (heat bath) register chunk x integer width, for states
+// in LDS; 32-bit arithmetic is instantiated for the quadratic classes (QUIO).  States in device
+// memory (very large N) use one generic 64-bit variant per rule.
+KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool narrow) {
+    if (rule == SA_METROPOLIS) {
+        if (!in_lds) return anneal_kernel<SA_METROPOLIS, false, 0, 1, uint64_t>;
+        return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t>
+                      : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t>;
+    }
     if (rule == SA_HEAT_BATH) {
-        if (!in_lds) return anneal_kernel<SA_HEAT_BATH, false, 0, kMaxExpPoly>;
+        if (!in_lds) return anneal_kernel<SA_HEAT_BATH, false, 0, kMaxExpPoly, uint64_t>;
         switch (maxe_class) {
-            case 1: return pick_heat_bath_lds<1>(reg_chunk);
-            case 2: return pick_heat_bath_lds<2>(reg_chunk);
-            case 4: return pick_heat_bath_lds<4>(reg_chunk);
-            default: return pick_heat_bath_lds<kMaxExpPoly>(reg_chunk);
+            case 1: return narrow ? pick_heat_bath_lds<1, uint32_t>(reg_chunk) : pick_heat_bath_lds<1, uint64_t>(reg_chunk);
+            case 2: return narrow ? pick_heat_bath_lds<2, uint32_t>(reg_chunk) : pick_heat_bath_lds<2, uint64_t>(reg_chunk);
+            case 4: return pick_heat_bath_lds<4, uint64_t>(reg_chunk);
+            default: return pick_heat_bath_lds<kMaxExpPoly, uint64_t>(reg_chunk);
         }
     }
     if (rule == SA_OPT_METROPOLIS) {
-        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 0, 4>;
+        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 0, 4, uint64_t>;
         switch (maxe_class) {
-            case 1: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1>;
-            case 2: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2>;
-            default: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 4>;
+            case 1: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t>
+                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t>;
+            case 2: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint32_t>
+                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint64_t>;
+            default: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 4, uint64_t>;
         }
     }
     return nullptr;
@@ -592,7 +633,7 @@ int64_t shared_state_bytes(int32_t n, int G) {
 }
 
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device, int win_waves) {
+                           int device, int win_waves, bool narrow_ok) {
     LaunchChoice lc;
     int cus = 256, max_lds = 65536;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -623,13 +664,14 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     lc.maxe_class = lc.state_in_lds ? maxe_class_of(max_exp)
                                     : (rule == SA_HEAT_BATH ? kMaxExpPoly : rule == SA_OPT_METROPOLIS ? 4 : 1);
     lc.reg_chunk = reg;
-    lc.variant = rule * 10000 + lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
+    lc.narrow = narrow_ok && lc.state_in_lds && lc.maxe_class <= 2;
+    lc.variant = rule * 100000 + (lc.narrow ? 10000 : 0) + lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
     return lc;
 }
 
 int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
                   std::string &err) {
-    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class);
+    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class, lc.narrow);
     if (!fn) {
         err = "unknown rule";
         return SA_EINVAL;
