@@ -32,7 +32,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis"])
+    ap.add_argument("--config", default="cfg2",
+                    choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis", "cfg4"])
+    ap.add_argument("--plain-sample", type=int, default=48,
+                    help="cfg4: problems timed with plain per-instance launches")
     ap.add_argument("--sweeps", type=int, default=0, help="override the number of sweeps")
     ap.add_argument("--reads", type=int, default=0, help="override the number of reads")
     ap.add_argument("--waves-per-replica", type=int, default=0,
@@ -77,6 +80,78 @@ def cpu_baseline(w, beta, n_reads, n_sweeps):
                       f"({upd:.3g} updates, {dt:.1f} s, coefficient-cache mode)"}
 
 
+def bench_batch(args):
+    """512 problems of uneven size, width, order and rule in one persistent (graph-replayed)
+    launch, against plain per-instance launches of a seeded sample of the same problems."""
+    import numpy as np
+    import torch
+    from paper_2511_17245_amd import inputs as I
+    from paper_2511_17245_amd import sa
+
+    items = I.cfg4_batch()
+    if args.sweeps:
+        for w in items:
+            w.n_sweeps = args.sweeps
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        batch = sa.Batch(items, autotune=True, use_graph=True, stream=stream.cuda_stream)
+        create_s = time.perf_counter() - t0
+        info = batch.info()
+        for _ in range(args.warmup):
+            batch.run()
+        batch.wait()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for i in range(args.steps):
+            batch.run()
+            print(f"[bench] queued batch {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+        stop.record(stream)
+        stream.synchronize()
+        ms = start.elapsed_time(stop) / args.steps
+        batched = batch.results()
+        value = info["total_updates"] / (ms / 1e3)
+
+        # plain launches, one problem at a time, on a seeded sample
+        rng = np.random.Generator(np.random.PCG64(4242))
+        sample = np.sort(rng.choice(len(items), size=min(args.plain_sample, len(items)), replace=False))
+        plain_ms, plain_upd, same = 0.0, 0, True
+        for i in sample:
+            w = items[i]
+            plan = sa.Plan(w.problem, w.rule)
+            z = torch.empty((w.n_reads, w.problem.n_vars), dtype=torch.int32, device="cuda")
+            e = torch.empty(w.n_reads, dtype=torch.int64, device="cuda")
+            beta = w.beta if w.beta is not None else sa.auto_schedule(w.problem, w.n_sweeps)
+            plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
+                            instance_id=w.instance_id)   # stages beta; not timed
+            stream.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
+                            instance_id=w.instance_id)
+            b.record(stream)
+            stream.synchronize()
+            plain_ms += a.elapsed_time(b)
+            plain_upd += w.n_reads * w.n_sweeps * w.problem.n_vars
+            same = same and np.array_equal(z.cpu().numpy(), batched[i][0]) and \
+                np.array_equal(e.cpu().numpy(), batched[i][1])
+            plan.close()
+        plain = plain_upd / (plain_ms / 1e3)
+    out = {
+        "metric": "single-variable updates/sec at 1 GPU (batched form)",
+        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": "512 mixed QUIO/HUIO problems, N 50-5000, widths 2-1000, 32 reads, 1000 sweeps, "
+                               "one persistent graph-replayed launch", "batch": info,
+                   "create_s": create_s},
+        "plain": {"value": plain, "unit": "updates/s", "sample_problems": int(len(sample)),
+                  "sample_ms": plain_ms, "identical_outputs": bool(same)},
+        "batched_over_plain": value / plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -89,6 +164,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.config == "cfg4":
+        return bench_batch(args)
     w = workload(args)
     prob = w.problem
     n, S, R = prob.n_vars, w.n_sweeps, w.n_reads

@@ -147,6 +147,73 @@ typedef struct {
 } sa_launch_info;
 int32_t sa_plan_last_launch(const sa_plan *plan, sa_launch_info *info);
 
+/* ---- batches: many instances annealed by one persistent launch ------------------------------
+ * Every problem keeps its own rule, schedule, read count, seed and instance id, and its results
+ * are identical to sa_anneal_ex of that problem alone (same Philox counters, exact arithmetic).
+ * One kernel launch runs all (problem, read) replicas: each workgroup of 8 wavefronts takes the
+ * next task from a device counter, longest first; a task is 8/G consecutive reads of one problem,
+ * each annealed by G cooperating wavefronts (G = 1, 2, 4 or 8 per problem, larger for the
+ * problems on the critical path) with its state in LDS.  Every problem's N must fit LDS
+ * (N <= 40960 on MI355X); otherwise creation fails with SA_EUNSUPPORTED. */
+typedef struct {
+    sa_instance inst;
+    sa_bounds bounds;
+    sa_schedule sched;          /* beta == NULL: automatic schedule of this problem */
+    int32_t rule;
+    int32_t n_reads;
+    uint64_t seed;
+    uint32_t instance_id;
+} sa_problem;
+
+typedef struct {
+    int32_t *states;            /* host int32[n_reads * N] (caller-allocated) */
+    int64_t *energies;          /* host int64[n_reads] */
+    int32_t status;             /* written by sa_batch_results / sa_anneal_batch */
+} sa_result;
+
+typedef struct {
+    int32_t autotune;           /* 1: time candidate launch geometries once and keep the fastest
+                                   (cached per batch shape within the process) */
+    int32_t use_graph;          /* 1: the launch is captured once into a HIP graph and replayed */
+    void *hip_stream;           /* stream of sa_batch_run (NULL: the batch creates its own) */
+    int32_t waves_per_group;    /* 0 or 8 (the batch kernel's workgroup size in wavefronts) */
+    int32_t groups;             /* 0: automatic / tuned; else the persistent workgroup count */
+} sa_batch_opts;
+
+typedef struct sa_batch sa_batch;
+
+/* Validates, canonicalises and uploads every problem, then (optionally) tunes and captures the
+ * launch.  Problems are copied; the caller's arrays may be freed after the call. */
+int32_t sa_batch_create(const sa_problem *problems, int32_t n_problems, const sa_batch_opts *opts,
+                        sa_batch **out);
+/* Queues one complete annealing of every problem on the batch's stream (asynchronous). */
+int32_t sa_batch_run(sa_batch *batch);
+/* Waits for the queued work of the batch. */
+int32_t sa_batch_wait(sa_batch *batch);
+/* Waits, then copies every problem's final states and energies to results[i]. */
+int32_t sa_batch_results(sa_batch *batch, sa_result *results);
+typedef struct {
+    int32_t n_problems;
+    int64_t n_tasks;            /* replicas */
+    int64_t total_updates;      /* sum over problems of n_reads * n_sweeps * N */
+    int32_t waves_per_group;
+    int32_t groups;
+    int32_t slot_bytes;         /* dynamic LDS per workgroup */
+    int32_t kernel_maxe;        /* exponent class of the batch kernel */
+    int32_t kernel_bits;        /* 32 or 64: integer width of energy differences */
+    int32_t state_bits;         /* 16 or 32: width of the states held in LDS */
+    int32_t graph;              /* 1 if replayed from a HIP graph */
+    int32_t max_team;           /* largest number of wavefronts cooperating on one replica */
+    double policy;              /* team-size policy strength in use (0: one wavefront per replica) */
+    double tune_ms;             /* time spent in tuning trials */
+} sa_batch_info;
+int32_t sa_batch_get_info(const sa_batch *batch, sa_batch_info *info);
+void sa_batch_destroy(sa_batch *batch);
+
+/* One-shot form: create, run, copy the results, destroy. */
+int32_t sa_anneal_batch(const sa_problem *problems, int32_t n_problems, sa_result *results,
+                        const sa_batch_opts *opts);
+
 /* ---- utilities -------------------------------------------------------------------------------- */
 /* The automatic schedule of Sec. 3.4 (host arithmetic): beta_out[0..n_sweeps-1]. */
 int32_t sa_auto_schedule(const sa_instance *inst, const sa_bounds *bounds, int32_t n_sweeps,

@@ -9,11 +9,13 @@
 #include <string>
 #include <vector>
 
-#include "sa_internal.h"
+#include "sa_plan.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace sa {
 
 int fail(int code, const std::string &msg) {
     g_last_error = msg;
@@ -24,49 +26,11 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(SA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// One device allocation holding several arrays, each 256-byte aligned.
-struct DevArena {
-    void *base = nullptr;
-    size_t bytes = 0;
-    ~DevArena() {
-        if (base) (void)hipFree(base);
-    }
-};
+}  // namespace sa
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-}  // namespace
-
-struct sa_plan {
-    int device = 0;
-    int rule = 0;
-    sa::DevProblem dp{};
-    DevArena arena;
-    sa_plan_info info{};
-    sa_launch_info last{};
-    std::vector<int32_t> lo, hi;  // host copy of the box (checks of host start states)
-    bool narrow_ok = false;       // every |dE| < 2^30: 32-bit integer kernels are exact
-    double t_init = 0.0, t_final = 0.0;
-    int auto_status = SA_OK;
-    std::string auto_error;
-    // device copy of the last schedule, reused while the schedule is unchanged
-    double *beta_dev = nullptr;
-    int32_t beta_cap = 0;
-    std::vector<double> beta_host;
-    // host packing (kept to build sweep schedules) and the device schedules built so far, by G
-    sa::Packed packed;
-    struct Sched {
-        sa::SchedRec *dev = nullptr;
-        int32_t n_win = 0;
-        int32_t n_active = 0;  // variables that are not fixed
-    };
-    Sched sched[9];
-    ~sa_plan() {
-        if (beta_dev) (void)hipFree(beta_dev);
-        for (auto &sc : sched)
-            if (sc.dev) (void)hipFree(sc.dev);
-    }
-};
+using sa::align256;
+using sa::fail;
+using sa::hip_fail;
 
 namespace {
 
@@ -124,6 +88,10 @@ int check_rule_support(int rule, int32_t max_exp) {
         return fail(SA_EUNSUPPORTED, "heat bath supports exponents up to 16 on the GPU");
     return SA_OK;
 }
+
+}  // namespace
+
+namespace sa {
 
 int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, sa_plan **out) {
     if (!out) return fail(SA_EINVAL, "plan output pointer is NULL");
@@ -203,7 +171,6 @@ int stage_beta(sa_plan *plan, const std::vector<double> &beta, hipStream_t strea
     return SA_OK;
 }
 
-// The sweep schedule for G waves per replica (built on first use and kept on the device).
 int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out) {
     sa_plan::Sched &sc = plan->sched[G];
     if (!sc.dev) {
@@ -228,13 +195,26 @@ int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out) {
     return SA_OK;
 }
 
+int reg_chunk_class(int32_t max_width) {
+    const int64_t chunk = ((int64_t)max_width + 63) / 64;
+    return chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0;
+}
+
+}  // namespace sa
+
+namespace {
+
+using sa::get_schedule;
+using sa::stage_beta;
+using sa::resolve_schedule;
+
 // Waves per replica.  The sweep is latency-bound (one dependent chain per replica), so the widest
 // window G in {8, 4, 2} is taken whose waves stay busy (mean window size >= 0.6 G), whose shared
 // state fits in LDS and which keeps at most 8 waves per SIMD in flight; otherwise G = 1.
 int auto_waves_per_replica(sa_plan *plan, int32_t n_reads, int device) {
     int cus = 256, max_lds = 65536;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     const int64_t max_waves = (int64_t)cus * 4 * 8;
     for (int G = 8; G > 1; G /= 2) {
         if ((int64_t)n_reads * G > max_waves) continue;
@@ -368,7 +348,7 @@ void sa_opts_default(sa_opts *opts) {
 int32_t sa_plan_create(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, sa_plan **out) {
     g_last_error.clear();
     try {
-        return build_plan(inst, bounds, rule, out);
+        return sa::build_plan(inst, bounds, rule, out);
     } catch (const std::bad_alloc &) {
         return fail(SA_ENOMEM, "host allocation failed");
     } catch (const std::exception &ex) {

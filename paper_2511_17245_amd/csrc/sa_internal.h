@@ -70,6 +70,7 @@ struct Packed {
     int32_t max_width = 1;
 };
 int pack(const Canonical &c, Packed &out, std::string &err);
+int maxe_class_of(int32_t max_exp);
 
 // One slot of the sweep schedule: in window w, wave g of a replica updates variable k (k = -1:
 // the wave idles in that window).  Variables of one window share no term, so their updates
@@ -138,6 +139,48 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
                            int device, int win_waves, bool narrow_ok);
 // LDS bytes of one replica's state when its G waves share it (state + per-wave energy slots).
 int64_t shared_state_bytes(int32_t n, int G);
+// Waves of one batch workgroup; a task runs kBatchWaves / G_p reads of problem p.
+constexpr int kBatchWaves = 8;
+
+// One problem of a batch as the persistent kernel sees it.
+struct BatchInst {
+    DevProblem P;
+    const double *beta;      // S inverse temperatures (device)
+    const SchedRec *sched;   // schedule for `team` waves per replica
+    int32_t n_win;
+    int32_t team;            // G_p: waves per replica (1, 2, 4 or 8)
+    int32_t slot_stride;     // state elements between the teams' LDS slots
+    int32_t n_reads;
+    int32_t n_sweeps;
+    int32_t rule;
+    int32_t chunk;           // heat bath: register chunk class (1, 2, 8; 0 = recompute)
+    uint32_t key0, key1, instance_id;
+    int32_t *z_out;          // n_reads x n (device)
+    int64_t *e_out;          // n_reads (device)
+};
+struct BatchTask {
+    int32_t inst;
+    int32_t read;            // first read of the task (kBatchWaves / G_p reads)
+};
+struct BatchArgs {
+    const BatchInst *insts;
+    const BatchTask *tasks;  // ordered longest first
+    int32_t n_tasks;
+    uint32_t *counter;       // next task (device)
+    int32_t lds_words;       // dynamic LDS of a workgroup, 32-bit words
+    int32_t parts_words;     // offset of the waves' energy parts (kBatchWaves int64)
+    int32_t sweep_limit;     // > 0: only the first sweep_limit sweeps (autotuning trials)
+};
+struct BatchLaunch {
+    int waves_per_group = kBatchWaves;
+    int groups = 1;
+    int maxe_class = 1;
+    bool narrow = false;
+    bool z16 = false;        // states held as int16 in LDS (every bound within int16)
+};
+// Queues the counter reset and the persistent kernel (both plain kernel launches).
+int launch_batch(const BatchArgs &b, const BatchLaunch &bl, void *stream, std::string &err);
+
 // Energies of n_states device-resident states (one wavefront per state).
 int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, int64_t *out,
                   void *stream, std::string &err);

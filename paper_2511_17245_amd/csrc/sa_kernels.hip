@@ -52,9 +52,6 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
 __device__ __forceinline__ uint32_t uni32(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
-}
 __device__ __forceinline__ uint32_t lane_read32(uint32_t x, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
@@ -184,8 +181,8 @@ __device__ __forceinline__ Acc upow(Acc x, int e) {
 // J_t times the product of the term's other factors, for one incidence record of the row being
 // visited.  Sets e to the exponent of the visited variable in the term.  A zero record (meta = 0,
 // coef = 0) contributes nothing, so lanes beyond the row hold one.
-template <typename Acc>
-__device__ __forceinline__ Acc record_product(const DevProblem &P, const int32_t *z, const IncRec &r,
+template <typename Acc, typename ZT>
+__device__ __forceinline__ Acc record_product(const DevProblem &P, const ZT *z, const IncRec &r,
                                               uint64_t coef, int &e) {
     e = (int)(r.meta & 0xFFu);
     const int no = (int)(r.meta >> 8);
@@ -223,8 +220,8 @@ struct Coeffs {
     Acc a[kMaxE + 1];
 };
 
-template <int kMaxE, typename Acc>
-__device__ __forceinline__ void row_coeffs(const DevProblem &P, const int32_t *z, int32_t row,
+template <int kMaxE, typename Acc, typename ZT>
+__device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int32_t row,
                                            int32_t deg, uint32_t emask, int lane, const IncRec &r0,
                                            uint64_t coef0, Coeffs<kMaxE, Acc> &C) {
     Acc part[kMaxE + 1];
@@ -232,7 +229,7 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const int32_t *z
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
     {
         int e;
-        const Acc prod = record_product<Acc>(P, z, r0, coef0, e);
+        const Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
 #pragma unroll
         for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
     }
@@ -241,7 +238,7 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const int32_t *z
         uint64_t coef;
         load_record(P, row, deg, c0, lane, r, coef);
         int e;
-        const Acc prod = record_product<Acc>(P, z, r, coef, e);
+        const Acc prod = record_product<Acc, ZT>(P, z, r, coef, e);
 #pragma unroll
         for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
     }
@@ -264,18 +261,18 @@ __device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE, Acc> &C, int64
 }
 
 // dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
-template <typename Acc>
-__device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const int32_t *z, int32_t row,
+template <typename Acc, typename ZT>
+__device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z, int32_t row,
                                                 int32_t deg, int64_t zk, int64_t v, int lane,
                                                 const IncRec &r0, uint64_t coef0) {
     int e;
-    Acc prod = record_product<Acc>(P, z, r0, coef0, e);
+    Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
     Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
     for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
         IncRec r;
         uint64_t coef;
         load_record(P, row, deg, c0, lane, r, coef);
-        prod = record_product<Acc>(P, z, r, coef, e);
+        prod = record_product<Acc, ZT>(P, z, r, coef, e);
         acc += prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
     }
     return to_i64<Acc>(wave_sum<Acc>(acc));
@@ -417,54 +414,67 @@ __device__ __forceinline__ void window_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc>
-__global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
-    extern __shared__ int32_t lds_state[];
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    const int wave = (int)(threadIdx.x / kWave);
-    const int G = A.win_waves;
-    const bool shared = G > 1;
-    const int read = shared ? (int)blockIdx.x : (int)blockIdx.x * A.waves_per_group + wave;
-    const int g = shared ? wave : 0;
-    if (read >= A.n_reads) return;  // uniform over the replica's waves; no barrier is skipped
-    const DevProblem &P = A.P;
-    const int32_t n = P.n;
-    int32_t *z = kStateInLds ? lds_state + (shared ? 0 : (size_t)wave * n) : A.z_out + (size_t)read * n;
-    const uint32_t rd = (uint32_t)read;
-    const int tid = g * kWave + lane, nthr = G * kWave;  // threads of this replica
+// What one replica's sweeps need (shared by the plain and the batched kernels).
+struct ReplicaCtx {
+    DevProblem P;
+    const double *beta;
+    int32_t n_sweeps, s_begin, s_end;
+    uint32_t key0, key1, instance_id, read;
+    double otm_r;
+    const SchedRec *sched;  // this wave's schedule slots (window-major for one wave)
+    int32_t n_win;
+    bool shared;            // the replica's waves cooperate (barrier after each window)
+    bool active;            // false: an idle team that only keeps the workgroup's barriers
+};
 
-    // initial state: given (resume) or uniform on each box (Sec. 3.1)
-    if (A.z_init) {
-        const int32_t *zi = A.z_init + (size_t)read * n;
-        if (zi != z)
-            for (int32_t k = tid; k < n; k += nthr) z[k] = zi[k];
+// Initial state (given, or uniform on each box, Sec. 3.1) written by threads tid, tid+nthr, ...
+template <typename ZT>
+__device__ __forceinline__ void init_state(const DevProblem &P, ZT *z, const int32_t *zi, uint32_t read,
+                                           uint32_t inst, uint32_t key0, uint32_t key1, int tid, int nthr) {
+    const int32_t n = P.n;
+    if (zi) {
+        if ((const void *)zi != (const void *)z)
+            for (int32_t k = tid; k < n; k += nthr) z[k] = (ZT)zi[k];
     } else {
         for (int32_t k = tid; k < n; k += nthr) {
-            uint32_t x0 = (uint32_t)k, x1 = 0xFFFFFFFFu, x2 = rd, x3 = A.instance_id;
-            philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+            uint32_t x0 = (uint32_t)k, x1 = 0xFFFFFFFFu, x2 = read, x3 = inst;
+            philox4x32_10(x0, x1, x2, x3, key0, key1);
             const VarRec vr = P.var[k];
-            z[k] = vr.lo + (int32_t)(((uint64_t)x0 * (uint64_t)(uint32_t)vr.width) >> 32);
+            z[k] = (ZT)(vr.lo + (int32_t)(((uint64_t)x0 * (uint64_t)(uint32_t)vr.width) >> 32));
         }
     }
-    if (shared) window_barrier();
-    else state_write_fence<kStateInLds>();
+}
 
-    // E(z) = sum_t J_t prod z (term-major, the replica's threads split the terms); each wave keeps
-    // its partial sum plus the energy changes of its own updates
+// This wave's share of E(z) = sum_t J_t prod z (threads tid, tid+nthr, ... take the terms).
+template <typename ZT>
+__device__ __forceinline__ int64_t energy_part(const DevProblem &P, const ZT *z, int tid, int nthr) {
     uint64_t eacc = 0;
     for (int32_t t = tid; t < P.n_terms; t += nthr) {
         uint64_t prod = (uint64_t)P.t_coef[t];
         for (int32_t f = P.t_off[t]; f < P.t_off[t + 1]; ++f) prod *= (uint64_t)(int64_t)z[P.t_var[f]];
         eacc += prod;
     }
-    int64_t E = (int64_t)wave_sum_u64(eacc);
+    return (int64_t)wave_sum_u64(eacc);
+}
 
-    const int32_t n_win = A.n_win;
-    const SchedRec *mine = A.sched + (size_t)g * n_win;
-    for (int32_t s = A.s_begin; s < A.s_end; ++s) {
-        const double beta = A.beta[s];
+// Sweeps [s_begin, s_end) of one replica (index order, Sec. 3.1): this wave's slots of the
+// schedule.  Returns the sum of the energy changes this wave applied.
+template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc, typename ZT>
+__device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int lane) {
+    const DevProblem &P = R.P;
+    const int32_t n_win = R.n_win;
+    const SchedRec *mine = R.sched;
+    int64_t E = 0;
+    if (!R.active) {
+        if (R.shared)
+            for (int32_t s = R.s_begin; s < R.s_end; ++s)
+                for (int32_t w = 0; w < n_win; ++w) window_barrier();
+        return 0;
+    }
+    for (int32_t s = R.s_begin; s < R.s_end; ++s) {
+        const double beta = R.beta[s];
         const double r_opt =
-            A.otm_r >= 0.0 ? A.otm_r : (A.n_sweeps > 1 ? (double)s / (double)(A.n_sweeps - 1) : 0.0);
+            R.otm_r >= 0.0 ? R.otm_r : (R.n_sweeps > 1 ? (double)s / (double)(R.n_sweeps - 1) : 0.0);
         for (int32_t wb = 0; wb < n_win; wb += kWave) {
             // per block of 64 windows: lane j holds this wave's slot of window wb+j and its draws
             const int32_t wl = wb + lane;
@@ -479,8 +489,8 @@ __global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
                 sl.deg = 0;
                 sl.emask = 0;
             }
-            uint32_t x0 = (uint32_t)sl.k, x1 = (uint32_t)s, x2 = rd, x3 = A.instance_id;
-            philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+            uint32_t x0 = (uint32_t)sl.k, x1 = (uint32_t)s, x2 = R.read, x3 = R.instance_id;
+            philox4x32_10(x0, x1, x2, x3, R.key0, R.key1);
             const int32_t wend = n_win - wb < kWave ? n_win - wb : kWave;
             // first chunk of the next slot's incidence records, loaded one window ahead
             IncRec nrec;
@@ -508,36 +518,79 @@ __global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
                     if (kRule == SA_METROPOLIS) {
                         v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                         if (v >= zk) v += 1;
-                        d = direct_delta<Acc>(P, z, row, deg, zk, v, lane, crec, ccoef);
+                        d = direct_delta<Acc, ZT>(P, z, row, deg, zk, v, lane, crec, ccoef);
                         accept = metropolis_accept(d, beta, U);
                     } else if (kRule == SA_HEAT_BATH) {
                         Coeffs<kMaxE, Acc> C;
-                        row_coeffs<kMaxE, Acc>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                        row_coeffs<kMaxE, Acc, ZT>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
                         v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane);
                         d = poly_delta(C, zk, v);
                         accept = true;
                     } else {
                         if ((double)r0 * 0x1p-32 < r_opt) {
                             Coeffs<kMaxE, Acc> C;
-                            row_coeffs<kMaxE, Acc>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                            row_coeffs<kMaxE, Acc, ZT>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
                             v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;
-                            d = direct_delta<Acc>(P, z, row, deg, zk, v, lane, crec, ccoef);
+                            d = direct_delta<Acc, ZT>(P, z, row, deg, zk, v, lane, crec, ccoef);
                         }
                         accept = metropolis_accept(d, beta, U);
                     }
                     if (accept && v != zk) {
-                        z[k] = (int32_t)v;  // every lane stores the same value
+                        z[k] = (ZT)v;  // every lane stores the same value
                         E += d;
-                        if (!shared) state_write_fence<kStateInLds>();
+                        if (!R.shared) state_write_fence<kStateInLds>();
                     }
                 }
-                if (shared) window_barrier();
+                if (R.shared) window_barrier();
             }
         }
     }
+    return E;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Plain launch: one instance, n_reads replicas.
+// ------------------------------------------------------------------------------------------------
+template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc>
+__global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
+    extern __shared__ int32_t lds_state[];
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    const int G = A.win_waves;
+    const bool shared = G > 1;
+    const int read = shared ? (int)blockIdx.x : (int)blockIdx.x * A.waves_per_group + wave;
+    const int g = shared ? wave : 0;
+    if (read >= A.n_reads) return;  // uniform over the replica's waves; no barrier is skipped
+    const DevProblem &P = A.P;
+    const int32_t n = P.n;
+    int32_t *z = kStateInLds ? lds_state + (shared ? 0 : (size_t)wave * n) : A.z_out + (size_t)read * n;
+    const int tid = g * kWave + lane, nthr = G * kWave;  // threads of this replica
+
+    init_state(P, z, A.z_init ? A.z_init + (size_t)read * n : nullptr, (uint32_t)read, A.instance_id,
+               A.key0, A.key1, tid, nthr);
+    if (shared) window_barrier();
+    else state_write_fence<kStateInLds>();
+    int64_t E = energy_part(P, z, tid, nthr);
+
+    ReplicaCtx R;
+    R.P = P;
+    R.beta = A.beta;
+    R.n_sweeps = A.n_sweeps;
+    R.s_begin = A.s_begin;
+    R.s_end = A.s_end;
+    R.key0 = A.key0;
+    R.key1 = A.key1;
+    R.instance_id = A.instance_id;
+    R.read = (uint32_t)read;
+    R.otm_r = A.otm_r;
+    R.sched = A.sched + (size_t)g * A.n_win;
+    R.n_win = A.n_win;
+    R.shared = shared;
+    R.active = true;
+    E += sweep_replica<kRule, kStateInLds, kRegChunk, kMaxE, Acc, int32_t>(R, z, lane);
 
     if (shared) {
         // combine the waves' energy parts; LDS slots follow the state
@@ -554,6 +607,88 @@ __global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
         for (int32_t k = tid; k < n; k += nthr) zo[k] = z[k];
     }
     if (g == 0 && lane == 0) A.e_out[read] = E;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Batched launch: one persistent kernel anneals many problems.  A workgroup of kBatchWaves waves
+// repeatedly takes the next task from a global counter (tasks are ordered longest first).  A task
+// is kBatchWaves / G_p consecutive reads of one problem p: each read is annealed by a team of G_p
+// waves (G_p = 1: independent waves; G_p > 1: cooperating waves over the problem's window schedule,
+// as in the plain kernel).  Rule and heat-bath chunk class are dispatched per task; the exponent
+// class, integer width and state width are those of the whole batch.
+// ------------------------------------------------------------------------------------------------
+template <int kMaxE, typename Acc, typename ZT>
+__global__ void __launch_bounds__(kBatchWaves * 64) batch_kernel(BatchArgs B) {
+    extern __shared__ int32_t lds_state[];
+    __shared__ uint32_t task_slot;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    int64_t *parts = (int64_t *)(lds_state + B.parts_words);
+    constexpr int kOtmE = kMaxE < 4 ? kMaxE : 4;
+    for (;;) {
+        if (threadIdx.x == 0) task_slot = atomicAdd(B.counter, 1u);
+        window_barrier();
+        const uint32_t t = task_slot;
+        window_barrier();  // every wave has the task before the slot can change again
+        if (t >= (uint32_t)B.n_tasks) break;  // uniform over the workgroup
+        const BatchTask task = B.tasks[t];
+        const BatchInst &D = B.insts[task.inst];
+        const DevProblem P = D.P;
+        const int G = D.team;
+        const int team = wave / G, g = wave % G;
+        const int32_t read_i = task.read + team;
+        const bool active = read_i < D.n_reads;
+        const uint32_t read = (uint32_t)read_i;
+        ZT *z = (ZT *)lds_state + (size_t)team * D.slot_stride;
+        const int tid = g * kWave + lane, nthr = G * kWave;
+        if (active) init_state(P, z, nullptr, read, D.instance_id, D.key0, D.key1, tid, nthr);
+        window_barrier();
+        int64_t E = active ? energy_part(P, z, tid, nthr) : 0;
+        ReplicaCtx R;
+        R.P = P;
+        R.beta = D.beta;
+        R.n_sweeps = D.n_sweeps;
+        R.s_begin = 0;
+        R.s_end = B.sweep_limit > 0 && B.sweep_limit < D.n_sweeps ? B.sweep_limit : D.n_sweeps;
+        R.key0 = D.key0;
+        R.key1 = D.key1;
+        R.instance_id = D.instance_id;
+        R.read = read;
+        R.otm_r = -1.0;
+        R.sched = D.sched + (size_t)g * D.n_win;
+        R.n_win = D.n_win;
+        R.shared = G > 1;
+        R.active = active;
+        if (D.rule == SA_METROPOLIS) {
+            E += sweep_replica<SA_METROPOLIS, true, 0, 1, Acc, ZT>(R, z, lane);
+        } else if (D.rule == SA_HEAT_BATH) {
+            switch (D.chunk) {
+                case 1: E += sweep_replica<SA_HEAT_BATH, true, 1, kMaxE, Acc, ZT>(R, z, lane); break;
+                case 2: E += sweep_replica<SA_HEAT_BATH, true, 2, kMaxE, Acc, ZT>(R, z, lane); break;
+                case 8: E += sweep_replica<SA_HEAT_BATH, true, 8, kMaxE, Acc, ZT>(R, z, lane); break;
+                default: E += sweep_replica<SA_HEAT_BATH, true, 0, kMaxE, Acc, ZT>(R, z, lane); break;
+            }
+        } else {
+            E += sweep_replica<SA_OPT_METROPOLIS, true, 0, kOtmE, Acc, ZT>(R, z, lane);
+        }
+        if (lane == 0) parts[wave] = E;
+        window_barrier();
+        if (active) {
+            if (g == 0 && lane == 0) {
+                int64_t tot = 0;
+                for (int q = 0; q < G; ++q) tot += parts[team * G + q];
+                D.e_out[read] = tot;
+            }
+            int32_t *zo = D.z_out + (size_t)read * P.n;
+            for (int32_t k = tid; k < P.n; k += nthr) zo[k] = (int32_t)z[k];
+        }
+        window_barrier();  // the slots' last reads come before the next task's writes
+    }
+}
+
+// Sets the batch's task counter to zero (a kernel, so that graph replays stay plain kernel nodes).
+__global__ void reset_counter_kernel(uint32_t *counter) {
+    if (threadIdx.x == 0) *counter = 0u;
 }
 
 // Energies of stored states, one wavefront per state.
@@ -619,14 +754,15 @@ KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool 
     return nullptr;
 }
 
+
+}  // namespace
+
 int maxe_class_of(int32_t max_exp) {
     if (max_exp <= 1) return 1;
     if (max_exp <= 2) return 2;
     if (max_exp <= 4) return 4;
     return kMaxExpPoly;
 }
-
-}  // namespace
 
 int64_t shared_state_bytes(int32_t n, int G) {
     return (((int64_t)n + 1) & ~(int64_t)1) * (int64_t)sizeof(int32_t) + (int64_t)G * (int64_t)sizeof(int64_t);
@@ -636,8 +772,8 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
                            int device, int win_waves, bool narrow_ok) {
     LaunchChoice lc;
     int cus = 256, max_lds = 65536;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
     if (win_waves > 1 && shared_state_bytes(n, win_waves) <= max_lds) {
         // one replica per workgroup, its G waves share the state
@@ -703,6 +839,47 @@ int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return SA_EDEVICE;
+    }
+    return SA_OK;
+}
+
+}  // namespace sa
+
+namespace sa {
+
+int launch_batch(const BatchArgs &b, const BatchLaunch &bl, void *stream, std::string &err) {
+    using Fn = void (*)(BatchArgs);
+    Fn fn;
+    if (bl.z16) {
+        switch (bl.maxe_class) {
+            case 1: fn = bl.narrow ? batch_kernel<1, uint32_t, int16_t> : batch_kernel<1, uint64_t, int16_t>; break;
+            case 2: fn = bl.narrow ? batch_kernel<2, uint32_t, int16_t> : batch_kernel<2, uint64_t, int16_t>; break;
+            case 4: fn = batch_kernel<4, uint64_t, int16_t>; break;
+            default: fn = batch_kernel<kMaxExpPoly, uint64_t, int16_t>; break;
+        }
+    } else {
+        switch (bl.maxe_class) {
+            case 1: fn = bl.narrow ? batch_kernel<1, uint32_t, int32_t> : batch_kernel<1, uint64_t, int32_t>; break;
+            case 2: fn = bl.narrow ? batch_kernel<2, uint32_t, int32_t> : batch_kernel<2, uint64_t, int32_t>; break;
+            case 4: fn = batch_kernel<4, uint64_t, int32_t>; break;
+            default: fn = batch_kernel<kMaxExpPoly, uint64_t, int32_t>; break;
+        }
+    }
+    const int lds = b.lds_words * (int)sizeof(int32_t);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) {
+            err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
+            return SA_EDEVICE;
+        }
+    }
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, b.counter);
+    hipLaunchKernelGGL(fn, dim3((unsigned)bl.groups), dim3((unsigned)(kBatchWaves * kWave)), (size_t)lds,
+                       (hipStream_t)stream, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("batch launch: ") + hipGetErrorString(e);
         return SA_EDEVICE;
     }
     return SA_OK;

@@ -1,0 +1,77 @@
+// sa_plan.h -- the plan object shared by the C ABI's one-shot, batched and served paths.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "sa_internal.h"
+
+namespace sa {
+
+// One device allocation holding several arrays, each 256-byte aligned.
+struct DevArena {
+    void *base = nullptr;
+    size_t bytes = 0;
+    DevArena() = default;
+    DevArena(const DevArena &) = delete;
+    DevArena &operator=(const DevArena &) = delete;
+    ~DevArena() {
+        if (base) (void)hipFree(base);
+    }
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace sa
+
+struct sa_plan {
+    int device = 0;
+    int rule = 0;
+    sa::DevProblem dp{};
+    sa::DevArena arena;
+    sa_plan_info info{};
+    sa_launch_info last{};
+    std::vector<int32_t> lo, hi;  // host copy of the box (checks of host start states)
+    bool narrow_ok = false;       // every |dE| < 2^30: 32-bit integer kernels are exact
+    double t_init = 0.0, t_final = 0.0;
+    int auto_status = SA_OK;
+    std::string auto_error;
+    // device copy of the last schedule, reused while the schedule is unchanged
+    double *beta_dev = nullptr;
+    int32_t beta_cap = 0;
+    std::vector<double> beta_host;
+    // host packing (kept to build sweep schedules) and the device schedules built so far, by G
+    sa::Packed packed;
+    struct Sched {
+        sa::SchedRec *dev = nullptr;
+        int32_t n_win = 0;
+        int32_t n_active = 0;  // variables that are not fixed
+    };
+    Sched sched[9];
+    ~sa_plan() {
+        if (beta_dev) (void)hipFree(beta_dev);
+        for (auto &sc : sched)
+            if (sc.dev) (void)hipFree(sc.dev);
+    }
+};
+
+
+namespace sa {
+
+// Records msg as this thread's last error and returns code.
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+// Canonicalise, check, pack and upload; *out owns the result.
+int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, sa_plan **out);
+// Inverse temperatures of a schedule (explicit or automatic) for the plan's instance.
+int resolve_schedule(sa_plan *plan, const sa_schedule *sched, std::vector<double> &beta);
+// The plan's sweep schedule for G waves per replica (built on first use, kept on the device).
+int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out);
+// Uploads the inverse temperatures unless the device already holds the same array.
+int stage_beta(sa_plan *plan, const std::vector<double> &beta, hipStream_t stream);
+// Heat-bath register chunk class of a plan's widest range (1, 2, 8, 32, or 0 = recompute).
+int reg_chunk_class(int32_t max_width);
+
+}  // namespace sa

@@ -57,6 +57,28 @@ class sa_launch_info(C.Structure):
                 ("waves_per_replica", C.c_int32), ("n_windows", C.c_int32)]
 
 
+class sa_problem(C.Structure):
+    _fields_ = [("inst", sa_instance), ("bounds", sa_bounds), ("sched", sa_schedule), ("rule", C.c_int32),
+                ("n_reads", C.c_int32), ("seed", C.c_uint64), ("instance_id", C.c_uint32)]
+
+
+class sa_result(C.Structure):
+    _fields_ = [("states", C.c_void_p), ("energies", C.c_void_p), ("status", C.c_int32)]
+
+
+class sa_batch_opts(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("use_graph", C.c_int32), ("hip_stream", C.c_void_p),
+                ("waves_per_group", C.c_int32), ("groups", C.c_int32)]
+
+
+class sa_batch_info(C.Structure):
+    _fields_ = [("n_problems", C.c_int32), ("n_tasks", C.c_int64), ("total_updates", C.c_int64),
+                ("waves_per_group", C.c_int32), ("groups", C.c_int32), ("slot_bytes", C.c_int32),
+                ("kernel_maxe", C.c_int32), ("kernel_bits", C.c_int32), ("state_bits", C.c_int32),
+                ("graph", C.c_int32), ("max_team", C.c_int32), ("policy", C.c_double),
+                ("tune_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -82,11 +104,21 @@ def lib():
         L.sa_plan_last_launch.argtypes = [vp, P(sa_launch_info)]
         L.sa_auto_schedule.argtypes = [P(sa_instance), P(sa_bounds), i32, vp]
         L.sa_energy.argtypes = [P(sa_instance), P(sa_bounds), i32, vp, vp]
+        L.sa_batch_create.argtypes = [P(sa_problem), i32, P(sa_batch_opts), P(vp)]
+        L.sa_batch_run.argtypes = [vp]
+        L.sa_batch_wait.argtypes = [vp]
+        L.sa_batch_results.argtypes = [vp, P(sa_result)]
+        L.sa_batch_get_info.argtypes = [vp, P(sa_batch_info)]
+        L.sa_batch_destroy.argtypes = [vp]
+        L.sa_batch_destroy.restype = None
+        L.sa_anneal_batch.argtypes = [P(sa_problem), i32, P(sa_result), P(sa_batch_opts)]
         L.sa_last_error.argtypes = []
         L.sa_last_error.restype = C.c_char_p
         L.sa_version.argtypes = []
         for name in ("sa_anneal", "sa_anneal_ex", "sa_plan_create", "sa_plan_run", "sa_plan_get_info",
-                     "sa_plan_last_launch", "sa_auto_schedule", "sa_energy", "sa_version"):
+                     "sa_plan_last_launch", "sa_auto_schedule", "sa_energy", "sa_version",
+                     "sa_batch_create", "sa_batch_run", "sa_batch_wait", "sa_batch_results",
+                     "sa_batch_get_info", "sa_anneal_batch"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -239,6 +271,62 @@ class Plan:
         return z, e
 
 
+class Batch:
+    """Many problems annealed by one persistent launch (sa_batch).
+
+    items: sequence of objects with .problem, .rule, .n_sweeps, .n_reads, .seed, .instance_id and
+    .beta (None for the automatic schedule), e.g. inputs.Workload."""
+
+    def __init__(self, items, autotune=False, use_graph=False, stream=None, waves_per_group=0, groups=0):
+        self.items = list(items)
+        n = len(self.items)
+        self._keep = []
+        probs = (sa_problem * n)()
+        for i, w in enumerate(self.items):
+            m = _Marshalled(w.problem)
+            sched, b = _schedule(w.n_sweeps, w.beta)
+            self._keep.append((m, b))
+            probs[i] = sa_problem(m.inst, m.bounds, sched, int(w.rule), int(w.n_reads),
+                                  int(w.seed) & 0xFFFFFFFFFFFFFFFF, int(w.instance_id) & 0xFFFFFFFF)
+        opts = sa_batch_opts(1 if autotune else 0, 1 if use_graph else 0, stream, int(waves_per_group),
+                             int(groups))
+        h = C.c_void_p()
+        _check(lib().sa_batch_create(probs, n, C.byref(opts), C.byref(h)), "sa_batch_create")
+        self.h = h
+        self._keep = None  # problems are copied by the library
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.sa_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def run(self):
+        _check(lib().sa_batch_run(self.h), "sa_batch_run")
+
+    def wait(self):
+        _check(lib().sa_batch_wait(self.h), "sa_batch_wait")
+
+    def results(self):
+        n = len(self.items)
+        res = (sa_result * n)()
+        bufs = []
+        for i, w in enumerate(self.items):
+            z = np.zeros((w.n_reads, w.problem.n_vars), np.int32)
+            e = np.zeros(w.n_reads, np.int64)
+            bufs.append((z, e))
+            res[i] = sa_result(_p(z), _p(e), 0)
+        _check(lib().sa_batch_results(self.h, res), "sa_batch_results")
+        return bufs
+
+    def info(self) -> dict:
+        i = sa_batch_info()
+        _check(lib().sa_batch_get_info(self.h, C.byref(i)), "sa_batch_get_info")
+        return {f: getattr(i, f) for f, _ in sa_batch_info._fields_}
+
+
 EXPORTED = ["sa_anneal", "sa_anneal_ex", "sa_opts_default", "sa_plan_create", "sa_plan_run",
             "sa_plan_destroy", "sa_plan_get_info", "sa_plan_last_launch", "sa_auto_schedule",
-            "sa_energy", "sa_last_error", "sa_version"]
+            "sa_energy", "sa_last_error", "sa_version", "sa_batch_create", "sa_batch_run", "sa_batch_wait",
+            "sa_batch_results", "sa_batch_get_info", "sa_batch_destroy", "sa_anneal_batch"]

@@ -88,3 +88,15 @@ def test_auto_schedule_worked_example():
     beta = sa.auto_schedule(I.from_terms(1, [(2, [0, 0]), (-1, [0])], 0, 3), 5)
     assert beta[0] == pytest.approx(math.log(2.0) / 21.0, rel=1e-15)
     assert beta[-1] == pytest.approx(math.log(1000.0), rel=1e-14)
+
+
+def test_batch_rejects_bad_problems_on_the_host():
+    w = I.cfg4_batch(n_instances=2, n_reads=2, n_sweeps=3, n_min=20, n_max=30)
+    w[1].n_reads = 0
+    _expect(sa.EINVAL, lambda: sa.Batch(w))
+    big = I.Workload(I.erdos_renyi_quio(50_000, 2.0, -1, 1, 1, 1, np.random.Generator(np.random.PCG64(1))),
+                     sa.METROPOLIS, 2, 2, 1)
+    _expect(sa.EUNSUPPORTED, lambda: sa.Batch([big]))
+    w = I.cfg4_batch(n_instances=2, n_reads=2, n_sweeps=3, n_min=20, n_max=30)
+    w[0].beta = np.array([1.0, -2.0, 1.0])
+    _expect(sa.EINVAL, lambda: sa.Batch(w))
