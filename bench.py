@@ -33,7 +33,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2",
-                    choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis", "cfg4"])
+                    choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis", "cfg4", "cfg5"])
+    ap.add_argument("--requests", type=int, default=300, help="cfg5: requests in the stream")
+    ap.add_argument("--load", type=float, default=0.8, help="cfg5: arrival rate / saturated rate")
     ap.add_argument("--plain-sample", type=int, default=48,
                     help="cfg4: problems timed with plain per-instance launches")
     ap.add_argument("--sweeps", type=int, default=0, help="override the number of sweeps")
@@ -152,6 +154,95 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    """Poisson stream of requests to the continuous-batching server: p50/p99 latency and updates/s
+    at a load below saturation, after a saturation pass that measures the request rate."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_2511_17245_amd import inputs as I
+    from paper_2511_17245_amd import sa
+
+    n = args.requests
+    t0 = time.perf_counter()
+    reqs = [I.cfg5_request(i) for i in range(n)]
+    gen_s = time.perf_counter() - t0
+    kinds = sum(1 for w in reqs if w.rule == sa.HEAT_BATH)
+    print(f"[bench] generated {n} requests ({kinds} dense heat-bath) in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    def stream(server, items, arrivals):
+        tickets = [None] * len(items)
+
+        def client():
+            start = time.perf_counter()
+            for i, w in enumerate(items):
+                delay = arrivals[i] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = server.submit(w)
+                if (i + 1) % 25 == 0:
+                    print(f"[bench] submitted {i + 1}/{len(items)}: {server.stats()}", file=sys.stderr, flush=True)
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        tim = []
+        for k, t in enumerate(tickets):
+            tim.append(server.wait(t))
+            if (k + 1) % 25 == 0:
+                print(f"[bench] completed {k + 1}/{len(items)}", file=sys.stderr, flush=True)
+        return tickets, tim
+
+    # saturation: everything submitted at once
+    m = min(n, max(60, n // 5))
+    srv = sa.Server(chunk_sweeps=50)
+    _, tim = stream(srv, reqs[:m], np.zeros(m))
+    span = max(t["t_done"] for t in tim) - min(t["t_submit"] for t in tim)
+    sat_rate = m / span
+    srv.close()
+    print(f"[bench] saturated: {m} requests in {span:.1f}s = {sat_rate:.2f} req/s", file=sys.stderr, flush=True)
+
+    rate = args.load * sat_rate
+    arrivals = I.cfg5_arrivals(n, rate)
+    srv = sa.Server(chunk_sweeps=50)
+    tickets, tim = stream(srv, reqs, arrivals)
+    stats = srv.stats()
+    ok = [t for t in tim if t["status"] == sa.OK]
+    lat = np.array([t["t_done"] - t["t_submit"] for t in ok])
+    span = max(t["t_done"] for t in ok) - min(t["t_submit"] for t in ok)
+    upd = float(sum(t["updates"] for t in ok))
+    # alone-versus-mix identity on a sample of requests
+    rng = np.random.Generator(np.random.PCG64(555))
+    sample = rng.choice(n, size=min(12, n), replace=False)
+    same = True
+    for i in sample:
+        w = reqs[i]
+        plan = sa.Plan(w.problem, w.rule)
+        z = torch.empty((w.n_reads, w.problem.n_vars), dtype=torch.int32, device="cuda")
+        e = torch.empty(w.n_reads, dtype=torch.int64, device="cuda")
+        plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, stream=torch.cuda.current_stream().cuda_stream,
+                        instance_id=w.instance_id)
+        torch.cuda.synchronize()
+        zs, es = srv.result(tickets[i])
+        same = same and np.array_equal(z.cpu().numpy(), zs) and np.array_equal(e.cpu().numpy(), es)
+        plan.close()
+    srv.close()
+    out = {
+        "metric": "single-variable updates/sec at 1 GPU (served stream)",
+        "value": upd / span, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": f"Poisson stream of {n} requests: 90% HUIO N=2000 (OTM/Metropolis, 16 reads, "
+                               f"1000 sweeps), 10% dense QUIO N=4096 [-1000,1000] heat bath (16 reads, 100 sweeps)",
+                   "arrival_rate_req_s": rate, "saturated_req_s": sat_rate, "load": args.load,
+                   "chunk_sweeps": 50},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean()), "max": float(lat.max())},
+        "completed": len(ok), "server": stats, "alone_vs_mix_identical": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -166,6 +257,8 @@ def main():
     torch.cuda.set_device(0)
     if args.config == "cfg4":
         return bench_batch(args)
+    if args.config == "cfg5":
+        return bench_serving(args)
     w = workload(args)
     prob = w.problem
     n, S, R = prob.n_vars, w.n_sweeps, w.n_reads

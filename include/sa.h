@@ -214,6 +214,58 @@ void sa_batch_destroy(sa_batch *batch);
 int32_t sa_anneal_batch(const sa_problem *problems, int32_t n_problems, sa_result *results,
                         const sa_batch_opts *opts);
 
+/* ---- serving: continuous batching ----------------------------------------------------------
+ * A server owns one device (the caller's current device at creation), a stream, host threads that
+ * canonicalise and upload arriving requests, and a scheduler thread.  The scheduler admits
+ * prepared requests in arrival order while a slot is free and their device footprint (plan,
+ * states, schedule) fits the memory budget, and advances all admitted requests together, one
+ * chunk of sweeps per batched launch, with their states kept on the device in between.  A
+ * request's results are identical to sa_anneal_ex of the same problem alone.  submit, poll, wait
+ * and cancel may be called from any thread. */
+typedef struct sa_server sa_server;
+
+typedef struct {
+    size_t mem_budget_bytes;    /* device bytes for admitted requests (0: 16 GiB) */
+    int32_t max_slots;          /* requests on the device at once (0: 256) */
+    int32_t chunk_sweeps;       /* sweeps per chunk launch for a request of median cost (0: 50);
+                                   cheaper requests run more sweeps per chunk, dearer ones fewer
+                                   (at least one), so that every chunk is about equally long */
+    int32_t prep_threads;       /* host threads preparing requests (0: 4) */
+} sa_server_opts;
+
+typedef struct {
+    double t_submit, t_admit, t_done;  /* seconds since the server was created (steady clock) */
+    uint64_t updates;                   /* n_reads * n_sweeps * N */
+    int32_t status;                     /* SA_EBUSY until done, then the request's status */
+} sa_timing;
+
+int32_t sa_server_create(const sa_server_opts *opts, sa_server **out);
+/* Copies the problem and queues it.  result's buffers (host, caller-owned) must stay valid until
+ * the request is done; they are written at completion.  SA_ENOMEM at once if the states alone
+ * exceed the budget; a request whose full footprint exceeds it completes with SA_ENOMEM. */
+int32_t sa_server_submit(sa_server *server, const sa_problem *problem, sa_result *result,
+                         uint64_t *ticket);
+/* Queues a run of an existing plan (shared, not copied: keep it alive until the request is done). */
+int32_t sa_server_submit_plan(sa_server *server, sa_plan *plan, const sa_schedule *sched,
+                              int32_t n_reads, uint64_t seed, uint32_t instance_id,
+                              sa_result *result, uint64_t *ticket);
+/* done = 1 once the request finished (timing->status then holds its status). */
+int32_t sa_server_poll(sa_server *server, uint64_t ticket, int32_t *done, sa_timing *timing);
+/* Blocks until the request is done; returns its status. */
+int32_t sa_server_wait(sa_server *server, uint64_t ticket, sa_timing *timing);
+/* Cancels a request: it completes with SA_ECANCELED at its next hand-over (before preparation,
+ * at admission, or at the next chunk boundary); other requests are unaffected. */
+int32_t sa_server_cancel(sa_server *server, uint64_t ticket);
+typedef struct {
+    int64_t submitted, completed, canceled, failed;
+    int64_t active, queued, chunks, updates;
+    size_t mem_in_use;
+    double elapsed_s;
+} sa_server_stats;
+int32_t sa_server_get_stats(sa_server *server, sa_server_stats *stats);
+/* Cancels what has not finished, joins the threads and frees everything. */
+void sa_server_destroy(sa_server *server);
+
 /* ---- utilities -------------------------------------------------------------------------------- */
 /* The automatic schedule of Sec. 3.4 (host arithmetic): beta_out[0..n_sweeps-1]. */
 int32_t sa_auto_schedule(const sa_instance *inst, const sa_bounds *bounds, int32_t n_sweeps,

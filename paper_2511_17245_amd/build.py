@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa.so")
-SOURCES = ["sa_kernels.hip", "sa_api.cpp", "sa_host.cpp", "sa_batch.cpp"]
+SOURCES = ["sa_kernels.hip", "sa_api.cpp", "sa_host.cpp", "sa_batch.cpp", "sa_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

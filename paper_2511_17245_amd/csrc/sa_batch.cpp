@@ -263,6 +263,9 @@ int create(const sa_problem *problems, int32_t n, const sa_batch_opts *opts_in, 
         d.beta = (const double *)(b->base + o_beta) + beta_off[i];
         d.n_reads = problems[i].n_reads;
         d.n_sweeps = problems[i].sched.n_sweeps;
+        d.s_begin = 0;
+        d.s_end = d.n_sweeps;
+        d.resume = 0;
         d.rule = p.rule;
         const int rc_class = sa::reg_chunk_class(p.info.max_width);
         d.chunk = rc_class == 32 ? 0 : rc_class;

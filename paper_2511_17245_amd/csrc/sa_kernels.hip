@@ -233,14 +233,19 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int
 #pragma unroll
         for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
     }
-    for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
-        IncRec r;
-        uint64_t coef;
-        load_record(P, row, deg, c0, lane, r, coef);
-        int e;
-        const Acc prod = record_product<Acc, ZT>(P, z, r, coef, e);
+    // further chunks (dense rows): four chunks' records are loaded before any is used
+    for (int32_t c0 = kWave; c0 < deg; c0 += 4 * kWave) {
+        IncRec r[4];
+        uint64_t coef[4];
 #pragma unroll
-        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
+        for (int u = 0; u < 4; ++u) load_record(P, row, deg, c0 + u * kWave, lane, r[u], coef[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int e;
+            const Acc prod = record_product<Acc, ZT>(P, z, r[u], coef[u], e);
+#pragma unroll
+            for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
+        }
     }
     C.a[0] = 0;
 #pragma unroll
@@ -268,12 +273,16 @@ __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z
     int e;
     Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
     Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
-    for (int32_t c0 = kWave; c0 < deg; c0 += kWave) {
-        IncRec r;
-        uint64_t coef;
-        load_record(P, row, deg, c0, lane, r, coef);
-        prod = record_product<Acc, ZT>(P, z, r, coef, e);
-        acc += prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
+    for (int32_t c0 = kWave; c0 < deg; c0 += 4 * kWave) {
+        IncRec r[4];
+        uint64_t coef[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) load_record(P, row, deg, c0 + u * kWave, lane, r[u], coef[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            prod = record_product<Acc, ZT>(P, z, r[u], coef[u], e);
+            acc += prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
+        }
     }
     return to_i64<Acc>(wave_sum<Acc>(acc));
 }
@@ -618,7 +627,7 @@ __global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
 // class, integer width and state width are those of the whole batch.
 // ------------------------------------------------------------------------------------------------
 template <int kMaxE, typename Acc, typename ZT>
-__global__ void __launch_bounds__(kBatchWaves * 64) batch_kernel(BatchArgs B) {
+__global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B) {
     extern __shared__ int32_t lds_state[];
     __shared__ uint32_t task_slot;
     const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -641,15 +650,16 @@ __global__ void __launch_bounds__(kBatchWaves * 64) batch_kernel(BatchArgs B) {
         const uint32_t read = (uint32_t)read_i;
         ZT *z = (ZT *)lds_state + (size_t)team * D.slot_stride;
         const int tid = g * kWave + lane, nthr = G * kWave;
-        if (active) init_state(P, z, nullptr, read, D.instance_id, D.key0, D.key1, tid, nthr);
+        int32_t *zo = D.z_out + (size_t)read * P.n;
+        if (active) init_state(P, z, D.resume ? zo : nullptr, read, D.instance_id, D.key0, D.key1, tid, nthr);
         window_barrier();
         int64_t E = active ? energy_part(P, z, tid, nthr) : 0;
         ReplicaCtx R;
         R.P = P;
         R.beta = D.beta;
         R.n_sweeps = D.n_sweeps;
-        R.s_begin = 0;
-        R.s_end = B.sweep_limit > 0 && B.sweep_limit < D.n_sweeps ? B.sweep_limit : D.n_sweeps;
+        R.s_begin = D.s_begin;
+        R.s_end = B.sweep_limit > 0 && B.sweep_limit < D.s_end ? B.sweep_limit : D.s_end;
         R.key0 = D.key0;
         R.key1 = D.key1;
         R.instance_id = D.instance_id;
@@ -679,7 +689,6 @@ __global__ void __launch_bounds__(kBatchWaves * 64) batch_kernel(BatchArgs B) {
                 for (int q = 0; q < G; ++q) tot += parts[team * G + q];
                 D.e_out[read] = tot;
             }
-            int32_t *zo = D.z_out + (size_t)read * P.n;
             for (int32_t k = tid; k < P.n; k += nthr) zo[k] = (int32_t)z[k];
         }
         window_barrier();  // the slots' last reads come before the next task's writes

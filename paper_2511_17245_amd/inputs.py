@@ -267,18 +267,26 @@ def cfg4_batch(n_instances=512, n_reads=32, n_sweeps=1000, n_min=50, n_max=5000,
     return out
 
 
-def cfg5_request(req_id: int, dense_n=4096) -> Workload:
+_DENSE_POOL = {}
+
+
+def cfg5_request(req_id: int, dense_n=4096, dense_pool=4) -> Workload:
     """Request `req_id` of the serving stream: 90% are HUIO drawn as the N=2000 config (rule OTM
     for even ids, Metropolis for odd ids; 16 reads, 1000 sweeps); 10% are dense QUIO N=4096,
-    z in [-1000,1000], J and h in {-10..10}, heat bath, 16 reads, 100 sweeps."""
+    z in [-1000,1000], J and h in {-10..10}, heat bath, 16 reads, 100 sweeps.  Dense requests draw
+    their instance from a pool of `dense_pool` seeded instances (their own seed and instance id
+    still make every request a distinct run)."""
     rng = np.random.Generator(np.random.PCG64([GEN_SEED_BASE + 5, req_id]))
     if rng.uniform() < 0.9:
         prob = random_huio(2000, 20_000, [2, 3, 4], 0, 100, 5, rng, name=f"req{req_id}_huio")
         rule = RULES["otm"] if req_id % 2 == 0 else RULES["metropolis"]
-        return Workload(prob, rule, 1000, 16, PHILOX_SEED_BASE + 5, req_id, None, f"req {req_id} A")
-    prob = dense_quio(dense_n, -1000, 1000, 10, 10, rng, name=f"req{req_id}_dense")
-    return Workload(prob, RULES["heat_bath"], 100, 16, PHILOX_SEED_BASE + 5, req_id, None,
-                    f"req {req_id} B")
+        return Workload(prob, rule, 1000, 16, PHILOX_SEED_BASE + 5 + req_id, req_id, None, f"req {req_id} A")
+    key = (dense_n, req_id % dense_pool)
+    if key not in _DENSE_POOL:
+        drng = np.random.Generator(np.random.PCG64([GEN_SEED_BASE + 5, 1 << 40, key[1]]))
+        _DENSE_POOL[key] = dense_quio(dense_n, -1000, 1000, 10, 10, drng, name=f"dense{key[1]}")
+    return Workload(_DENSE_POOL[key], RULES["heat_bath"], 100, 16, PHILOX_SEED_BASE + 5 + req_id, req_id,
+                    None, f"req {req_id} B")
 
 
 def cfg5_arrivals(n_requests: int, rate_per_s: float, seed=0x5A0005A0) -> np.ndarray:

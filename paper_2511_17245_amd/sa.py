@@ -79,6 +79,22 @@ class sa_batch_info(C.Structure):
                 ("tune_ms", C.c_double)]
 
 
+class sa_server_opts(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("chunk_sweeps", C.c_int32),
+                ("prep_threads", C.c_int32)]
+
+
+class sa_timing(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("updates", C.c_uint64), ("status", C.c_int32)]
+
+
+class sa_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("canceled", C.c_int64),
+                ("failed", C.c_int64), ("active", C.c_int64), ("queued", C.c_int64), ("chunks", C.c_int64),
+                ("updates", C.c_int64), ("mem_in_use", C.c_size_t), ("elapsed_s", C.c_double)]
+
+
 _lib = None
 
 
@@ -112,13 +128,24 @@ def lib():
         L.sa_batch_destroy.argtypes = [vp]
         L.sa_batch_destroy.restype = None
         L.sa_anneal_batch.argtypes = [P(sa_problem), i32, P(sa_result), P(sa_batch_opts)]
+        L.sa_server_create.argtypes = [P(sa_server_opts), P(vp)]
+        L.sa_server_submit.argtypes = [vp, P(sa_problem), P(sa_result), P(C.c_uint64)]
+        L.sa_server_submit_plan.argtypes = [vp, vp, P(sa_schedule), i32, u64, u32, P(sa_result), P(C.c_uint64)]
+        L.sa_server_poll.argtypes = [vp, C.c_uint64, P(i32), P(sa_timing)]
+        L.sa_server_wait.argtypes = [vp, C.c_uint64, P(sa_timing)]
+        L.sa_server_cancel.argtypes = [vp, C.c_uint64]
+        L.sa_server_get_stats.argtypes = [vp, P(sa_server_stats)]
+        L.sa_server_destroy.argtypes = [vp]
+        L.sa_server_destroy.restype = None
         L.sa_last_error.argtypes = []
         L.sa_last_error.restype = C.c_char_p
         L.sa_version.argtypes = []
         for name in ("sa_anneal", "sa_anneal_ex", "sa_plan_create", "sa_plan_run", "sa_plan_get_info",
                      "sa_plan_last_launch", "sa_auto_schedule", "sa_energy", "sa_version",
                      "sa_batch_create", "sa_batch_run", "sa_batch_wait", "sa_batch_results",
-                     "sa_batch_get_info", "sa_anneal_batch"):
+                     "sa_batch_get_info", "sa_anneal_batch", "sa_server_create", "sa_server_submit",
+                     "sa_server_submit_plan", "sa_server_poll", "sa_server_wait", "sa_server_cancel",
+                     "sa_server_get_stats"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -326,7 +353,81 @@ class Batch:
         return {f: getattr(i, f) for f, _ in sa_batch_info._fields_}
 
 
+class Server:
+    """Continuous-batching server (sa_server).  submit() copies the problem; results land in
+    host buffers owned by this object and are returned by result()."""
+
+    def __init__(self, mem_budget_bytes=0, max_slots=0, chunk_sweeps=0, prep_threads=0):
+        o = sa_server_opts(int(mem_budget_bytes), int(max_slots), int(chunk_sweeps), int(prep_threads))
+        h = C.c_void_p()
+        _check(lib().sa_server_create(C.byref(o), C.byref(h)), "sa_server_create")
+        self.h = h
+        self._out = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.sa_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def submit(self, w) -> int:
+        """w: object with .problem, .rule, .n_sweeps, .n_reads, .seed, .instance_id, .beta."""
+        m = _Marshalled(w.problem)
+        sched, keep = _schedule(w.n_sweeps, w.beta)
+        prob = sa_problem(m.inst, m.bounds, sched, int(w.rule), int(w.n_reads),
+                          int(w.seed) & 0xFFFFFFFFFFFFFFFF, int(w.instance_id) & 0xFFFFFFFF)
+        z = np.zeros((w.n_reads, w.problem.n_vars), np.int32)
+        e = np.zeros(w.n_reads, np.int64)
+        res = sa_result(_p(z), _p(e), 0)
+        t = C.c_uint64()
+        _check(lib().sa_server_submit(self.h, C.byref(prob), C.byref(res), C.byref(t)), "sa_server_submit")
+        self._out[t.value] = (z, e)
+        return t.value
+
+    def submit_plan(self, plan, n_sweeps, n_reads, seed, instance_id=0, beta=None) -> int:
+        sched, keep = _schedule(n_sweeps, beta)
+        z = np.zeros((n_reads, plan.n), np.int32)
+        e = np.zeros(n_reads, np.int64)
+        res = sa_result(_p(z), _p(e), 0)
+        t = C.c_uint64()
+        _check(lib().sa_server_submit_plan(self.h, plan.h, C.byref(sched), int(n_reads),
+                                           int(seed) & 0xFFFFFFFFFFFFFFFF, int(instance_id) & 0xFFFFFFFF,
+                                           C.byref(res), C.byref(t)), "sa_server_submit_plan")
+        self._out[t.value] = (z, e)
+        return t.value
+
+    @staticmethod
+    def _timing(t):
+        return {f: getattr(t, f) for f, _ in sa_timing._fields_}
+
+    def poll(self, ticket):
+        done = C.c_int32()
+        t = sa_timing()
+        _check(lib().sa_server_poll(self.h, C.c_uint64(ticket), C.byref(done), C.byref(t)), "sa_server_poll")
+        return bool(done.value), self._timing(t)
+
+    def wait(self, ticket):
+        """Blocks until done; returns the request's timing (status inside)."""
+        t = sa_timing()
+        lib().sa_server_wait(self.h, C.c_uint64(ticket), C.byref(t))
+        return self._timing(t)
+
+    def result(self, ticket):
+        return self._out[ticket]
+
+    def cancel(self, ticket):
+        _check(lib().sa_server_cancel(self.h, C.c_uint64(ticket)), "sa_server_cancel")
+
+    def stats(self) -> dict:
+        st = sa_server_stats()
+        _check(lib().sa_server_get_stats(self.h, C.byref(st)), "sa_server_get_stats")
+        return {f: getattr(st, f) for f, _ in sa_server_stats._fields_}
+
+
 EXPORTED = ["sa_anneal", "sa_anneal_ex", "sa_opts_default", "sa_plan_create", "sa_plan_run",
             "sa_plan_destroy", "sa_plan_get_info", "sa_plan_last_launch", "sa_auto_schedule",
             "sa_energy", "sa_last_error", "sa_version", "sa_batch_create", "sa_batch_run", "sa_batch_wait",
-            "sa_batch_results", "sa_batch_get_info", "sa_batch_destroy", "sa_anneal_batch"]
+            "sa_batch_results", "sa_batch_get_info", "sa_batch_destroy", "sa_anneal_batch",
+            "sa_server_create", "sa_server_submit", "sa_server_submit_plan", "sa_server_poll",
+            "sa_server_wait", "sa_server_cancel", "sa_server_get_stats", "sa_server_destroy"]

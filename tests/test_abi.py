@@ -34,12 +34,14 @@ def test_library_exports_every_declared_function():
 
 
 def test_binding_covers_declared_functions():
-    assert set(declared_functions()) <= set(sa.EXPORTED) | {"sa_anneal_batch", "sa_batch_create",
-                                                           "sa_batch_run", "sa_batch_results",
-                                                           "sa_batch_destroy", "sa_batch_info",
-                                                           "sa_server_create", "sa_server_submit",
-                                                           "sa_server_poll", "sa_server_cancel",
-                                                           "sa_server_destroy", "sa_server_stats"}
+    assert set(declared_functions()) == set(sa.EXPORTED)
+
+
+def test_server_creation_without_a_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    _expect(sa.EDEVICE, lambda: sa.Server())
 
 
 def _expect(code, fn):

@@ -1,0 +1,118 @@
+"""GPU: the continuous-batching server.  Every served result must equal the same problem annealed
+alone (and the oracle), whatever the chunk size, the memory budget or the other requests."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_17245_amd import inputs as I
+from paper_2511_17245_amd import sa
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-server]", *a, flush=True)
+
+
+def requests(n=10, sweeps=40, reads=5):
+    items = I.cfg4_batch(n_instances=n, n_reads=reads, n_sweeps=sweeps, n_min=30, n_max=600,
+                         w_min=2, w_max=200)
+    for i, w in enumerate(items):
+        w.instance_id = 1000 + i
+        if i % 3 == 0:
+            w.beta = oracle.Poly(w.problem).schedule(sweeps)[0]
+    return items
+
+
+def alone(w):
+    import torch
+    plan = sa.Plan(w.problem, w.rule)
+    z = torch.empty((w.n_reads, w.problem.n_vars), dtype=torch.int32, device="cuda")
+    e = torch.empty(w.n_reads, dtype=torch.int64, device="cuda")
+    plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=w.beta,
+                    stream=torch.cuda.current_stream().cuda_stream, instance_id=w.instance_id)
+    torch.cuda.synchronize()
+    plan.close()
+    return z.cpu().numpy(), e.cpu().numpy()
+
+
+def serve(items, **kw):
+    srv = sa.Server(**kw)
+    tickets = [srv.submit(w) for w in items]
+    timings = [srv.wait(t) for t in tickets]
+    out = [srv.result(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    return out, timings, stats
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 1000])
+def test_served_results_equal_alone(chunk):
+    items = requests()
+    say("chunk", chunk)
+    out, timings, stats = serve(items, chunk_sweeps=chunk)
+    say("stats", stats)
+    assert all(t["status"] == sa.OK for t in timings)
+    assert stats["completed"] == len(items)
+    for i, w in enumerate(items):
+        z, e = alone(w)
+        assert np.array_equal(out[i][0], z) and np.array_equal(out[i][1], e), f"request {i}"
+    P = oracle.Poly(items[2].problem)
+    zo, eo = P.anneal(items[2].rule, P.schedule(items[2].n_sweeps)[0], items[2].n_reads, items[2].seed,
+                      items[2].instance_id)
+    assert np.array_equal(out[2][0], zo) and np.array_equal(out[2][1], eo)
+
+
+def test_memory_budget_admission():
+    items = requests(n=8, sweeps=20, reads=4)
+    # a budget that holds only a few requests at a time: everything still completes, identically
+    out, timings, stats = serve(items, mem_budget_bytes=2_000_000, chunk_sweeps=5, max_slots=3)
+    for i, w in enumerate(items):
+        assert timings[i]["status"] == sa.OK
+        z, e = alone(w)
+        assert np.array_equal(out[i][0], z) and np.array_equal(out[i][1], e)
+    srv = sa.Server(mem_budget_bytes=100_000)
+    big = I.Workload(I.erdos_renyi_quio(20_000, 3.0, -3, 3, 3, 3, np.random.Generator(np.random.PCG64(2))),
+                     sa.METROPOLIS, 5, 4, 1)
+    with pytest.raises(sa.SAError) as ex:
+        srv.submit(big)                      # states alone exceed the budget
+    assert ex.value.code == sa.ENOMEM
+    mid = I.Workload(I.erdos_renyi_quio(5_000, 3.0, -3, 3, 3, 3, np.random.Generator(np.random.PCG64(3))),
+                     sa.METROPOLIS, 5, 4, 1)
+    t = srv.submit(mid)                      # fits the states, not the packed instance as well
+    assert srv.wait(t)["status"] == sa.ENOMEM
+    srv.close()
+
+
+def test_cancel_leaves_others_untouched():
+    items = requests(n=6, sweeps=30, reads=4)
+    long = I.cfg3_huio(rule="otm", n=1500, m=15000, n_sweeps=100000, n_reads=8)
+    long.instance_id = 77
+    srv = sa.Server(chunk_sweeps=10)
+    tl = srv.submit(long)
+    ts = [srv.submit(w) for w in items]
+    time.sleep(0.5)
+    srv.cancel(tl)
+    for i, t in enumerate(ts):
+        assert srv.wait(t)["status"] == sa.OK
+        z, e = alone(items[i])
+        assert np.array_equal(srv.result(t)[0], z) and np.array_equal(srv.result(t)[1], e)
+    assert srv.wait(tl)["status"] == sa.ECANCELED
+    assert srv.stats()["canceled"] == 1
+    srv.close()
+
+
+def test_shared_plan_requests():
+    w = I.cfg3_huio(rule="metropolis", n=400, m=4000, n_sweeps=25, n_reads=6)
+    plan = sa.Plan(w.problem, w.rule)
+    srv = sa.Server(chunk_sweeps=6)
+    tickets = [srv.submit_plan(plan, w.n_sweeps, w.n_reads, w.seed, instance_id=k) for k in range(5)]
+    for k, t in enumerate(tickets):
+        assert srv.wait(t)["status"] == sa.OK
+        w.instance_id = k
+        z, e = alone(w)
+        assert np.array_equal(srv.result(t)[0], z) and np.array_equal(srv.result(t)[1], e)
+    srv.close()
+    plan.close()
