@@ -132,6 +132,8 @@ typedef struct {
     int64_t device_bytes;       /* device memory held by the plan */
     int32_t coef_bits;          /* 32 or 64: width of the stored coefficients */
     int32_t arith_bits;         /* 32 or 64: integer width of energy differences in the kernel */
+    int32_t dense;              /* 1: stored as a dense coupling matrix (QUIO with >= 25% of all
+                                   pairs present); 0: variable-major incidence records */
 } sa_plan_info;
 int32_t sa_plan_get_info(const sa_plan *plan, sa_plan_info *info);
 

@@ -49,6 +49,10 @@ int upload_packed(const sa::Packed &pk, sa_plan *plan) {
         {pk.t_off.data(), pk.t_off.size() * sizeof(int32_t), 0},
         {pk.t_var.data(), pk.t_var.size() * sizeof(int32_t), 0},
         {pk.t_coef.data(), pk.t_coef.size() * sizeof(int64_t), 0},
+        {pk.jbytes == 1 ? (const void *)pk.jd8.data() : (const void *)pk.jd32.data(),
+         pk.jbytes == 1 ? pk.jd8.size() : pk.jd32.size() * sizeof(int32_t), 0},
+        {pk.h.data(), pk.h.size() * sizeof(int64_t), 0},
+        {pk.d.data(), pk.d.size() * sizeof(int64_t), 0},
     };
     size_t total = 0;
     for (auto &p : parts) {
@@ -75,6 +79,12 @@ int upload_packed(const sa::Packed &pk, sa_plan *plan) {
     d.t_off = (const int32_t *)(b + parts[5].off);
     d.t_var = (const int32_t *)(b + parts[6].off);
     d.t_coef = (const int64_t *)(b + parts[7].off);
+    d.dense = pk.dense ? 1 : 0;
+    d.jbytes = pk.jbytes;
+    d.row_stride = pk.row_stride;
+    d.jd = (const void *)(b + parts[8].off);
+    d.h = (const int64_t *)(b + parts[9].off);
+    d.d = (const int64_t *)(b + parts[10].off);
     return SA_OK;
 }
 
@@ -121,7 +131,8 @@ int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, s
     sa_plan_info &in = plan->info;
     in.n_vars = pk.n;
     in.n_terms = pk.n_terms;
-    in.n_incidences = (int64_t)pk.inc.size();
+    in.n_incidences = pk.dense ? 2 * pk.n_pairs : (int64_t)pk.inc.size();
+    in.dense = pk.dense ? 1 : 0;
     int64_t slots = (int64_t)pk.overflow.size();
     for (const auto &r : pk.inc) slots += std::min<int64_t>(r.meta >> 8, 3);
     in.n_factor_slots = slots;

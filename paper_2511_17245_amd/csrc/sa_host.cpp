@@ -239,6 +239,73 @@ void geometric_betas(double t_init, double t_final, int32_t n_sweeps, double *be
     }
 }
 
+namespace {
+
+// A QUIO whose pair terms cover at least a quarter of all pairs is packed as a dense matrix: a
+// row of J costs 1 or 4 bytes per pair instead of an incidence record per pair.
+bool pack_dense(const Canonical &c, Packed &p) {
+    const int32_t n = c.n;
+    const int64_t nt = c.n_terms();
+    if (n < 32) return false;
+    int64_t pairs = 0;
+    int64_t jmax = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t deg = c.t_off[t + 1] - c.t_off[t];
+        if (deg > 2) return false;
+        if (deg == 2 && c.t_var[c.t_off[t]] != c.t_var[c.t_off[t] + 1]) {
+            ++pairs;
+            const int64_t a = c.t_coef[t] < 0 ? -c.t_coef[t] : c.t_coef[t];
+            jmax = std::max(jmax, a);
+        }
+    }
+    if ((double)pairs < 0.25 * (double)n * (double)(n - 1) / 2.0) return false;
+    if (jmax > INT32_MAX) return false;
+    const int32_t stride = (n + 15) & ~15;
+    const int jbytes = jmax <= 127 ? 1 : 4;
+    if ((double)n * stride * jbytes > 8.0e9) return false;
+    p.dense = true;
+    p.jbytes = jbytes;
+    p.row_stride = stride;
+    p.n_pairs = pairs;
+    p.h.assign(n, 0);
+    p.d.assign(n, 0);
+    if (jbytes == 1) p.jd8.assign((size_t)n * stride, 0);
+    else p.jd32.assign((size_t)n * stride, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = c.t_off[t];
+        const int64_t deg = c.t_off[t + 1] - a;
+        const int32_t i = c.t_var[a];
+        if (deg == 1) {
+            p.h[i] += c.t_coef[t];
+        } else if (c.t_var[a + 1] == i) {
+            p.d[i] += c.t_coef[t];
+        } else {
+            const int32_t j = c.t_var[a + 1];
+            if (jbytes == 1) {
+                p.jd8[(size_t)i * stride + j] = (int8_t)c.t_coef[t];
+                p.jd8[(size_t)j * stride + i] = (int8_t)c.t_coef[t];
+            } else {
+                p.jd32[(size_t)i * stride + j] = (int32_t)c.t_coef[t];
+                p.jd32[(size_t)j * stride + i] = (int32_t)c.t_coef[t];
+            }
+            p.emask[i] |= 2u;
+            p.emask[j] |= 2u;
+        }
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        if (p.h[k] != 0) p.emask[k] |= 2u;
+        if (p.d[k] != 0) {
+            p.emask[k] |= 4u;
+            p.max_exp = 2;
+        } else if (p.emask[k]) {
+            p.max_exp = std::max(p.max_exp, 1);
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
 int pack(const Canonical &c, Packed &p, std::string &err) {
     const int32_t n = c.n;
     const int64_t nt = c.n_terms();
@@ -251,6 +318,16 @@ int pack(const Canonical &c, Packed &p, std::string &err) {
     p.n_terms = (int32_t)nt;
     p.var.resize(n);
     p.emask.assign(n, 0u);
+    if (pack_dense(c, p)) {
+        for (int32_t k = 0; k < n; ++k) {
+            const int64_t w = (int64_t)c.hi[k] - c.lo[k] + 1;
+            p.var[k] = VarRec{c.lo[k], (int32_t)w, 0, 0};
+            p.max_width = std::max<int32_t>(p.max_width, (int32_t)w);
+        }
+        p.n_terms = 0;  // energies come from the matrix
+        p.t_off.assign(1, 0);
+        return SA_OK;
+    }
     // count incidences (distinct variables per term)
     std::vector<int64_t> deg(n, 0);
     for (int64_t t = 0; t < nt; ++t)
@@ -327,7 +404,8 @@ int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out) {
     for (int32_t k = 0; k < n; ++k) {
         const VarRec &vr = p.var[k];
         if (vr.width == 1) continue;
-        if (count == G || stamp[k] == win) {
+        // a dense problem couples (almost) every pair: one variable per window
+        if (count == G || stamp[k] == win || p.dense) {
             ++win;
             count = 0;
             starts.push_back((int32_t)members.size());

@@ -68,6 +68,15 @@ struct Packed {
     std::vector<int64_t> t_coef;
     int32_t max_exp = 0;
     int32_t max_width = 1;
+    // dense QUIO form (no incidence records): E = sum_k h_k z_k + d_k z_k^2 + sum_{j<k} J_kj z_j z_k
+    // with J stored as a symmetric n x row_stride matrix (zero diagonal and padding)
+    bool dense = false;
+    int32_t jbytes = 0;             // 1 (int8) or 4 (int32)
+    int32_t row_stride = 0;         // elements per matrix row (multiple of 16)
+    std::vector<int8_t> jd8;
+    std::vector<int32_t> jd32;
+    std::vector<int64_t> h, d;
+    int64_t n_pairs = 0;
 };
 int pack(const Canonical &c, Packed &out, std::string &err);
 int maxe_class_of(int32_t max_exp);
@@ -98,6 +107,13 @@ struct DevProblem {
     const int32_t *t_off;
     const int32_t *t_var;
     const int64_t *t_coef;
+    // dense QUIO form (dense != 0)
+    int32_t dense;
+    int32_t jbytes;
+    int32_t row_stride;
+    const void *jd;
+    const int64_t *h;
+    const int64_t *d;
 };
 
 // Kernel arguments of one annealing launch.

@@ -213,6 +213,45 @@ __device__ __forceinline__ void load_record(const DevProblem &P, int32_t row, in
     }
 }
 
+// Dense form: this lane's part of sum_j J_kj z_j over row k of the coupling matrix.  Lane l reads
+// elements 16l.. of each 1024-element block (one 16-byte load for int8 rows, four for int32); the
+// row's padding is zero, so indexes past N are clamped instead of tested.
+template <typename Acc, typename ZT>
+__device__ __forceinline__ Acc dense_dot(const DevProblem &P, const ZT *z, int32_t k, int lane) {
+    const int32_t n = P.n;
+    Acc acc = 0;
+    if (P.jbytes == 1) {
+        const int8_t *row = (const int8_t *)P.jd + (size_t)k * P.row_stride;
+
+        for (int32_t j0 = lane * 16; j0 < n; j0 += kWave * 16) {
+            const int4 q = *(const int4 *)(row + j0);
+            const uint32_t w[4] = {(uint32_t)q.x, (uint32_t)q.y, (uint32_t)q.z, (uint32_t)q.w};
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int32_t jv = (int32_t)(int8_t)(w[u >> 2] >> (8 * (u & 3)));
+                const int32_t j = j0 + u < n ? j0 + u : n - 1;
+                acc += (Acc)(int64_t)jv * (Acc)(int64_t)z[j];
+            }
+        }
+    } else {
+        const int32_t *row = (const int32_t *)P.jd + (size_t)k * P.row_stride;
+
+        for (int32_t j0 = lane * 16; j0 < n; j0 += kWave * 16) {
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int4 q = *(const int4 *)(row + j0 + 4 * q4);
+                const int32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t j = j0 + 4 * q4 + u < n ? j0 + 4 * q4 + u : n - 1;
+                    acc += (Acc)(int64_t)w[u] * (Acc)(int64_t)z[j];
+                }
+            }
+        }
+    }
+    return acc;
+}
+
 // Uniform coefficients a_k^(m) (Sec. 3.2, T_k = sum_m a_k^(m) z_k^m) for m = 1..kMaxE; every
 // index is static so the coefficients stay in registers.
 template <int kMaxE, typename Acc>
@@ -221,9 +260,17 @@ struct Coeffs {
 };
 
 template <int kMaxE, typename Acc, typename ZT>
-__device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int32_t row,
+__device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
                                            int32_t deg, uint32_t emask, int lane, const IncRec &r0,
                                            uint64_t coef0, Coeffs<kMaxE, Acc> &C) {
+    if (P.dense) {
+        // QUIO: a^(1) = h_k + sum_j J_kj z_j, a^(2) = J_kk (Sec. 3.2, the c^(1), c^(2) of QUIO)
+#pragma unroll
+        for (int m = 0; m <= kMaxE; ++m) C.a[m] = 0;
+        C.a[1] = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane)) + (Acc)P.h[k];
+        if (kMaxE >= 2) C.a[kMaxE >= 2 ? 2 : 1] = (Acc)P.d[k];
+        return;
+    }
     Acc part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
@@ -267,9 +314,14 @@ __device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE, Acc> &C, int64
 
 // dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
 template <typename Acc, typename ZT>
-__device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z, int32_t row,
+__device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
                                                 int32_t deg, int64_t zk, int64_t v, int lane,
                                                 const IncRec &r0, uint64_t coef0) {
+    if (P.dense) {
+        const Acc a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane)) + (Acc)P.h[k];
+        const Acc d = a1 * (Acc)(v - zk) + (Acc)P.d[k] * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk);
+        return to_i64<Acc>(d);
+    }
     int e;
     Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
     Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
@@ -457,6 +509,25 @@ __device__ __forceinline__ void init_state(const DevProblem &P, ZT *z, const int
 // This wave's share of E(z) = sum_t J_t prod z (threads tid, tid+nthr, ... take the terms).
 template <typename ZT>
 __device__ __forceinline__ int64_t energy_part(const DevProblem &P, const ZT *z, int tid, int nthr) {
+    if (P.dense) {
+        // rows k = g, g + G, ... of the upper triangle, lanes across the row
+        const int lane = tid & (kWave - 1), g = tid / kWave, G = nthr / kWave;
+        uint64_t acc = 0;
+        for (int32_t k = g; k < P.n; k += G) {
+            const int64_t zk = z[k];
+            if (lane == 0) acc += (uint64_t)zk * (uint64_t)(P.h[k] + P.d[k] * zk);
+            uint64_t racc = 0;
+            if (P.jbytes == 1) {
+                const int8_t *row = (const int8_t *)P.jd + (size_t)k * P.row_stride;
+                for (int32_t j = k + 1 + lane; j < P.n; j += kWave) racc += (uint64_t)(int64_t)row[j] * (uint64_t)(int64_t)z[j];
+            } else {
+                const int32_t *row = (const int32_t *)P.jd + (size_t)k * P.row_stride;
+                for (int32_t j = k + 1 + lane; j < P.n; j += kWave) racc += (uint64_t)(int64_t)row[j] * (uint64_t)(int64_t)z[j];
+            }
+            acc += racc * (uint64_t)zk;
+        }
+        return (int64_t)wave_sum_u64(acc);
+    }
     uint64_t eacc = 0;
     for (int32_t t = tid; t < P.n_terms; t += nthr) {
         uint64_t prod = (uint64_t)P.t_coef[t];
@@ -527,23 +598,23 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     if (kRule == SA_METROPOLIS) {
                         v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                         if (v >= zk) v += 1;
-                        d = direct_delta<Acc, ZT>(P, z, row, deg, zk, v, lane, crec, ccoef);
+                        d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef);
                         accept = metropolis_accept(d, beta, U);
                     } else if (kRule == SA_HEAT_BATH) {
                         Coeffs<kMaxE, Acc> C;
-                        row_coeffs<kMaxE, Acc, ZT>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                        row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
                         v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane);
                         d = poly_delta(C, zk, v);
                         accept = true;
                     } else {
                         if ((double)r0 * 0x1p-32 < r_opt) {
                             Coeffs<kMaxE, Acc> C;
-                            row_coeffs<kMaxE, Acc, ZT>(P, z, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
+                            row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
                             v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;
-                            d = direct_delta<Acc, ZT>(P, z, row, deg, zk, v, lane, crec, ccoef);
+                            d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef);
                         }
                         accept = metropolis_accept(d, beta, U);
                     }
@@ -706,15 +777,8 @@ __global__ void __launch_bounds__(256) energy_kernel(DevProblem P, const int32_t
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int idx = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
     if (idx >= n_states) return;
-    const int32_t *z = states + (size_t)idx * P.n;
-    uint64_t acc = 0;
-    for (int32_t t = lane; t < P.n_terms; t += kWave) {
-        uint64_t prod = (uint64_t)P.t_coef[t];
-        for (int32_t f = P.t_off[t]; f < P.t_off[t + 1]; ++f) prod *= (uint64_t)(int64_t)z[P.t_var[f]];
-        acc += prod;
-    }
-    const uint64_t E = wave_sum_u64(acc);
-    if (lane == 0) out[idx] = (int64_t)E;
+    const int64_t E = energy_part(P, states + (size_t)idx * P.n, lane, kWave);
+    if (lane == 0) out[idx] = E;
 }
 
 using KernelFn = void (*)(AnnealArgs);

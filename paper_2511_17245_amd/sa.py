@@ -48,7 +48,8 @@ class sa_opts(C.Structure):
 class sa_plan_info(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("n_terms", C.c_int64), ("n_incidences", C.c_int64),
                 ("n_factor_slots", C.c_int64), ("max_exponent", C.c_int32), ("max_width", C.c_int32),
-                ("device_bytes", C.c_int64), ("coef_bits", C.c_int32), ("arith_bits", C.c_int32)]
+                ("device_bytes", C.c_int64), ("coef_bits", C.c_int32), ("arith_bits", C.c_int32),
+                ("dense", C.c_int32)]
 
 
 class sa_launch_info(C.Structure):

@@ -18,6 +18,9 @@ def mixed_items(n=18, sweeps=30, reads=6):
     """Uneven sizes, widths, orders and rules, drawn like the 512-instance batch but small."""
     items = I.cfg4_batch(n_instances=n, n_reads=reads, n_sweeps=sweeps, n_min=20, n_max=700,
                          w_min=2, w_max=300)
+    r = np.random.Generator(np.random.PCG64(8))
+    items.append(I.Workload(I.dense_quio(160, -30, 30, 10, 10, r), sa.HEAT_BATH, sweeps, reads, 5, 901))
+    items.append(I.Workload(I.dense_quio(70, -4, 4, 400, 50, r), sa.OPT_METROPOLIS, sweeps, reads, 6, 902))
     # explicit schedules for some problems, automatic for the others
     for i, w in enumerate(items):
         if i % 4 == 0:

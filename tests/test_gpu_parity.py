@@ -69,6 +69,8 @@ def small_cases():
                                              fixed.coef, np.r_[fixed.lower, [-3] * 5],
                                              np.r_[fixed.upper, [3] * 5]), 30, 16, RULES
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 50, 64, RULES
+    yield "dense_int32_couplings_n70", I.dense_quio(70, -20, 20, 1000, 1000, r), 40, 24, RULES
+    yield "dense_no_diagonal_n150", I.fully_connected(150, 1, 3), 30, 16, RULES
     yield "many_reads_n50", I.random_huio(50, 200, [2, 3], -3, 3, 3, r), 20, 2048, RULES
 
 
@@ -89,7 +91,8 @@ def test_cooperating_waves_match_sequential_sweep(rule):
     # G waves per replica update the variables of a window (no shared term) at the same time;
     # the result must equal the sequential index-order sweep for every G
     r = rng(55)
-    cases = [("er_quio", I.erdos_renyi_quio(700, 5.0, -20, 20, 10, 10, r)),
+    cases = [("dense", I.dense_quio(90, -5, 5, 10, 10, r)),
+             ("er_quio", I.erdos_renyi_quio(700, 5.0, -20, 20, 10, 10, r)),
              ("huio_powers", I.random_huio(400, 1200, [1, 2, 3, 4], -6, 6, 4, r)),
              ("ml_long", I.multilinear(150, 7, 2))]
     for name, prob in cases:
@@ -154,9 +157,14 @@ def test_otm_fixed_r():
 
 
 def test_energy_kernel_and_one_shot_api():
+    r = rng(3)
+    for dense in (I.dense_quio(130, -50, 50, 10, 10, r), I.dense_quio(75, -9, 9, 500, 30, r)):
+        assert sa.Plan(dense, sa.METROPOLIS).info()["dense"] == 1
+        Pd = oracle.Poly(dense)
+        st = r.integers(dense.lower, dense.upper + 1, size=(9, dense.n_vars)).astype(np.int32)
+        assert [int(x) for x in sa.energy(dense, st)] == [Pd.energy(s) for s in st]
     prob = I.cfg3_huio(n=400, m=4000).problem
     P = oracle.Poly(prob)
-    r = rng(3)
     states = r.integers(prob.lower, prob.upper + 1, size=(37, prob.n_vars)).astype(np.int32)
     say("sa_energy")
     e = sa.energy(prob, states)
