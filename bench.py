@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--reads", type=int, default=0, help="override the number of reads")
     ap.add_argument("--waves-per-replica", type=int, default=0,
                     help="wavefronts cooperating on one replica (0: automatic)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only copy a device buffer of this many MiB (counter calibration) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reads", type=int, default=32)
     ap.add_argument("--cpu-sweeps", type=int, default=100)
@@ -62,6 +64,43 @@ def workload(args):
     if args.reads:
         w.n_reads = args.reads
     return w
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP library sources: HBM traffic measured with counters applies only to the
+    kernels built from exactly these sources."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_17245_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key):
+    """HBM bytes per launch from the committed counter summary, or None when the kernels changed
+    since it was taken (or none exists)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(workload_key)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_probe(mib):
+    import torch
+    a = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": mib << 20}), flush=True)
 
 
 def cpu_baseline(w, beta, n_reads, n_sweeps):
@@ -255,6 +294,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        return copy_probe(args.copy_probe_mib)
     if args.config == "cfg4":
         return bench_batch(args)
     if args.config == "cfg5":
@@ -292,17 +333,18 @@ def main():
 
     e_host = e.cpu().numpy()
     W_mean = float(np.mean(prob.upper.astype(np.int64) - prob.lower + 1))
+    traffic = measured_traffic(f"{args.config}:{S}:{R}")
     if w.rule == sa.HEAT_BATH:
         flops = updates * W_mean * FP64_FLOPS_PER_WEIGHT
         achieved = flops / (ms / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic}
     else:
         # Metropolis / OTM: instance bytes streamed per update (incidence records + coefficients)
         rec_bytes = info["n_incidences"] * (16 + 8) / n
         achieved = updates * rec_bytes / (ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic}
 
     out = {
         "metric": "single-variable updates/sec at 1 GPU",
@@ -315,9 +357,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int64+f64",
+        "dtype": f"int{info['arith_bits']}+f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n_vars": n, "n_sweeps": S, "n_reads": R,
+                   "kernel_source_hash": kernel_source_hash(),
                    "rule": sa.RULE_NAMES[w.rule], "n_terms": info["n_terms"],
                    "n_incidences": info["n_incidences"], "launch": launch,
                    "mean_final_energy": float(np.mean(e_host)), "min_final_energy": int(e_host.min()),
