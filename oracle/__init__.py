@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsa_oracle.so")
 SRC_PATH = os.path.join(HERE, "sa_oracle.c")
 
 OK, EINVAL, ERANGE, EUNSUPPORTED, ENOMEM, EINTERNAL = 0, -1, -2, -3, -4, -8
-METROPOLIS, HEAT_BATH, OPT_METROPOLIS = 0, 1, 2
+METROPOLIS, HEAT_BATH, OPT_METROPOLIS, HEAT_BATH_CLOSED = 0, 1, 2, 3
 
 
 def build(verbose: bool = False) -> str:

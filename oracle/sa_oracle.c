@@ -481,6 +481,36 @@ static int64_t heat_bath_choose(chain_ctx *c, int64_t lo, int64_t W, int32_t max
     return lo + W - 1; /* rounding put U*total at or above every cumulative weight */
 }
 
+/* Heat bath for a variable whose energy difference is linear in the change, dE(v) = a (v - z_k)
+ * (Sec. 3.3.2, multilinear case).  Index i = v - l_k has probability proportional to
+ * exp(-beta a i); the paper inverts its cumulative distribution,
+ *     x = -(T/a) ln[1 - U (1 - exp(-a W / T))],   v = l_k + ceil(x) - 1,
+ * (its change dz = ceil(x - (z_k - l_k + 1))).  Written with c = beta |a|:
+ *   a > 0:  x = g(U)        with g(q) = -log1p(q expm1(-c W)) / c,
+ *   a < 0:  x = W - g(1-U)  (the same value; the paper's form overflows exp(+c W) here),
+ * and ceil(x) - 1 is clamped to [0, W-1] (rounding at the ends; NaN cannot occur for c > 0).
+ * With a = 0 or beta = 0 the distribution is uniform: v = l_k + floor(x1 W / 2^32). */
+static int64_t heat_bath_closed(int64_t a, int64_t lo, int64_t W, double beta, double U,
+                                uint32_t x1) {
+    double c = beta * (double)(a < 0 ? -a : a);
+    if (a == 0 || !(c > 0.0)) return lo + (int64_t)(((uint64_t)x1 * (uint64_t)W) >> 32);
+    double Wd = (double)W;
+    double m = expm1(-(c * Wd));
+    double x;
+    if (a > 0)
+        x = -log1p(U * m) / c;
+    else
+        x = Wd + log1p((1.0 - U) * m) / c;
+    int64_t i;
+    if (!(x > 0.0))
+        i = 0;
+    else if (x >= Wd)
+        i = W - 1;
+    else
+        i = (int64_t)ceil(x) - 1;
+    return lo + i;
+}
+
 /* Returns 1 if z_k changed; *dE is the energy change applied. */
 static int update_variable(chain_ctx *c, int32_t *z, int32_t k, uint32_t s, uint32_t read,
                            double beta, double r_opt, int64_t *dE) {
@@ -505,7 +535,11 @@ static int update_variable(chain_ctx *c, int32_t *z, int32_t k, uint32_t s, uint
         v = metropolis_proposal(x[1], lo, W, zk);
         d = delta_from_coeffs(a, maxe, zk, v);
         accept = metropolis_accept(d, beta, U);
-    } else if (c->rule == SAO_HEAT_BATH) {
+    } else if (c->rule == SAO_HEAT_BATH_CLOSED && maxe <= 1) {
+        v = heat_bath_closed(maxe == 1 ? a[1] : 0, lo, W, beta, U, x[1]);
+        d = delta_from_coeffs(a, maxe, zk, v);
+        accept = 1;
+    } else if (c->rule == SAO_HEAT_BATH || c->rule == SAO_HEAT_BATH_CLOSED) {
         v = heat_bath_choose(c, lo, W, maxe, zk, beta, U);
         d = delta_from_coeffs(a, maxe, zk, v);
         accept = 1;
@@ -570,7 +604,7 @@ static int ctx_init(chain_ctx *c, const sao_poly *p, int rule, uint64_t seed, ui
     c->inst = inst;
     c->a = (int64_t *)malloc(sizeof(int64_t) * (p->max_exp + 1));
     if (!c->a) return SAO_ENOMEM;
-    if (rule == SAO_HEAT_BATH) {
+    if (rule == SAO_HEAT_BATH || rule == SAO_HEAT_BATH_CLOSED) {
         c->w = (double *)malloc(sizeof(double) * p->max_width);
         if (!c->w) return SAO_ENOMEM;
     }
@@ -706,7 +740,7 @@ static int run_jobs(job_t *tmpl, int n_threads, void *(*fn)(void *)) {
 }
 
 static int check_rule(const sao_poly *p, int rule) {
-    if (rule < 0 || rule > 2) return SAO_EINVAL;
+    if (rule < 0 || rule > 3) return SAO_EINVAL;
     /* the optimal transition is defined for energy differences of degree <= 4 (Sec. 3.3.3) */
     if (rule == SAO_OPT_METROPOLIS && p->max_exp > 4) return SAO_EUNSUPPORTED;
     return SAO_OK;

@@ -35,6 +35,10 @@ extern "C" {
 #define SAO_METROPOLIS 0
 #define SAO_HEAT_BATH 1
 #define SAO_OPT_METROPOLIS 2
+/* Heat bath with the closed-form draw of Sec. 3.3.2 for every variable whose energy
+ * difference is linear in its change (it appears in no term with an exponent above one);
+ * other variables use the enumeration of SAO_HEAT_BATH. */
+#define SAO_HEAT_BATH_CLOSED 3
 
 typedef struct sao_poly sao_poly;
 

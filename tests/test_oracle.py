@@ -365,7 +365,8 @@ def test_fixed_beta_sampling_is_boltzmann(rule):
             assert brute.chi2_pvalue(counts, probs) > 1e-4
 
 
-@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS])
+@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS,
+                                  oracle.HEAT_BATH_CLOSED])
 def test_tracked_energy_equals_recomputed(rule):
     r = rng(500 + rule)
     p = I.tiny_random(r, 12, -6, 9, 60, 4)
@@ -377,7 +378,8 @@ def test_tracked_energy_equals_recomputed(rule):
         assert np.all(row >= p.lower) and np.all(row <= p.upper)
 
 
-@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS])
+@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS,
+                                  oracle.HEAT_BATH_CLOSED])
 def test_coefficient_cache_matches_recompute(rule):
     # the paper's incremental coefficient update (Sec. 3.2) keeps a_k^(m) equal to a fresh
     # recomputation, so both modes give identical trajectories
@@ -401,7 +403,8 @@ def test_otm_with_r_zero_is_metropolis():
     assert np.array_equal(za, zb) and np.array_equal(ea, eb)
 
 
-@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS])
+@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS,
+                                  oracle.HEAT_BATH_CLOSED])
 def test_resume_is_exact(rule):
     # counter-based draws make (z, sweep) a complete checkpoint
     r = rng(800 + rule)
@@ -499,3 +502,109 @@ def test_sampled_reads_reproduce_full_run():
     ids = [19, 0, 7, 7, 12]
     zs, es = P.anneal_reads(oracle.OPT_METROPOLIS, beta, ids, seed=4)
     assert np.array_equal(zs, z[ids]) and np.array_equal(es, e[ids])
+
+
+# ---------------------------------------------------------------------------------------------
+# Heat bath with the closed-form (inverse-transform) draw for linear energy differences
+# (Sec. 3.3.2, multilinear case)
+# ---------------------------------------------------------------------------------------------
+
+def _linear_probe(a, lo, hi, zk=None):
+    """Variable 0 with dE(v) = a (v - z_0) for any state: E = a z_0 + (a pair term with a fixed
+    partner, so the variable is not isolated)."""
+    # z_1 is fixed to 1, so a*z_0 = (a - 3) z_0 + 3 z_0 z_1
+    terms = [(a - 3, [0]), (3, [0, 1])] if a != 3 else [(3, [0, 1])]
+    p = I.from_terms(2, terms, [lo, 1], [hi, 1])
+    z = np.array([lo if zk is None else zk, 1])
+    return p, z
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.05, 0.4, 3.0])
+def test_closed_form_heat_bath_single_step(beta):
+    # the inverse-transform draw has the heat-bath kernel exp(-beta dE_v) / sum exp(-beta dE_j)
+    cases = [(0, -3, 4), (1, -3, 4), (-1, -3, 4), (2, 0, 1), (-5, 0, 1), (7, -50, 50), (-3, -50, 50),
+             (40, -1, 5), (-40, -1, 5), (1, -1000, 1000), (-1, 0, 2000)]
+    n = 60_000
+    for a, lo, hi in cases:
+        for zk in (lo, (lo + hi) // 2, hi):
+            p, z = _linear_probe(a, lo, hi, zk)
+            P = oracle.Poly(p)
+            dE = brute.deltas(p, z, 0)
+            assert all(dE[v] == a * (v - zk) for v in dE)
+            c = _one_step_distribution(P, oracle.HEAT_BATH_CLOSED, z, 0, beta, 0.0, n)
+            _assert_matches(c, _heat_bath_kernel(dE, beta))
+
+
+def test_closed_form_heat_bath_is_the_exact_inverse_cdf():
+    # v = l + min{i : CDF(i) >= U}, with CDF(i) = sum_{j<=i} w_j / sum_j w_j, w_j = exp(-beta a j)
+    # evaluated at 40 digits from the definition; U is the read's uniform number (Philox words
+    # x2, x3 of counter (variable, sweep, read, instance)).
+    import mpmath
+    mpmath.mp.dps = 40
+    seed, s = 1234, 5
+    for a, lo, hi, beta in [(3, -10, 10, 0.2), (-2, 0, 30, 0.05), (1, -50, 50, 0.013),
+                            (-9, -5, 5, 0.9), (25, 0, 7, 0.01), (-1, -500, 500, 0.002)]:
+        p, z = _linear_probe(a, lo, hi, (lo + hi) // 2)
+        P = oracle.Poly(p)
+        n = 3000
+        v = P.single_step(oracle.HEAT_BATH_CLOSED, z, 0, s, beta, 0.0, n, seed=seed)
+        W = hi - lo + 1
+        w = [mpmath.exp(-mpmath.mpf(beta) * a * j) for j in range(W)]
+        tot = mpmath.fsum(w)
+        cdf, run = [], mpmath.mpf(0)
+        for x in w:
+            run += x
+            cdf.append(run / tot)
+        checked = 0
+        for r in range(n):
+            x = oracle.philox([0, s, r, 0], [seed & 0xFFFFFFFF, seed >> 32])
+            U = mpmath.mpf(int(((int(x[2]) << 32) | int(x[3])) >> 11)) / 2 ** 53
+            i = next(j for j in range(W) if cdf[j] >= U)
+            if min(abs(cdf[j] - U) for j in (i - 1, i) if j >= 0) < 1e-12:
+                continue   # U within rounding of a CDF step: either neighbour is acceptable
+            assert int(v[r]) == lo + i, (a, lo, hi, beta, r)
+            checked += 1
+        assert checked > 0.99 * n
+
+
+def test_closed_form_extreme_couplings_pick_the_end_of_the_box():
+    # |beta a W| far beyond the double range of exp(): all mass on one end, no overflow
+    for a, want in [(10 ** 12, "lo"), (-(10 ** 12), "hi")]:
+        p, z = _linear_probe(a, -1000, 1000, 0)
+        v = oracle.Poly(p).single_step(oracle.HEAT_BATH_CLOSED, z, 0, 0, 5.0, 0.0, 2000, seed=8)
+        assert np.all(v == (-1000 if want == "lo" else 1000))
+
+
+def test_closed_form_dispatch_uses_enumeration_for_variables_with_powers():
+    # every variable carries a square: the closed-form rule is the enumeration rule, draw for draw
+    r = rng(610)
+    n = 12
+    terms = [(int(r.integers(1, 4)), [i, i]) for i in range(n)]
+    terms += [(int(r.integers(-5, 6)), [int(r.integers(0, n)), int(r.integers(0, n))]) for _ in range(30)]
+    p = I.from_terms(n, terms, -4, 6)
+    P = oracle.Poly(p)
+    beta = P.schedule(40)[0]
+    za, ea = P.anneal(oracle.HEAT_BATH, beta, 32, seed=9)
+    zb, eb = P.anneal(oracle.HEAT_BATH_CLOSED, beta, 32, seed=9)
+    assert np.array_equal(za, zb) and np.array_equal(ea, eb)
+    # and on a multilinear problem the two rules draw differently but both track E exactly
+    q = I.erdos_renyi_quio(60, 4.0, -5, 5, 5, 5, rng(611))
+    Q = oracle.Poly(q)
+    zc, ec = Q.anneal(oracle.HEAT_BATH_CLOSED, Q.schedule(30)[0], 16, seed=3)
+    assert all(int(ec[i]) == brute.energy_raw(q, zc[i]) for i in range(16))
+
+
+def test_closed_form_fixed_beta_sampling_is_boltzmann():
+    # mixed problem: z_0, z_1 multilinear (closed form), z_2 carries a cube (enumeration)
+    cases = [I.from_terms(3, [(2, [0, 1]), (-1, [1, 2]), (1, [0, 1, 2]), (-1, [0]), (1, [2])], -2, 2),
+             I.from_terms(3, [(1, [0, 1]), (-1, [1, 2]), (1, [2, 2, 2]), (-2, [0])], -2, 2)]
+    for p in cases:
+        P = oracle.Poly(p)
+        for beta in (0.1, 0.25):    # larger beta: 60-100 sweeps no longer mix these landscapes
+            z, _ = P.anneal(oracle.HEAT_BATH_CLOSED, np.full(100, beta), 40_000, seed=77)
+            states, probs = brute.boltzmann(p, beta)
+            index = {s: i for i, s in enumerate(states)}
+            counts = np.zeros(len(states))
+            for row in z:
+                counts[index[tuple(int(x) for x in row)]] += 1
+            assert brute.chi2_pvalue(counts, probs) > 1e-4
