@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2",
-                    choices=["cfg1", "cfg2", "cfg3-otm", "cfg3-metropolis", "cfg4", "cfg5"])
+                    choices=["cfg1", "cfg2", "cfg2-closed", "cfg3-otm", "cfg3-metropolis", "cfg4",
+                             "cfg5"])
     ap.add_argument("--requests", type=int, default=300, help="cfg5: requests in the stream")
     ap.add_argument("--load", type=float, default=0.8, help="cfg5: arrival rate / saturated rate")
     ap.add_argument("--plain-sample", type=int, default=48,
@@ -45,6 +46,8 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB (counter calibration) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closed-form", action="store_true",
+                    help="cfg2: skip timing the closed-form heat-bath draw beside the enumeration")
     ap.add_argument("--cpu-reads", type=int, default=32)
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     return ap.parse_args()
@@ -54,8 +57,12 @@ def workload(args):
     from paper_2511_17245_amd import inputs as I
     if args.config == "cfg1":
         w = I.cfg1_dense_quio()
-    elif args.config == "cfg2":
+    elif args.config in ("cfg2", "cfg2-closed"):
         w = I.cfg2_sparse_quio()
+        if args.config == "cfg2-closed":
+            # the same workload with the closed-form heat-bath draw (every variable is linear)
+            w.rule = I.RULES["heat_bath_closed"]
+            w.name = w.name.replace("heat bath", "heat bath (closed-form draw)")
     else:
         w = I.cfg3_huio(rule=args.config.split("-")[1])
     if args.sweeps:
@@ -367,6 +374,27 @@ def main():
                    "wall_s": wall},
         "roofline": roof,
     }
+    if args.config == "cfg2" and not args.no_closed_form:
+        # the paper's O(1) heat-bath draw on the same workload (its variables are all linear)
+        cplan = sa.Plan(prob, sa.HEAT_BATH_CLOSED)
+
+        def cstep():
+            cplan.run_device(S, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
+                             instance_id=w.instance_id, waves_per_replica=args.waves_per_replica)
+
+        cstep()
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            cstep()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        cms = start.elapsed_time(stop) / args.steps
+        ce = e.cpu().numpy()
+        out["heat_bath_closed_form"] = {"value": updates / (cms / 1e3), "unit": "updates/s", "ms_per_step": cms,
+                                        "speedup_over_enumeration": ms / cms, "launch": cplan.last_launch(),
+                                        "mean_final_energy": float(np.mean(ce)), "min_final_energy": int(ce.min())}
+        cplan.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, beta, min(args.cpu_reads, R), min(args.cpu_sweeps, S))

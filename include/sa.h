@@ -5,7 +5,8 @@
  * Method: K. Suzuki, "Simulated Annealing for Quadratic and Higher-Order Unconstrained Integer
  * Optimization", arXiv:2511.17245.  The library runs the paper's single-variable update sweep
  * (Sec. 3.1) with the energy difference of Sec. 3.2 and the three transition rules of Sec. 3.3
- * (Metropolis, heat bath, optimal-transition Metropolis) as HIP kernels, one replica (read) per
+ * (Metropolis, heat bath, optimal-transition Metropolis; the heat bath also with the closed-form
+ * draw of Sec. 3.3.2 for linear energy differences) as HIP kernels, one replica (read) per
  * 64-lane wavefront.
  *
  * Conventions shared by every entry point
@@ -49,6 +50,9 @@ extern "C" {
 #define SA_METROPOLIS 0        /* uniform nonzero change, accept min[1, exp(-dE/T)]   (Sec. 3.3.1) */
 #define SA_HEAT_BATH 1         /* draw the new value with probability exp(-dE/T)/sum  (Sec. 3.3.2) */
 #define SA_OPT_METROPOLIS 2    /* optimal transition with probability r = s/(S-1)     (Sec. 3.3.3) */
+#define SA_HEAT_BATH_CLOSED 3  /* heat bath; a variable whose dE is linear in its new value (no
+                                  exponent above one) takes the O(1) inverse-transform draw of
+                                  Sec. 3.3.2, the others the enumeration of SA_HEAT_BATH */
 
 /* ---- problem description (Sec. 2) ----------------------------------------------------------
  * E(z) = sum_t coef[t] * prod_{f = term_ptr[t]}^{term_ptr[t+1]-1} z[factor_var[f]].
@@ -99,7 +103,7 @@ typedef struct {
     double otm_r;               /* < 0: r = s/(S-1) as in Sec. 3.3.3 (default); else a fixed r */
     int32_t waves_per_replica;  /* 0: automatic.  G > 1 lets G wavefronts of one replica update G
                                    consecutive variables that share no term at the same time (the
-                                   result is identical to the sequential sweep); 1, 2, 4 or 8 */
+                                   result is identical to the sequential sweep); 1, 2, 4, 8 or 16 */
 } sa_opts;
 
 void sa_opts_default(sa_opts *opts);

@@ -89,12 +89,12 @@ int upload_packed(const sa::Packed &pk, sa_plan *plan) {
 }
 
 int check_rule_support(int rule, int32_t max_exp) {
-    if (rule < SA_METROPOLIS || rule > SA_OPT_METROPOLIS) return fail(SA_EINVAL, "unknown rule");
+    if (rule < SA_METROPOLIS || rule > SA_HEAT_BATH_CLOSED) return fail(SA_EINVAL, "unknown rule");
     if (rule == SA_OPT_METROPOLIS && max_exp > 4)
         return fail(SA_EUNSUPPORTED,
                     "optimal-transition Metropolis needs every exponent <= 4 (energy difference of "
                     "degree <= 4)");
-    if (rule == SA_HEAT_BATH && max_exp > sa::kMaxExpPoly)
+    if ((rule == SA_HEAT_BATH || rule == SA_HEAT_BATH_CLOSED) && max_exp > sa::kMaxExpPoly)
         return fail(SA_EUNSUPPORTED, "heat bath supports exponents up to 16 on the GPU");
     return SA_OK;
 }
@@ -227,7 +227,7 @@ int auto_waves_per_replica(sa_plan *plan, int32_t n_reads, int device) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     const int64_t max_waves = (int64_t)cus * 4 * 8;
-    for (int G = 8; G > 1; G /= 2) {
+    for (int G = 16; G > 1; G /= 2) {
         if ((int64_t)n_reads * G > max_waves) continue;
         if (sa::shared_state_bytes(plan->dp.n, G) > max_lds) continue;
         sa_plan::Sched *sc = nullptr;
@@ -306,9 +306,9 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     a.z_out = z_dev;
     a.e_out = e_dev;
     int G = opts.waves_per_replica;
-    if (G != 0 && G != 1 && G != 2 && G != 4 && G != 8) {
+    if (G != 0 && G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
         if (tmp) (void)hipFree(tmp);
-        return fail(SA_EINVAL, "waves_per_replica must be 0, 1, 2, 4 or 8");
+        return fail(SA_EINVAL, "waves_per_replica must be 0, 1, 2, 4, 8 or 16");
     }
     if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
     sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,

@@ -66,7 +66,8 @@ std::map<std::string, Tuned> g_tune_cache;  // batch shape -> tuned choice
 double update_cost(const sa_plan &p) {
     const double chunks = 1.0 + (double)p.info.n_incidences / std::max(1, p.info.n_vars) / 64.0;
     const double per_lane = std::ceil(p.info.max_width / 64.0);
-    if (p.rule == SA_HEAT_BATH) return chunks + 3.0 * per_lane;
+    if (p.rule == SA_HEAT_BATH_CLOSED && p.info.max_exponent <= 1) return chunks + 2.0;
+    if (p.rule == SA_HEAT_BATH || p.rule == SA_HEAT_BATH_CLOSED) return chunks + 3.0 * per_lane;
     if (p.rule == SA_OPT_METROPOLIS) return chunks + 1.0 + 0.5 * per_lane;
     return chunks + 1.0;
 }

@@ -461,6 +461,28 @@ __device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE, Acc> &C, i
     return wave_min_i32(best == dbest ? bv : INT32_MAX);
 }
 
+// Heat bath for a variable whose energy difference is linear, dE(v) = a (v - z_k) (Sec. 3.3.2,
+// multilinear case): the inverse of the cumulative distribution in O(1).  Index i = v - lo has
+// probability proportional to exp(-beta a i); with c = beta |a| and g(q) = -log1p(q expm1(-c W)) / c
+// the paper's x = -(T/a) ln[1 - U (1 - exp(-a W / T))] is g(U) for a > 0 and W - g(1 - U) for a < 0
+// (the same value without overflowing exp(c W)); v = lo + ceil(x) - 1, clamped to the box.  a = 0
+// or beta = 0 is the uniform distribution, drawn from x1 by a multiply-high.  Wave-uniform.
+__device__ __forceinline__ int64_t heat_bath_closed(int64_t a, int64_t lo, int64_t W, double beta, double U,
+                                                    uint32_t x1) {
+    const double c = beta * (double)(a < 0 ? -a : a);
+    if (a == 0 || !(c > 0.0)) return lo + (int64_t)(((uint64_t)x1 * (uint64_t)W) >> 32);
+    const double Wd = (double)W;
+    const double m = expm1(-(c * Wd));
+    double x;
+    if (a > 0)
+        x = -log1p(U * m) / c;
+    else
+        x = Wd + log1p((1.0 - U) * m) / c;
+    if (!(x > 0.0)) return lo;
+    if (x >= Wd) return lo + W - 1;
+    return lo + (int64_t)ceil(x) - 1;
+}
+
 // ------------------------------------------------------------------------------------------------
 // The annealing kernel.
 //
@@ -600,10 +622,15 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         if (v >= zk) v += 1;
                         d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef);
                         accept = metropolis_accept(d, beta, U);
-                    } else if (kRule == SA_HEAT_BATH) {
+                    } else if (kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED) {
                         Coeffs<kMaxE, Acc> C;
-                        row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
-                        v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane);
+                        const uint32_t em = lane_read32(sl.emask, j);
+                        row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
+                        // closed form where dE is linear in the new value (no exponent above one)
+                        if (kRule == SA_HEAT_BATH_CLOSED && (kMaxE == 1 || (em & ~2u) == 0))
+                            v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, r1);
+                        else
+                            v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane);
                         d = poly_delta(C, zk, v);
                         accept = true;
                     } else {
@@ -634,8 +661,10 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
 // ------------------------------------------------------------------------------------------------
 // Plain launch: one instance, n_reads replicas.
 // ------------------------------------------------------------------------------------------------
-template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc>
-__global__ void __launch_bounds__(512) anneal_kernel(AnnealArgs A) {
+// kThreads: 512 (up to 8 waves per replica) or 1024 (16 waves; fewer registers per lane, so only
+// the variants that need no more than 128 VGPRs are built that way).
+template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc, int kThreads>
+__global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
     extern __shared__ int32_t lds_state[];
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
@@ -749,6 +778,13 @@ __global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B)
                 case 8: E += sweep_replica<SA_HEAT_BATH, true, 8, kMaxE, Acc, ZT>(R, z, lane); break;
                 default: E += sweep_replica<SA_HEAT_BATH, true, 0, kMaxE, Acc, ZT>(R, z, lane); break;
             }
+        } else if (D.rule == SA_HEAT_BATH_CLOSED) {
+            switch (D.chunk) {
+                case 1: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 1, kMaxE, Acc, ZT>(R, z, lane); break;
+                case 2: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 2, kMaxE, Acc, ZT>(R, z, lane); break;
+                case 8: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 8, kMaxE, Acc, ZT>(R, z, lane); break;
+                default: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 0, kMaxE, Acc, ZT>(R, z, lane); break;
+            }
         } else {
             E += sweep_replica<SA_OPT_METROPOLIS, true, 0, kOtmE, Acc, ZT>(R, z, lane);
         }
@@ -785,14 +821,57 @@ using KernelFn = void (*)(AnnealArgs);
 
 // Heat bath: the weights of ceil(W/64) <= kRegChunk values per lane stay in registers (the
 // unrolled loops then cost kRegChunk steps); wider ranges recompute them (kRegChunk = 0).
-template <int kMaxE, typename Acc>
+template <int kRule, int kMaxE, typename Acc>
 KernelFn pick_heat_bath_lds(int reg_chunk) {
     switch (reg_chunk) {
-        case 1: return anneal_kernel<SA_HEAT_BATH, true, 1, kMaxE, Acc>;
-        case 2: return anneal_kernel<SA_HEAT_BATH, true, 2, kMaxE, Acc>;
-        case 8: return anneal_kernel<SA_HEAT_BATH, true, 8, kMaxE, Acc>;
-        case 32: return anneal_kernel<SA_HEAT_BATH, true, 32, kMaxE, Acc>;
-        default: return anneal_kernel<SA_HEAT_BATH, true, 0, kMaxE, Acc>;
+        case 1: return anneal_kernel<kRule, true, 1, kMaxE, Acc, 512>;
+        case 2: return anneal_kernel<kRule, true, 2, kMaxE, Acc, 512>;
+        case 8: return anneal_kernel<kRule, true, 8, kMaxE, Acc, 512>;
+        case 32: return anneal_kernel<kRule, true, 32, kMaxE, Acc, 512>;
+        default: return anneal_kernel<kRule, true, 0, kMaxE, Acc, 512>;
+    }
+}
+template <int kRule, int kMaxE, typename Acc>
+KernelFn pick_heat_bath_lds_16(int reg_chunk) {
+    switch (reg_chunk) {
+        case 1: return anneal_kernel<kRule, true, 1, kMaxE, Acc, 1024>;
+        case 2: return anneal_kernel<kRule, true, 2, kMaxE, Acc, 1024>;
+        default: return anneal_kernel<kRule, true, 8, kMaxE, Acc, 1024>;
+    }
+}
+
+// Variants built for 16 waves per replica (their register needs fit 128 VGPRs): states in LDS,
+// every exponent <= 2, at most 8 heat-bath weights per lane, and the closed-form heat bath only
+// when every variable takes the closed form.
+bool sixteen_waves_ok(int rule, bool in_lds, int reg_chunk, int maxe_class) {
+    if (!in_lds || maxe_class > 2) return false;
+    if (rule == SA_HEAT_BATH) return reg_chunk >= 1 && reg_chunk <= 8;
+    if (rule == SA_HEAT_BATH_CLOSED) return maxe_class == 1;
+    return true;
+}
+
+KernelFn pick_kernel_16(int rule, int reg_chunk, int maxe_class, bool narrow) {
+    switch (rule) {
+        case SA_METROPOLIS:
+            return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t, 1024>
+                          : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t, 1024>;
+        case SA_OPT_METROPOLIS:
+            if (maxe_class == 1)
+                return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t, 1024>
+                              : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t, 1024>;
+            return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint32_t, 1024>
+                          : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint64_t, 1024>;
+        case SA_HEAT_BATH:
+            if (maxe_class == 1)
+                return narrow ? pick_heat_bath_lds_16<SA_HEAT_BATH, 1, uint32_t>(reg_chunk)
+                              : pick_heat_bath_lds_16<SA_HEAT_BATH, 1, uint64_t>(reg_chunk);
+            return narrow ? pick_heat_bath_lds_16<SA_HEAT_BATH, 2, uint32_t>(reg_chunk)
+                          : pick_heat_bath_lds_16<SA_HEAT_BATH, 2, uint64_t>(reg_chunk);
+        case SA_HEAT_BATH_CLOSED:
+            return narrow ? anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint32_t, 1024>
+                          : anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint64_t, 1024>;
+        default:
+            return nullptr;
     }
 }
 
@@ -801,27 +880,41 @@ KernelFn pick_heat_bath_lds(int reg_chunk) {
 // memory (very large N) use one generic 64-bit variant per rule.
 KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool narrow) {
     if (rule == SA_METROPOLIS) {
-        if (!in_lds) return anneal_kernel<SA_METROPOLIS, false, 0, 1, uint64_t>;
-        return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t>
-                      : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t>;
+        if (!in_lds) return anneal_kernel<SA_METROPOLIS, false, 0, 1, uint64_t, 512>;
+        return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t, 512>
+                      : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t, 512>;
     }
     if (rule == SA_HEAT_BATH) {
-        if (!in_lds) return anneal_kernel<SA_HEAT_BATH, false, 0, kMaxExpPoly, uint64_t>;
+        if (!in_lds) return anneal_kernel<SA_HEAT_BATH, false, 0, kMaxExpPoly, uint64_t, 512>;
         switch (maxe_class) {
-            case 1: return narrow ? pick_heat_bath_lds<1, uint32_t>(reg_chunk) : pick_heat_bath_lds<1, uint64_t>(reg_chunk);
-            case 2: return narrow ? pick_heat_bath_lds<2, uint32_t>(reg_chunk) : pick_heat_bath_lds<2, uint64_t>(reg_chunk);
-            case 4: return pick_heat_bath_lds<4, uint64_t>(reg_chunk);
-            default: return pick_heat_bath_lds<kMaxExpPoly, uint64_t>(reg_chunk);
+            case 1: return narrow ? pick_heat_bath_lds<SA_HEAT_BATH, 1, uint32_t>(reg_chunk)
+                                  : pick_heat_bath_lds<SA_HEAT_BATH, 1, uint64_t>(reg_chunk);
+            case 2: return narrow ? pick_heat_bath_lds<SA_HEAT_BATH, 2, uint32_t>(reg_chunk)
+                                  : pick_heat_bath_lds<SA_HEAT_BATH, 2, uint64_t>(reg_chunk);
+            case 4: return pick_heat_bath_lds<SA_HEAT_BATH, 4, uint64_t>(reg_chunk);
+            default: return pick_heat_bath_lds<SA_HEAT_BATH, kMaxExpPoly, uint64_t>(reg_chunk);
+        }
+    }
+    if (rule == SA_HEAT_BATH_CLOSED) {
+        // every variable linear (class 1): no enumeration code at all
+        if (!in_lds) return anneal_kernel<SA_HEAT_BATH_CLOSED, false, 0, kMaxExpPoly, uint64_t, 512>;
+        switch (maxe_class) {
+            case 1: return narrow ? anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint32_t, 512>
+                                  : anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint64_t, 512>;
+            case 2: return narrow ? pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, 2, uint32_t>(reg_chunk)
+                                  : pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, 2, uint64_t>(reg_chunk);
+            case 4: return pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, 4, uint64_t>(reg_chunk);
+            default: return pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, kMaxExpPoly, uint64_t>(reg_chunk);
         }
     }
     if (rule == SA_OPT_METROPOLIS) {
-        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 0, 4, uint64_t>;
+        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 0, 4, uint64_t, 512>;
         switch (maxe_class) {
-            case 1: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t>
-                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t>;
-            case 2: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint32_t>
-                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint64_t>;
-            default: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 4, uint64_t>;
+            case 1: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t, 512>
+                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t, 512>;
+            case 2: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint32_t, 512>
+                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint64_t, 512>;
+            default: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 4, uint64_t, 512>;
         }
     }
     return nullptr;
@@ -848,6 +941,15 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
+    const bool heat_bath = rule == SA_HEAT_BATH || rule == SA_HEAT_BATH_CLOSED;
+    const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
+    const int reg_in_lds =
+        heat_bath && !(rule == SA_HEAT_BATH_CLOSED && max_exp <= 1)
+            ? (chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0)
+            : 0;
+    if (win_waves == 16 && !(shared_state_bytes(n, 16) <= max_lds &&
+                             sixteen_waves_ok(rule, true, reg_in_lds, maxe_class_of(max_exp))))
+        win_waves = 8;  // no 16-wave build of this variant: the next width gives the same result
     if (win_waves > 1 && shared_state_bytes(n, win_waves) <= max_lds) {
         // one replica per workgroup, its G waves share the state
         lc.win_waves = win_waves;
@@ -866,21 +968,20 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
         lc.groups = (n_reads + wpg - 1) / wpg;
         lc.lds_bytes = lc.state_in_lds ? (int)(per_wave * wpg) : 0;
     }
-    const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
-    int reg = 0;
-    if (rule == SA_HEAT_BATH && lc.state_in_lds)
-        reg = chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0;
+    const int reg = lc.state_in_lds ? reg_in_lds : 0;
     lc.maxe_class = lc.state_in_lds ? maxe_class_of(max_exp)
-                                    : (rule == SA_HEAT_BATH ? kMaxExpPoly : rule == SA_OPT_METROPOLIS ? 4 : 1);
+                                    : (heat_bath ? kMaxExpPoly : rule == SA_OPT_METROPOLIS ? 4 : 1);
     lc.reg_chunk = reg;
     lc.narrow = narrow_ok && lc.state_in_lds && lc.maxe_class <= 2;
-    lc.variant = rule * 100000 + (lc.narrow ? 10000 : 0) + lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
+    lc.variant = (lc.win_waves == 16 ? 1000000 : 0) + rule * 100000 + (lc.narrow ? 10000 : 0) +
+                 lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
     return lc;
 }
 
 int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
                   std::string &err) {
-    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class, lc.narrow);
+    KernelFn fn = lc.win_waves == 16 ? pick_kernel_16(rule, lc.reg_chunk, lc.maxe_class, lc.narrow)
+                                     : pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class, lc.narrow);
     if (!fn) {
         err = "unknown rule";
         return SA_EINVAL;

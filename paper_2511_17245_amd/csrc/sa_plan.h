@@ -49,7 +49,7 @@ struct sa_plan {
         int32_t n_win = 0;
         int32_t n_active = 0;  // variables that are not fixed
     };
-    Sched sched[9];
+    Sched sched[17];  // index G = 1, 2, 4, 8, 16
     ~sa_plan() {
         if (beta_dev) (void)hipFree(beta_dev);
         for (auto &sc : sched)

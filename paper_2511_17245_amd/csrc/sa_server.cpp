@@ -68,7 +68,8 @@ struct Request {
 double cost_of_update(const sa_plan &p) {
     const double chunks = 1.0 + (double)p.info.n_incidences / std::max(1, p.info.n_vars) / 64.0;
     const double per_lane = std::ceil(p.info.max_width / 64.0);
-    if (p.rule == SA_HEAT_BATH) return chunks + 3.0 * per_lane;
+    if (p.rule == SA_HEAT_BATH_CLOSED && p.info.max_exponent <= 1) return chunks + 2.0;
+    if (p.rule == SA_HEAT_BATH || p.rule == SA_HEAT_BATH_CLOSED) return chunks + 3.0 * per_lane;
     if (p.rule == SA_OPT_METROPOLIS) return chunks + 1.0 + 0.5 * per_lane;
     return chunks + 1.0;
 }
@@ -456,7 +457,7 @@ uint64_t enqueue(sa_server *S, std::unique_ptr<Request> req) {
 int check_request(const sa_schedule *sched, int32_t rule, int32_t n_reads, const sa_result *result) {
     if (!result || !result->states || !result->energies) return fail(SA_EINVAL, "result buffers are required");
     if (n_reads < 1) return fail(SA_EINVAL, "n_reads must be >= 1");
-    if (rule < SA_METROPOLIS || rule > SA_OPT_METROPOLIS) return fail(SA_EINVAL, "unknown rule");
+    if (rule < SA_METROPOLIS || rule > SA_HEAT_BATH_CLOSED) return fail(SA_EINVAL, "unknown rule");
     if (!sched || sched->n_sweeps < 1) return fail(SA_EINVAL, "n_sweeps must be >= 1");
     if (sched->beta)
         for (int32_t s = 0; s < sched->n_sweeps; ++s)

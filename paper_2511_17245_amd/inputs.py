@@ -201,7 +201,7 @@ def random_interaction(n, p, u, n_terms, rng, kmax=100, name=None) -> Problem:
 # Measured configurations
 # ----------------------------------------------------------------------------------------------
 
-RULES = {"metropolis": 0, "heat_bath": 1, "otm": 2}
+RULES = {"metropolis": 0, "heat_bath": 1, "otm": 2, "heat_bath_closed": 3}
 
 
 @dataclasses.dataclass

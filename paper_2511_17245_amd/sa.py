@@ -16,8 +16,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsa.so")
 
 OK, EINVAL, ERANGE, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
-METROPOLIS, HEAT_BATH, OPT_METROPOLIS = 0, 1, 2
-RULE_NAMES = {METROPOLIS: "metropolis", HEAT_BATH: "heat_bath", OPT_METROPOLIS: "otm"}
+METROPOLIS, HEAT_BATH, OPT_METROPOLIS, HEAT_BATH_CLOSED = 0, 1, 2, 3
+RULE_NAMES = {METROPOLIS: "metropolis", HEAT_BATH: "heat_bath", OPT_METROPOLIS: "otm",
+              HEAT_BATH_CLOSED: "heat_bath_closed"}
 
 
 class SAError(RuntimeError):

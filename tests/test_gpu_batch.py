@@ -21,6 +21,11 @@ def mixed_items(n=18, sweeps=30, reads=6):
     r = np.random.Generator(np.random.PCG64(8))
     items.append(I.Workload(I.dense_quio(160, -30, 30, 10, 10, r), sa.HEAT_BATH, sweeps, reads, 5, 901))
     items.append(I.Workload(I.dense_quio(70, -4, 4, 400, 50, r), sa.OPT_METROPOLIS, sweeps, reads, 6, 902))
+    # closed-form heat bath: all variables linear, and mixed with squared variables
+    items.append(I.Workload(I.erdos_renyi_quio(300, 6.0, -40, 40, 10, 20, r), sa.HEAT_BATH_CLOSED, sweeps,
+                            reads, 7, 903))
+    items.append(I.Workload(I.random_huio(120, 600, [1, 2, 3], -6, 9, 5, r), sa.HEAT_BATH_CLOSED, sweeps,
+                            reads, 8, 904))
     # explicit schedules for some problems, automatic for the others
     for i, w in enumerate(items):
         if i % 4 == 0:
@@ -59,7 +64,7 @@ def test_batch_equals_per_instance_and_oracle(mode):
     for i, w in enumerate(items):
         zp, ep = per_instance(w)
         assert np.array_equal(got[i][0], zp) and np.array_equal(got[i][1], ep), f"problem {i} vs plain"
-        if i % 3 == 0:
+        if i % 3 == 0 or w.rule == sa.HEAT_BATH_CLOSED:
             zo, eo = oracle_run(w)
             assert np.array_equal(got[i][0], zo) and np.array_equal(got[i][1], eo), f"problem {i} vs oracle"
     b.close()

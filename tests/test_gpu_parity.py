@@ -16,7 +16,7 @@ from paper_2511_17245_amd import sa
 
 pytestmark = pytest.mark.gpu
 
-RULES = [sa.METROPOLIS, sa.HEAT_BATH, sa.OPT_METROPOLIS]
+RULES = [sa.METROPOLIS, sa.HEAT_BATH, sa.OPT_METROPOLIS, sa.HEAT_BATH_CLOSED]
 
 
 def say(*a):
@@ -58,10 +58,13 @@ def small_cases():
     yield "cfg2_like_n1000", I.cfg2_sparse_quio(n=1000).problem, 40, 64, RULES
     yield "cfg3_like_n300", I.cfg3_huio(n=300, m=3000).problem, 100, 128, RULES
     yield "ml_p30_u1_long_terms", I.multilinear(100, 30, 1), 50, 16, RULES
-    yield "fc_p8_u2_high_power", I.fully_connected(30, 8, 2), 60, 16, [sa.METROPOLIS, sa.HEAT_BATH]
+    yield "fc_p8_u2_high_power", I.fully_connected(30, 8, 2), 60, 16, [sa.METROPOLIS, sa.HEAT_BATH,
+                                                                      sa.HEAT_BATH_CLOSED]
     yield "binary_qubo_n200", I.dense_quio(200, 0, 1, 5, 5, r), 40, 32, RULES
     yield "wide_w2001_regs", I.erdos_renyi_quio(64, 6.0, -1000, 1000, 10, 10, r), 12, 8, RULES
-    yield "wide_w5001_recompute", I.dense_quio(40, -2500, 2500, 3, 3, r), 6, 4, [sa.HEAT_BATH]
+    yield "wide_w5001_recompute", I.dense_quio(40, -2500, 2500, 3, 3, r), 6, 4, [sa.HEAT_BATH,
+                                                                                   sa.HEAT_BATH_CLOSED]
+    yield "linear_w2000001", I.erdos_renyi_quio(80, 5.0, -10 ** 6, 10 ** 6, 3, 3, r), 30, 16, [sa.HEAT_BATH_CLOSED]
     fixed = I.random_huio(90, 300, [1, 2, 3], -4, 4, 4, r)
     fixed.lower[::7] = 2
     fixed.upper[::7] = 2
@@ -99,10 +102,13 @@ def test_cooperating_waves_match_sequential_sweep(rule):
         P = oracle.Poly(prob)
         beta, _, _ = P.schedule(25)
         zo, eo = P.anneal(rule, beta, 12, seed=31)
-        for G in (1, 2, 4):
+        for G in (1, 2, 4, 8, 16):
             say("windows", name, sa.RULE_NAMES[rule], "G", G)
             zg, eg, launch = gpu_run(prob, rule, beta, 12, seed=31, G=G)
-            assert launch["waves_per_replica"] == G
+            # 16 waves only for the variants built that way; the others fall back to 8
+            assert launch["waves_per_replica"] == G or (G == 16 and launch["waves_per_replica"] == 8)
+            if G == 16 and name == "er_quio":
+                assert launch["waves_per_replica"] == 16
             assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]}/G={G} {launch}")
 
 
@@ -209,6 +215,12 @@ def full_size(w, n_sample, label):
 
 def test_cfg2_full_size_sampled():
     full_size(I.cfg2_sparse_quio(), 8, "cfg2")
+
+
+def test_cfg2_closed_form_full_size_sampled():
+    w = I.cfg2_sparse_quio()
+    w.rule = sa.HEAT_BATH_CLOSED
+    full_size(w, 16, "cfg2-closed")
 
 
 @pytest.mark.parametrize("rule", ["otm", "metropolis"])
