@@ -442,8 +442,10 @@ static int64_t metropolis_proposal(uint32_t x1, int64_t lo, int64_t W, int64_t z
 /* Heat bath (Sec. 3.3.2): P(v) = exp(-beta dE_v) / sum_j exp(-beta dE_j) over all W values
  * including the current one.  Weights are taken relative to the minimum dE (same ratios).
  * Summation order: value j belongs to block b = j / c with c = ceil(W/64); the 64 block sums
- * (left to right inside a block) are combined by a Kogge-Stone inclusive scan with strides
- * 1,2,4,...,32; value j's cumulative weight is (scan of block b-1) + (running sum inside b). */
+ * (left to right inside a block) are combined by an inclusive scan over four rows of 16 blocks:
+ * inside every row a Kogge-Stone scan with strides 1, 2, 4, 8; then rows 1 and 3 add the last
+ * entry of rows 0 and 2; then rows 2 and 3 add the (new) last entry of row 1.  Value j's
+ * cumulative weight is (scan of block b-1) + (running sum inside b). */
 static int64_t heat_bath_choose(chain_ctx *c, int64_t lo, int64_t W, int32_t maxe, int64_t zk,
                                 double beta, double U) {
     const int64_t *a = c->a;
@@ -464,10 +466,16 @@ static int64_t heat_bath_choose(chain_ctx *c, int64_t lo, int64_t W, int32_t max
         for (int64_t j = b * cpl; j < (b + 1) * cpl && j < W; ++j) s += w[j];
         incl[b] = s;
     }
-    for (int stride = 1; stride < 64; stride *= 2) {
+    for (int stride = 1; stride < 16; stride *= 2) {
         memcpy(tmp, incl, sizeof tmp);
-        for (int b = stride; b < 64; ++b) incl[b] = tmp[b] + tmp[b - stride];
+        for (int b = 0; b < 64; ++b)
+            if (b % 16 >= stride) incl[b] = tmp[b] + tmp[b - stride];
     }
+    double row0 = incl[15], row2 = incl[47];
+    for (int b = 16; b < 32; ++b) incl[b] = incl[b] + row0;
+    for (int b = 48; b < 64; ++b) incl[b] = incl[b] + row2;
+    double rows01 = incl[31];
+    for (int b = 32; b < 64; ++b) incl[b] = incl[b] + rows01;
     double total = incl[63];
     double thr = U * total;
     for (int b = 0; b < 64; ++b) {

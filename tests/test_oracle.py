@@ -608,3 +608,19 @@ def test_closed_form_fixed_beta_sampling_is_boltzmann():
             for row in z:
                 counts[index[tuple(int(x) for x in row)]] += 1
             assert brute.chi2_pvalue(counts, probs) > 1e-4
+
+
+@pytest.mark.parametrize("lo,hi", [(-50, 50), (0, 299), (-500, 499)])
+def test_heat_bath_single_step_wide_ranges(lo, hi):
+    # the blocked summation spans all four rows of 16 blocks once W > 48; its cumulative weights
+    # must still give the exact kernel exp(-beta dE_v) / sum_j exp(-beta dE_j)
+    r = rng(700 + hi)
+    terms = [(2, [0, 0]), (-3, [0, 1]), (5, [0]), (1, [1, 2])]
+    p = I.from_terms(3, terms, [lo, -4, -4], [hi, 4, 4])
+    P = oracle.Poly(p)
+    W = hi - lo + 1
+    for beta in (0.3 / W, 4.0 / W ** 2):
+        z = np.array([int(r.integers(lo, hi + 1)), int(r.integers(-4, 5)), int(r.integers(-4, 5))])
+        dE = brute.deltas(p, z, 0)
+        c = _one_step_distribution(P, oracle.HEAT_BATH, z, 0, beta, 0.0, 80_000)
+        _assert_matches(c, _heat_bath_kernel(dE, beta))
