@@ -70,6 +70,14 @@ __device__ __forceinline__ uint64_t dpp64(uint64_t x, uint64_t identity) {
                                                               kBankMask, false);
     return ((uint64_t)hi << 32) | lo;
 }
+// DPP move of a 64-bit value over all rows; lanes whose source lies outside their row read zero
+// (bound_ctrl), so no old value is needed.
+template <int kCtrl>
+__device__ __forceinline__ uint64_t dpp64_zero(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)x, kCtrl, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), kCtrl, 0xf, 0xf, true);
+    return ((uint64_t)hi << 32) | lo;
+}
 template <int kCtrl, int kRowMask, int kBankMask>
 __device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t identity) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, kCtrl, kRowMask, kBankMask, false);
@@ -119,15 +127,6 @@ __device__ __forceinline__ double wave_shift_up1(double x, double first) {
     const uint64_t b = dpp64<0x138, 0xf, 0xf>((uint64_t)__double_as_longlong(x),
                                               (uint64_t)__double_as_longlong(first));
     return __longlong_as_double((long long)b);
-}
-
-// Lane l receives lane (l - d)'s value for l >= d, else its own (ds_bpermute).
-__device__ __forceinline__ double wave_shift_up(double x, int d, int lane) {
-    const int src = lane >= d ? lane - d : lane;
-    const uint64_t b = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)b);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(b >> 32));
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Orders a lane's LDS/global state write before later reads by other lanes of the same wave.
@@ -345,10 +344,25 @@ __device__ __forceinline__ bool metropolis_accept(int64_t d, double beta, double
     return U < exp(-(beta * (double)d));
 }
 
+// Inclusive scan of one double per lane in the order of the DPP network: inside each row of 16
+// lanes a Kogge-Stone scan (row_shr 1, 2, 4, 8), then rows 1 and 3 add the last lane of rows 0
+// and 2 (row_bcast:15), then rows 2 and 3 add lane 31 (row_bcast:31).  Lanes without a source add
+// +0.0, which leaves a non-negative value unchanged.
+__device__ __forceinline__ double wave_scan_rows(double x) {
+    auto step = [](double v, uint64_t shifted) { return v + __longlong_as_double((long long)shifted); };
+    x = step(x, dpp64_zero<0x111>((uint64_t)__double_as_longlong(x)));
+    x = step(x, dpp64_zero<0x112>((uint64_t)__double_as_longlong(x)));
+    x = step(x, dpp64_zero<0x114>((uint64_t)__double_as_longlong(x)));
+    x = step(x, dpp64_zero<0x118>((uint64_t)__double_as_longlong(x)));
+    x = step(x, dpp64<0x142, 0xa, 0xf>((uint64_t)__double_as_longlong(x), 0));
+    x = step(x, dpp64<0x143, 0xc, 0xf>((uint64_t)__double_as_longlong(x), 0));
+    return x;
+}
+
 // Heat-bath choice (Sec. 3.3.2) among all W values, with the fixed summation order: value j of the
 // range belongs to lane j / c (c = ceil(W/64)); lane sums are left to right; the lanes' sums are
-// combined by a Kogge-Stone inclusive scan (strides 1..32); the first value whose cumulative weight
-// exceeds U * total is drawn (the last value if rounding leaves none).
+// combined by wave_scan_rows; the first value whose cumulative weight exceeds U * total is drawn
+// (the last value if rounding leaves none).
 template <int kRegChunk, int kMaxE, typename Acc>
 __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
                                                   int64_t zk, double beta, double U, int lane) {
@@ -384,12 +398,13 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
     if (kRegChunk > 0) {
 #pragma unroll
         for (int i = 0; i < (kRegChunk > 0 ? kRegChunk : 1); ++i) {
-            if (i < c) {
-                const int64_t j = j0 + i;
-                const double wi = j < W ? weight(j) : 0.0;
-                w[i] = wi;
-                lane_sum += wi;
-            }
+            // evaluated for every slot (a clamped index past the range) so that the exps of a lane
+            // are independent instructions; slots past the range or the chunk weigh zero
+            const int64_t j = j0 + i;
+            const double wv = weight(j < W ? j : W - 1);
+            const double wi = (i < c && j < W) ? wv : 0.0;
+            w[i] = wi;
+            lane_sum += wi;
         }
     } else {
         for (int64_t i = 0; i < c; ++i) {
@@ -397,17 +412,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             if (j < W) lane_sum += weight(j);
         }
     }
-    // Kogge-Stone inclusive scan, strides 1, 2, 4, 8, 16, 32: incl_l += incl_(l-d) for l >= d
-    double incl = lane_sum;
-    {
-        const double y = wave_shift_up1(incl, 0.0);
-        if (lane >= 1) incl = incl + y;
-    }
-#pragma unroll
-    for (int off = 2; off < kWave; off <<= 1) {
-        const double y = wave_shift_up(incl, off, lane);
-        if (lane >= off) incl = incl + y;
-    }
+    const double incl = wave_scan_rows(lane_sum);
     const double total = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(incl), kWave - 1));
     const double before = wave_shift_up1(incl, 0.0);
     const double thr = U * total;
