@@ -216,13 +216,18 @@ class Workload:
     name: str = ""
 
 
+def cfg1_beta(n_sweeps: int) -> np.ndarray:
+    """The dense configuration's given schedule, geometric from beta 0.01 to 10 over n_sweeps."""
+    s = np.arange(n_sweeps, dtype=np.float64)
+    return 0.01 * np.power(1000.0, s / max(n_sweeps - 1, 1))
+
+
 def cfg1_dense_quio() -> Workload:
     """Dense QUIO, N=100, z in [0,15], J_ij (i<=j) and h_i uniform on {-10..10}; Metropolis with
     geometric beta 0.01 -> 10 over 1000 sweeps, 16 reads."""
     rng = np.random.Generator(np.random.PCG64(GEN_SEED_BASE + 1))
     prob = dense_quio(100, 0, 15, 10, 10, rng, name="cfg1_dense_quio_n100")
-    s = np.arange(1000, dtype=np.float64)
-    beta = 0.01 * np.power(1000.0, s / 999.0)
+    beta = cfg1_beta(1000)
     return Workload(prob, RULES["metropolis"], 1000, 16, PHILOX_SEED_BASE + 1, 0, beta,
                     "dense QUIO N=100 [0,15] Metropolis 1000 sweeps 16 reads")
 
