@@ -104,6 +104,9 @@ typedef struct {
     int32_t waves_per_replica;  /* 0: automatic.  G > 1 lets G wavefronts of one replica update G
                                    consecutive variables that share no term at the same time (the
                                    result is identical to the sequential sweep); 1, 2, 4, 8 or 16 */
+    int32_t otm_enum_max;       /* optimal transition: ranges of at most this many values take the
+                                   argmin by enumeration, wider ones from the stationary points of
+                                   the degree-<=4 energy difference (same result); 0: 2048 */
 } sa_opts;
 
 void sa_opts_default(sa_opts *opts);

@@ -302,6 +302,11 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     a.key1 = (uint32_t)(seed >> 32);
     a.instance_id = opts.instance_id;
     a.otm_r = opts.otm_r;
+    if (opts.otm_enum_max < 0) {
+        if (tmp) (void)hipFree(tmp);
+        return fail(SA_EINVAL, "otm_enum_max must be >= 0");
+    }
+    a.otm_enum_max = opts.otm_enum_max > 0 ? opts.otm_enum_max : sa::kOtmEnumMax;
     a.z_init = zi_dev;
     a.z_out = z_dev;
     a.e_out = e_dev;
@@ -312,7 +317,8 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     }
     if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
     sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
-                                            plan->info.max_exponent, plan->device, G, plan->narrow_ok);
+                                            plan->info.max_exponent, plan->device, G, plan->narrow_ok,
+                                            a.otm_enum_max);
     sa_plan::Sched *sc = nullptr;
     rc = get_schedule(plan, lc.win_waves, &sc);
     if (rc != SA_OK) {

@@ -18,6 +18,9 @@ constexpr int kMaxExpPoly = 16;
 constexpr int kMaxExpStored = 255;
 // Heat-bath weights kept in registers when ceil(W/64) <= this; wider ranges recompute them.
 constexpr int kHeatBathRegChunk = 32;
+// Optimal transition: ranges up to this width take the argmin by enumeration, wider ones from the
+// stationary points of the energy difference.
+constexpr int kOtmEnumMax = 2048;
 
 // Canonical polynomial: merged terms, nonzero coefficients, factors sorted (a power is a
 // repeated index).
@@ -127,6 +130,7 @@ struct AnnealArgs {
     uint32_t key0, key1;     // Philox key (seed)
     uint32_t instance_id;
     double otm_r;            // < 0: r = s/(S-1)
+    int32_t otm_enum_max;    // widest range whose optimal transition is found by enumeration
     const SchedRec *sched;   // G * n_win schedule slots (device)
     int32_t n_win;           // windows per sweep
     int32_t win_waves;       // G: waves per replica (1: each wave is an independent replica)
@@ -152,7 +156,7 @@ int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *s
                   std::string &err);
 // Picks the launch geometry for n_reads replicas of an n-variable problem on `device`.
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device, int win_waves, bool narrow_ok);
+                           int device, int win_waves, bool narrow_ok, int32_t otm_enum_max);
 // LDS bytes of one replica's state when its G waves share it (state + per-wave energy slots).
 int64_t shared_state_bytes(int32_t n, int G);
 // Waves of one batch workgroup; a task runs kBatchWaves / G_p reads of problem p.

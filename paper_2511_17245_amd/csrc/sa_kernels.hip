@@ -466,6 +466,113 @@ __device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE, Acc> &C, i
     return wave_min_i32(best == dbest ? bv : INT32_MAX);
 }
 
+// Optimal transition over a wide range (Sec. 3.3.3 restricts the rule to energy differences of
+// degree <= 4, whose minimisers lie next to stationary points).  With p(v) = sum_m a_m v^m,
+// dE(v) = p(v) - p(z_k).  The smallest minimiser v* over [lo, hi] minus {z_k} is an end of the
+// range, z_k - 1 or z_k + 1, or else p(v*-1) > p(v*) <= p(v*+1), so the real polynomial has a
+// stationary point t with |t - v*| < 1.  Every real root of the first derivative (and, in case
+// rounding hides a nearly double root, of the second and third derivatives) is found in double
+// precision; the 64 integers around each such centre, around both ends and around z_k are then
+// evaluated exactly, and the wave takes the lexicographic (dE, v) minimum.  The result equals the
+// enumeration whenever each computed root is within 30 of the true one.
+
+// Real roots of a x^2 + b x + c (a = 0: the linear root), preceded by the vertex -b/2a.
+__device__ __forceinline__ int quadratic_centres(double a, double b, double c, double *r) {
+    if (a == 0.0) {
+        if (b == 0.0) return 0;
+        r[0] = -c / b;
+        return 1;
+    }
+    int n = 0;
+    r[n++] = -b / (2.0 * a);
+    const double disc = b * b - 4.0 * a * c;
+    if (disc >= 0.0) {
+        const double q = -0.5 * (b + copysign(sqrt(disc), b));
+        r[n++] = q / a;
+        if (q != 0.0) r[n++] = c / q;
+    }
+    return n;
+}
+
+// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 (c3 != 0): trigonometric form for three real roots,
+// Cardano's for one, each then improved by two Newton steps.
+__device__ __forceinline__ int cubic_roots(double c3, double c2, double c1, double c0, double *r) {
+    const double A = c2 / c3, B = c1 / c3, C = c0 / c3;
+    const double A3 = A / 3.0;
+    const double p = B - A * A3;                 // depressed cubic y^3 + p y + q, x = y - A/3
+    const double q = (2.0 * A3 * A3 - B) * A3 + C;
+    const double D = 0.25 * q * q + p * p * p / 27.0;
+    int n = 0;
+    if (D <= 0.0 && p < 0.0) {
+        const double m = 2.0 * sqrt(-p / 3.0);
+        double cs = -4.0 * q / (m * m * m);
+        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+        const double th = acos(cs) / 3.0;
+        const double tau = 2.0943951023931957;   // 2 pi / 3
+        r[n++] = m * cos(th) - A3;
+        r[n++] = m * cos(th - tau) - A3;
+        r[n++] = m * cos(th + tau) - A3;
+    } else {
+        const double sd = sqrt(D > 0.0 ? D : 0.0);
+        const double u = cbrt(-0.5 * q - copysign(sd, q));
+        r[n++] = (u != 0.0 ? u - p / (3.0 * u) : 0.0) - A3;
+    }
+    for (int i = 0; i < n; ++i) {
+        double x = r[i];
+        for (int it = 0; it < 2; ++it) {
+            const double f = ((c3 * x + c2) * x + c1) * x + c0;
+            const double g = (3.0 * c3 * x + 2.0 * c2) * x + c1;
+            const double xn = g != 0.0 ? x - f / g : x;
+            x = isfinite(xn) ? xn : x;
+        }
+        r[i] = x;
+    }
+    return n;
+}
+
+template <int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t argmin_stationary(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
+                                                     int64_t zk, int lane, int64_t &dbest) {
+    const int64_t hi = lo + W - 1;
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 1; m <= (kMaxE < 4 ? kMaxE : 4); ++m) a[m] = (double)to_i64<Acc>(C.a[m]);
+    double cen[12];
+    int nc = 0;
+    cen[nc++] = (double)(lo + 31);
+    cen[nc++] = (double)(hi - 32);
+    cen[nc++] = (double)zk;
+    // first derivative 4 a4 x^3 + 3 a3 x^2 + 2 a2 x + a1; second 12 a4 x^2 + 6 a3 x + 2 a2
+    if (a[4] != 0.0) {
+        nc += cubic_roots(4.0 * a[4], 3.0 * a[3], 2.0 * a[2], a[1], cen + nc);
+        nc += quadratic_centres(12.0 * a[4], 6.0 * a[3], 2.0 * a[2], cen + nc);
+    } else {
+        nc += quadratic_centres(3.0 * a[3], 2.0 * a[2], a[1], cen + nc);
+        if (a[3] != 0.0) cen[nc++] = -a[2] / (3.0 * a[3]);
+    }
+    int64_t best = INT64_MAX;
+    int32_t bv = INT32_MAX;
+    for (int i = 0; i < nc; ++i) {
+        // window [b, b + 63] around the centre, inside the range
+        const double c = cen[i];
+        int64_t b;
+        if (!(c > (double)lo + 31.0)) b = lo;
+        else if (!(c < (double)hi - 32.0)) b = hi - 63;
+        else b = (int64_t)floor(c) - 31;
+        b = b < lo ? lo : b;
+        const int64_t v = b + lane;
+        if (v <= hi && v != zk) {
+            const int64_t d = poly_delta(C, zk, v);
+            if (d < best || (d == best && v < bv)) {
+                best = d;
+                bv = (int32_t)v;
+            }
+        }
+    }
+    dbest = wave_min_i64(best);
+    return wave_min_i32(best == dbest ? bv : INT32_MAX);
+}
+
 // Heat bath for a variable whose energy difference is linear, dE(v) = a (v - z_k) (Sec. 3.3.2,
 // multilinear case): the inverse of the cumulative distribution in O(1).  Index i = v - lo has
 // probability proportional to exp(-beta a i); with c = beta |a| and g(q) = -log1p(q expm1(-c W)) / c
@@ -509,6 +616,7 @@ struct ReplicaCtx {
     int32_t n_sweeps, s_begin, s_end;
     uint32_t key0, key1, instance_id, read;
     double otm_r;
+    int32_t otm_enum_max;   // widest range whose optimal transition is enumerated
     const SchedRec *sched;  // this wave's schedule slots (window-major for one wave)
     int32_t n_win;
     bool shared;            // the replica's waves cooperate (barrier after each window)
@@ -642,7 +750,11 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         if ((double)r0 * 0x1p-32 < r_opt) {
                             Coeffs<kMaxE, Acc> C;
                             row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
-                            v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
+                            // kRegChunk = 1 builds the stationary-point argmin for wide ranges
+                            if (kRegChunk == 1 && W > R.otm_enum_max)
+                                v = argmin_stationary<kMaxE, Acc>(C, lo, W, zk, lane, d);
+                            else
+                                v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;
@@ -700,6 +812,7 @@ __global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
     R.instance_id = A.instance_id;
     R.read = (uint32_t)read;
     R.otm_r = A.otm_r;
+    R.otm_enum_max = A.otm_enum_max;
     R.sched = A.sched + (size_t)g * A.n_win;
     R.n_win = A.n_win;
     R.shared = shared;
@@ -770,6 +883,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B)
         R.instance_id = D.instance_id;
         R.read = read;
         R.otm_r = -1.0;
+        R.otm_enum_max = kOtmEnumMax;
         R.sched = D.sched + (size_t)g * D.n_win;
         R.n_win = D.n_win;
         R.shared = G > 1;
@@ -852,6 +966,7 @@ bool sixteen_waves_ok(int rule, bool in_lds, int reg_chunk, int maxe_class) {
     if (!in_lds || maxe_class > 2) return false;
     if (rule == SA_HEAT_BATH) return reg_chunk >= 1 && reg_chunk <= 8;
     if (rule == SA_HEAT_BATH_CLOSED) return maxe_class == 1;
+    if (rule == SA_OPT_METROPOLIS) return reg_chunk == 0;
     return true;
 }
 
@@ -913,7 +1028,15 @@ KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool 
         }
     }
     if (rule == SA_OPT_METROPOLIS) {
-        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 0, 4, uint64_t, 512>;
+        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 1, 4, uint64_t, 512>;
+        if (reg_chunk == 1) {
+            // ranges wider than the enumeration limit: the stationary-point argmin is built in
+            switch (maxe_class) {
+                case 1: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 1, uint64_t, 512>;
+                case 2: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 2, uint64_t, 512>;
+                default: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 4, uint64_t, 512>;
+            }
+        }
         switch (maxe_class) {
             case 1: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t, 512>
                                   : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t, 512>;
@@ -940,7 +1063,7 @@ int64_t shared_state_bytes(int32_t n, int G) {
 }
 
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device, int win_waves, bool narrow_ok) {
+                           int device, int win_waves, bool narrow_ok, int32_t otm_enum_max) {
     LaunchChoice lc;
     int cus = 256, max_lds = 65536;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -948,10 +1071,12 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
     const bool heat_bath = rule == SA_HEAT_BATH || rule == SA_HEAT_BATH_CLOSED;
     const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
+    // heat bath: weights per lane kept in registers; optimal transition: 1 = stationary-point argmin
+    const bool otm_wide = rule == SA_OPT_METROPOLIS && max_width > otm_enum_max;
     const int reg_in_lds =
         heat_bath && !(rule == SA_HEAT_BATH_CLOSED && max_exp <= 1)
             ? (chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0)
-            : 0;
+            : (otm_wide ? 1 : 0);
     if (win_waves == 16 && !(shared_state_bytes(n, 16) <= max_lds &&
                              sixteen_waves_ok(rule, true, reg_in_lds, maxe_class_of(max_exp))))
         win_waves = 8;  // no 16-wave build of this variant: the next width gives the same result
@@ -977,7 +1102,7 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     lc.maxe_class = lc.state_in_lds ? maxe_class_of(max_exp)
                                     : (heat_bath ? kMaxExpPoly : rule == SA_OPT_METROPOLIS ? 4 : 1);
     lc.reg_chunk = reg;
-    lc.narrow = narrow_ok && lc.state_in_lds && lc.maxe_class <= 2;
+    lc.narrow = narrow_ok && lc.state_in_lds && lc.maxe_class <= 2 && !otm_wide;
     lc.variant = (lc.win_waves == 16 ? 1000000 : 0) + rule * 100000 + (lc.narrow ? 10000 : 0) +
                  lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
     return lc;

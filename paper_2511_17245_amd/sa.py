@@ -43,7 +43,7 @@ class sa_schedule(C.Structure):
 class sa_opts(C.Structure):
     _fields_ = [("instance_id", C.c_uint32), ("hip_stream", C.c_void_p), ("device_buffers", C.c_int32),
                 ("sweep_begin", C.c_int32), ("sweep_end", C.c_int32), ("init_states", C.c_void_p),
-                ("otm_r", C.c_double), ("waves_per_replica", C.c_int32)]
+                ("otm_r", C.c_double), ("waves_per_replica", C.c_int32), ("otm_enum_max", C.c_int32)]
 
 
 class sa_plan_info(C.Structure):
@@ -194,7 +194,7 @@ def _schedule(n_sweeps: int, beta):
 
 
 def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, sweep_end=0,
-              init_states=None, otm_r=-1.0, waves_per_replica=0) -> sa_opts:
+              init_states=None, otm_r=-1.0, waves_per_replica=0, otm_enum_max=0) -> sa_opts:
     o = sa_opts()
     lib().sa_opts_default(C.byref(o))
     o.instance_id = int(instance_id) & 0xFFFFFFFF
@@ -205,6 +205,7 @@ def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, s
     o.init_states = _p(init_states)
     o.otm_r = float(otm_r)
     o.waves_per_replica = int(waves_per_replica)
+    o.otm_enum_max = int(otm_enum_max)
     return o
 
 
@@ -271,7 +272,7 @@ class Plan:
 
     def run_device(self, n_sweeps, n_reads, seed, z_out, e_out, beta=None, stream=None,
                    instance_id=0, sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0,
-                   waves_per_replica=0):
+                   waves_per_replica=0, otm_enum_max=0):
         """Queue a run writing into device tensors z_out (int32 [n_reads, N]) and e_out (int64)."""
         assert z_out.is_cuda and e_out.is_cuda
         assert z_out.dtype.itemsize == 4 and e_out.dtype.itemsize == 8
@@ -281,7 +282,7 @@ class Plan:
             assert init_states.is_cuda and init_states.numel() == n_reads * self.n
         sched, keep = _schedule(n_sweeps, beta)
         opts = make_opts(instance_id, stream, True, sweep_begin, sweep_end, init_states, otm_r,
-                         waves_per_replica)
+                         waves_per_replica, otm_enum_max)
         rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                _p(z_out), _p(e_out), C.byref(opts))
         _check(rc, "sa_plan_run")

@@ -27,7 +27,8 @@ def rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=None, s0=0, s1=0, G=0):
+def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=None, s0=0, s1=0, G=0,
+            otm_enum_max=0):
     import torch
     plan = sa.Plan(prob, rule)
     z = torch.empty((n_reads, prob.n_vars), dtype=torch.int32, device="cuda")
@@ -35,7 +36,8 @@ def gpu_run(prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0, init=Non
     zi = None if init is None else torch.as_tensor(np.ascontiguousarray(init, np.int32), device="cuda")
     plan.run_device(len(beta), n_reads, seed, z, e, beta=beta,
                     stream=torch.cuda.current_stream().cuda_stream, instance_id=instance_id,
-                    otm_r=otm_r, init_states=zi, sweep_begin=s0, sweep_end=s1, waves_per_replica=G)
+                    otm_r=otm_r, init_states=zi, sweep_begin=s0, sweep_end=s1, waves_per_replica=G,
+                    otm_enum_max=otm_enum_max)
     torch.cuda.synchronize()
     launch = plan.last_launch()
     plan.close()
@@ -160,6 +162,28 @@ def test_otm_fixed_r():
         zg, eg, _ = gpu_run(prob, sa.OPT_METROPOLIS, beta, 32, seed=2, otm_r=r)
         zo, eo = P.anneal(sa.OPT_METROPOLIS, beta, 32, seed=2, otm_r=r)
         assert_same(zg, eg, zo, eo, f"OTM r={r}")
+
+
+def test_otm_stationary_point_argmin_matches_enumeration():
+    # ranges wider than the enumeration limit take the argmin from the stationary points of the
+    # degree <= 4 energy difference; it must be the oracle's enumerated argmin (ties to the
+    # smallest value) in every step.  otm_enum_max = 1 forces the path on narrow ranges too.
+    r = rng(91)
+    cases = [("huio_quartic_w6001", I.random_huio(60, 240, [1, 2, 3, 4], -3000, 3000, 3, r), 20, 16, -1.0, 0),
+             ("fc_p4_w4001", I.fully_connected(20, 4, 2000), 12, 8, -1.0, 0),
+             ("fc_p3_w20001", I.fully_connected(12, 3, 10000), 12, 8, 0.7, 0),
+             ("forced_narrow_ranges", I.cfg3_huio(n=300, m=3000).problem, 30, 32, -1.0, 1),
+             ("forced_quartic_w81", I.random_huio(80, 400, [1, 2, 3, 4], -40, 40, 5, r), 30, 32, -1.0, 1),
+             ("square_ties", I.from_terms(2, [(3, [0, 0]), (1, [1, 1]), (-1, [0, 1])], -5000, 5000),
+              40, 32, 1.0, 0)]
+    for name, prob, sweeps, reads, r_fixed, enum_max in cases:
+        P = oracle.Poly(prob)
+        beta, _, _ = P.schedule(sweeps)
+        say("otm stationary", name)
+        zg, eg, launch = gpu_run(prob, sa.OPT_METROPOLIS, beta, reads, seed=17, otm_r=r_fixed,
+                                 otm_enum_max=enum_max)
+        zo, eo = P.anneal(sa.OPT_METROPOLIS, beta, reads, seed=17, otm_r=r_fixed)
+        assert_same(zg, eg, zo, eo, f"{name} {launch}")
 
 
 def test_energy_kernel_and_one_shot_api():
