@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB (counter calibration) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--suite", action="store_true",
+                    help="the paper's experiments (FC, ML, RI models at N = 100) instead of updates/s")
     ap.add_argument("--ttt", action="store_true",
                     help="time to target energy instead of updates/s (cfg1, cfg2, cfg2-closed, cfg3-*)")
     ap.add_argument("--ttt-oracle-reads", type=int, default=0,
@@ -216,6 +218,141 @@ def bench_ttt(args):
         "tts99_best_s": min(tts) if tts else None,
         "cpu_baseline": out_cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_suite(args):
+    """The paper's experiments (Sec. 4) on the GPU with its three models at N = 100 (integer-scaled
+    fixtures, synthetic random-interaction realizations): annealing time against the range 2u+1
+    and the degree p at 1000 sweeps and 100 reads (Figs. 1-2), energy against temperature within
+    one anneal (Figs. 3-4), against the sweep count (Figs. 5-6) and against annealing time for wide
+    ranges (Figs. 7-8).  The heat bath is the paper's: closed-form draws where the energy
+    difference is linear, enumeration elsewhere.  Times are GPU kernel times of one launch that
+    runs all reads at once."""
+    import numpy as np
+    import torch
+    from paper_2511_17245_amd import inputs as I
+    from paper_2511_17245_amd import sa
+
+    stream = torch.cuda.current_stream()
+    HB = sa.HEAT_BATH_CLOSED
+    names = {sa.METROPOLIS: "metropolis", HB: "heat_bath", sa.OPT_METROPOLIS: "otm",
+             sa.HEAT_BATH: "heat_bath_enumerated"}
+    otm_enum_max = 64   # wider ranges take the stationary-point argmin (O(1) in the range)
+
+    def run(prob, rule, n_sweeps, n_reads=100, seed=2511, beta=None, reps=2):
+        plan = sa.Plan(prob, rule)
+        beta = sa.auto_schedule(prob, n_sweeps) if beta is None else beta
+        z = torch.empty((n_reads, prob.n_vars), dtype=torch.int32, device="cuda")
+        e = torch.empty(n_reads, dtype=torch.int64, device="cuda")
+        best = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            plan.run_device(n_sweeps, n_reads, seed, z, e, beta=beta, stream=stream.cuda_stream,
+                            otm_enum_max=otm_enum_max)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        out = e.cpu().numpy()
+        plan.close()
+        return best, out
+
+    res = {}
+    # Figs. 1-2: time against 2u+1 (FC, p = 1, 2) and against p (FC u = 1; ML u = 10)
+    t_range = []
+    for p_ in (1, 2):
+        for u in (1, 10, 100, 1000):
+            prob = I.fully_connected(100, p_, u)
+            rules = [sa.METROPOLIS, HB, sa.OPT_METROPOLIS] + ([sa.HEAT_BATH] if p_ == 1 else [])
+            for rule in rules:
+                ms, e = run(prob, rule, 1000)
+                t_range.append({"model": "FC", "p": p_, "u": u, "range": 2 * u + 1, "rule": names[rule],
+                                "ms": ms, "mean_energy_over_gs": float(np.mean(e)) /
+                                (I.fully_connected_scale(p_, u) * 100 * 101 / 2)})
+        print(f"[bench] suite: time vs range p={p_} done", file=sys.stderr, flush=True)
+    res["time_vs_range"] = t_range
+    t_p = []
+    for p_ in (1, 2, 3, 4, 6, 8):
+        prob = I.fully_connected(100, p_, 1)
+        for rule in [sa.METROPOLIS, HB] + ([sa.OPT_METROPOLIS] if p_ <= 4 else []):
+            ms, _ = run(prob, rule, 1000)
+            t_p.append({"model": "FC", "u": 1, "p": p_, "rule": names[rule], "ms": ms})
+    for p_ in (2, 3, 4, 6, 8, 10):
+        prob = I.multilinear(100, p_, 10)
+        for rule in (sa.METROPOLIS, HB, sa.OPT_METROPOLIS):
+            ms, _ = run(prob, rule, 1000)
+            t_p.append({"model": "ML", "u": 10, "p": p_, "rule": names[rule], "ms": ms})
+    res["time_vs_p"] = t_p
+    print("[bench] suite: time vs p done", file=sys.stderr, flush=True)
+
+    # Figs. 3-4: energy against temperature inside one 1000-sweep anneal (chunks of 50 sweeps)
+    e_T = []
+    for label, prob, gs in (("FC p=2 u=10", I.fully_connected(100, 2, 10), 100 * 100 * 101 / 2),
+                            ("ML p=3 u=10", I.multilinear(100, 3, 10), 100 * 1000)):
+        for rule in (sa.METROPOLIS, HB, sa.OPT_METROPOLIS):
+            plan = sa.Plan(prob, rule)
+            S = 1000
+            beta = sa.auto_schedule(prob, S)
+            z = torch.empty((100, prob.n_vars), dtype=torch.int32, device="cuda")
+            e = torch.empty(100, dtype=torch.int64, device="cuda")
+            pts = []
+            for s0 in range(0, S, 50):
+                plan.run_device(S, 100, 7, z, e, beta=beta, stream=stream.cuda_stream, sweep_begin=s0,
+                                sweep_end=s0 + 50, init_states=None if s0 == 0 else z)
+                torch.cuda.synchronize()
+                pts.append({"T": 1.0 / float(beta[s0 + 49]), "mean_energy_over_gs":
+                            float(e.float().mean().item()) / gs})
+            plan.close()
+            e_T.append({"model": label, "rule": names[rule], "points": pts})
+    res["energy_vs_temperature"] = e_T
+    print("[bench] suite: energy vs temperature done", file=sys.stderr, flush=True)
+
+    # Figs. 5-8: energy against sweeps and annealing time
+    e_s = []
+    rng = np.random.Generator(np.random.PCG64(2511))
+    models = [("FC p=2 u=10", I.fully_connected(100, 2, 10), 100 * 100 * 101 / 2),
+              ("ML p=3 u=10", I.multilinear(100, 3, 10), 100 * 1000)]
+    for u in (10, 1000):
+        for r_ in range(3):
+            models.append((f"RI p=2 u={u} #{r_}", I.random_interaction(100, 2, u, 1000, rng), None))
+    for label, prob, gs in models:
+        rows = []
+        for S in (10, 30, 100, 300, 1000):
+            for rule in (sa.METROPOLIS, HB, sa.OPT_METROPOLIS):
+                ms, e = run(prob, rule, S)
+                rows.append({"sweeps": S, "rule": names[rule], "ms": ms, "mean_energy": float(np.mean(e)),
+                             "min_energy": int(e.min()), "p_ground": None if gs is None else
+                             float(np.mean(e <= -gs))})
+        best = min(r["min_energy"] for r in rows)
+        for r in rows:
+            r["mean_energy_over_best"] = r["mean_energy"] / abs(best)
+        e_s.append({"model": label, "ground_energy": None if gs is None else -gs, "rows": rows})
+        print(f"[bench] suite: energy vs sweeps {label} done", file=sys.stderr, flush=True)
+    res["energy_vs_sweeps_and_time"] = e_s
+
+    # the paper's qualitative statements, evaluated on these numbers
+    def t(model, p_, u, rule):
+        return next(r["ms"] for r in t_range if r["p"] == p_ and r["u"] == u and r["rule"] == rule)
+    checks = {
+        "p1_time_flat_in_range": {r: t("FC", 1, 1000, r) / t("FC", 1, 1, r)
+                                  for r in ("metropolis", "heat_bath", "otm")},
+        "p1_enumerated_heat_bath_growth": t("FC", 1, 1000, "heat_bath_enumerated") / t("FC", 1, 1, "heat_bath_enumerated"),
+        "p2_heat_bath_growth_u1000_over_u10": t("FC", 2, 1000, "heat_bath") / t("FC", 2, 10, "heat_bath"),
+        "p2_metropolis_otm_growth_u1000_over_u10": {r: t("FC", 2, 1000, r) / t("FC", 2, 10, r)
+                                                   for r in ("metropolis", "otm")},
+        "ml_time_ratio_p10_over_p2": {r: next(x["ms"] for x in t_p if x["model"] == "ML" and x["p"] == 10 and x["rule"] == r)
+                                      / next(x["ms"] for x in t_p if x["model"] == "ML" and x["p"] == 2 and x["rule"] == r)
+                                      for r in ("metropolis", "heat_bath", "otm")},
+    }
+    wide = [m for m in e_s if m["model"].startswith("RI p=2 u=1000")]
+    short = {r: float(np.mean([next(x["mean_energy_over_best"] for x in m["rows"] if x["sweeps"] == 10 and x["rule"] == r)
+                               for m in wide])) for r in ("metropolis", "heat_bath", "otm")}
+    checks["ri_wide_mean_energy_over_best_at_10_sweeps"] = short
+    out = {"metric": "paper experiment suite (Sec. 4) on 1 GPU", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "FC / ML / RI models, N = 100, 100 reads", "otm_enum_max": otm_enum_max},
+           "checks": checks, "results": res}
     print(json.dumps(out), flush=True)
 
 
@@ -396,6 +533,8 @@ def main():
         return copy_probe(args.copy_probe_mib)
     if args.ttt:
         return bench_ttt(args)
+    if args.suite:
+        return bench_suite(args)
     if args.config == "cfg4":
         return bench_batch(args)
     if args.config == "cfg5":
