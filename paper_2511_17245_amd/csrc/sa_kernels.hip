@@ -573,23 +573,83 @@ __device__ __forceinline__ int64_t argmin_stationary(const Coeffs<kMaxE, Acc> &C
     return wave_min_i32(best == dbest ? bv : INT32_MAX);
 }
 
+// expm1(x) for x <= 0 (the closed-form heat bath's expm1(-c W)).  Below -40, e^x is under half an
+// ulp of 1 and the value is -1 exactly.  On [-0.35, 0] the Taylor series of e^x - 1 to x^14 (error
+// below 2^-60 relative); otherwise exp(x) - 1, which cancels nothing because exp(x) <= 0.71.
+__device__ __forceinline__ double expm1_nonpos(double x) {
+    if (x < -40.0) return -1.0;
+    if (x < -0.35) return exp(x) - 1.0;
+    // Horner on 1/k!, k = 14 .. 2, then x + x^2 (...)
+    double p = 1.0 / 87178291200.0;            // 1/14!
+    p = fma(p, x, 1.0 / 6227020800.0);         // 1/13!
+    p = fma(p, x, 1.0 / 479001600.0);          // 1/12!
+    p = fma(p, x, 1.0 / 39916800.0);           // 1/11!
+    p = fma(p, x, 1.0 / 3628800.0);            // 1/10!
+    p = fma(p, x, 1.0 / 362880.0);             // 1/9!
+    p = fma(p, x, 1.0 / 40320.0);              // 1/8!
+    p = fma(p, x, 1.0 / 5040.0);               // 1/7!
+    p = fma(p, x, 1.0 / 720.0);                // 1/6!
+    p = fma(p, x, 1.0 / 120.0);                // 1/5!
+    p = fma(p, x, 1.0 / 24.0);                 // 1/4!
+    p = fma(p, x, 1.0 / 6.0);                  // 1/3!
+    p = fma(p, x, 0.5);                        // 1/2!
+    return fma(p * x, x, x);
+}
+
+// log1p(y) for -1 < y <= 0 (the closed-form heat bath's log1p(U m)).  u = 1 + y rounded; log(u)
+// from u = f 2^e with f in [sqrt(1/2), sqrt(2)) and log f = 2 atanh(s), s = (f - 1)/(f + 1),
+// |s| <= 0.1716, by its odd series to s^21 (error below 2^-62 relative); the rounding of u is
+// put back to first order, log1p(y) = log(u) + (y - (u - 1)) / u (Kahan's correction).
+__device__ __forceinline__ double log1p_nonpos(double y) {
+    if (y == 0.0) return 0.0;
+    if (y <= -1.0) return -__builtin_huge_val();
+    const double u = 1.0 + y;
+    const double corr = (y - (u - 1.0)) * __builtin_amdgcn_rcp(u);
+    int e = __builtin_amdgcn_frexp_exp(u);
+    double f = __builtin_amdgcn_frexp_mant(u);  // [0.5, 1)
+    if (f < 0.70710678118654752) {
+        f = f + f;
+        e -= 1;
+    }
+    const double s = (f - 1.0) / (f + 1.0);
+    const double s2 = s * s;
+    double r = 1.0 / 21.0;
+    r = fma(r, s2, 1.0 / 19.0);
+    r = fma(r, s2, 1.0 / 17.0);
+    r = fma(r, s2, 1.0 / 15.0);
+    r = fma(r, s2, 1.0 / 13.0);
+    r = fma(r, s2, 1.0 / 11.0);
+    r = fma(r, s2, 1.0 / 9.0);
+    r = fma(r, s2, 1.0 / 7.0);
+    r = fma(r, s2, 1.0 / 5.0);
+    r = fma(r, s2, 1.0 / 3.0);
+    const double ln2_hi = 0.6931471803691238;    // ln 2 rounded to 32 bits: e * ln2_hi is exact
+    const double ln2_lo = 1.9082149292705877e-10;  // ln 2 - ln2_hi
+    const double ed = (double)e;
+    const double two_s = s + s;
+    // log u = e ln2_hi + (2 s + (2 s s^2 r + e ln2_lo)) + corr
+    return fma(ed, ln2_hi, two_s + (fma(two_s * s2, r, ed * ln2_lo) + corr));
+}
+
 // Heat bath for a variable whose energy difference is linear, dE(v) = a (v - z_k) (Sec. 3.3.2,
 // multilinear case): the inverse of the cumulative distribution in O(1).  Index i = v - lo has
 // probability proportional to exp(-beta a i); with c = beta |a| and g(q) = -log1p(q expm1(-c W)) / c
 // the paper's x = -(T/a) ln[1 - U (1 - exp(-a W / T))] is g(U) for a > 0 and W - g(1 - U) for a < 0
 // (the same value without overflowing exp(c W)); v = lo + ceil(x) - 1, clamped to the box.  a = 0
 // or beta = 0 is the uniform distribution, drawn from x1 by a multiply-high.  Wave-uniform.
+// expm1 and log1p are the functions above (about an ulp, like the host library); a last-bit
+// difference moves a draw only when x lies within a few ulps of an integer.
 __device__ __forceinline__ int64_t heat_bath_closed(int64_t a, int64_t lo, int64_t W, double beta, double U,
                                                     uint32_t x1) {
     const double c = beta * (double)(a < 0 ? -a : a);
     if (a == 0 || !(c > 0.0)) return lo + (int64_t)(((uint64_t)x1 * (uint64_t)W) >> 32);
     const double Wd = (double)W;
-    const double m = expm1(-(c * Wd));
+    const double m = expm1_nonpos(-(c * Wd));
     double x;
     if (a > 0)
-        x = -log1p(U * m) / c;
+        x = -log1p_nonpos(U * m) / c;
     else
-        x = Wd + log1p((1.0 - U) * m) / c;
+        x = Wd + log1p_nonpos((1.0 - U) * m) / c;
     if (!(x > 0.0)) return lo;
     if (x >= Wd) return lo + W - 1;
     return lo + (int64_t)ceil(x) - 1;
