@@ -79,6 +79,7 @@ int upload_packed(const sa::Packed &pk, sa_plan *plan) {
     d.t_off = (const int32_t *)(b + parts[5].off);
     d.t_var = (const int32_t *)(b + parts[6].off);
     d.t_coef = (const int64_t *)(b + parts[7].off);
+    d.max_other = pk.max_other;
     d.dense = pk.dense ? 1 : 0;
     d.jbytes = pk.jbytes;
     d.row_stride = pk.row_stride;

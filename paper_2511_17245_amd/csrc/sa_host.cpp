@@ -369,6 +369,7 @@ int pack(const Canonical &c, Packed &p, std::string &err) {
                 if (c.t_var[h] != k) others.push_back(c.t_var[h]);
             IncRec r{};
             r.meta = (uint32_t)e | ((uint32_t)others.size() << 8);
+            p.max_other = std::max<int32_t>(p.max_other, (int32_t)others.size());
             if (others.size() <= 3) {
                 for (size_t q = 0; q < 3; ++q) r.o[q] = q < others.size() ? others[q] : 0;
             } else {

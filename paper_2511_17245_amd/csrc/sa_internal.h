@@ -66,6 +66,7 @@ struct Packed {
     std::vector<IncRec> inc;
     std::vector<int64_t> inc_coef;
     std::vector<int32_t> overflow;  // other-factor indices of incidences with > 3 others
+    int32_t max_other = 0;          // most other factors of any incidence (1: pair terms only)
     std::vector<int32_t> t_off;     // term-major copy for energies
     std::vector<int32_t> t_var;
     std::vector<int64_t> t_coef;
@@ -110,6 +111,7 @@ struct DevProblem {
     const int32_t *t_off;
     const int32_t *t_var;
     const int64_t *t_coef;
+    int32_t max_other;       // most other factors of any incidence
     // dense QUIO form (dense != 0)
     int32_t dense;
     int32_t jbytes;

@@ -186,7 +186,11 @@ __device__ __forceinline__ Acc record_product(const DevProblem &P, const ZT *z, 
     e = (int)(r.meta & 0xFFu);
     const int no = (int)(r.meta >> 8);
     Acc prod = (Acc)coef;
-    if (no <= 3) {
+    if (P.max_other <= 1) {
+        // pair terms only (QUIO): at most one other factor
+        const int64_t z0 = z[r.o[0]];
+        prod *= no > 0 ? (Acc)z0 : (Acc)1;
+    } else if (no <= 3) {
         // all three reads issued together (unused slots hold index 0, a valid variable)
         const int64_t z0 = z[r.o[0]], z1 = z[r.o[1]], z2 = z[r.o[2]];
         prod *= no > 0 ? (Acc)z0 : (Acc)1;
@@ -338,10 +342,38 @@ __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z
     return to_i64<Acc>(wave_sum<Acc>(acc));
 }
 
+// e^x for x <= 0 (every exponential of the annealer has a non-positive argument): x = n ln 2 + r
+// with |r| <= ln(2)/2, e^r by its Taylor polynomial to r^13 (truncation below 2^-57 relative), then
+// scaled by 2^n; 0 below -745.2, where e^x is under half the smallest subnormal.  Within about an
+// ulp, like the host library the oracle uses; a last-bit difference moves a draw only when a
+// uniform number falls within that ulp of a threshold.
+__device__ __forceinline__ double exp_nonpos(double x) {
+    const double xc = x > -746.0 ? x : -746.0;
+    const double n = rint(xc * 1.4426950408889634);     // 1 / ln 2
+    double r = fma(-n, 0.6931471803691238, xc);          // ln 2 rounded to 32 bits (n * it exact)
+    r = fma(-n, 1.9082149292705877e-10, r);              // the rest of ln 2
+    double p = 1.0 / 6227020800.0;                       // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    const double e = __builtin_amdgcn_ldexp(p, (int)n);
+    return x < -745.2 ? 0.0 : e;
+}
+
 // Metropolis acceptance min[1, exp(-dE/T)] (Sec. 3.3.1), T = 1/beta; U in [0,1).
 __device__ __forceinline__ bool metropolis_accept(int64_t d, double beta, double U) {
     if (d <= 0) return true;
-    return U < exp(-(beta * (double)d));
+    return U < exp_nonpos(-(beta * (double)d));
 }
 
 // Inclusive scan of one double per lane in the order of the DPP network: inside each row of 16
@@ -390,7 +422,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
         const int64_t d = poly_delta(C, zk, lo + j);
         const double x = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)d - (uint32_t)dmin)
                                           : (double)(d - dmin);
-        return exp(-(beta * x));
+        return exp_nonpos(-(beta * x));
     };
 
     double w[kRegChunk > 0 ? kRegChunk : 1];
@@ -575,10 +607,10 @@ __device__ __forceinline__ int64_t argmin_stationary(const Coeffs<kMaxE, Acc> &C
 
 // expm1(x) for x <= 0 (the closed-form heat bath's expm1(-c W)).  Below -40, e^x is under half an
 // ulp of 1 and the value is -1 exactly.  On [-0.35, 0] the Taylor series of e^x - 1 to x^14 (error
-// below 2^-60 relative); otherwise exp(x) - 1, which cancels nothing because exp(x) <= 0.71.
+// below 2^-60 relative); otherwise e^x - 1, which cancels nothing because e^x <= 0.71.
 __device__ __forceinline__ double expm1_nonpos(double x) {
     if (x < -40.0) return -1.0;
-    if (x < -0.35) return exp(x) - 1.0;
+    if (x < -0.35) return exp_nonpos(x) - 1.0;
     // Horner on 1/k!, k = 14 .. 2, then x + x^2 (...)
     double p = 1.0 / 87178291200.0;            // 1/14!
     p = fma(p, x, 1.0 / 6227020800.0);         // 1/13!
@@ -766,6 +798,8 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
             }
             uint32_t x0 = (uint32_t)sl.k, x1 = (uint32_t)s, x2 = R.read, x3 = R.instance_id;
             philox4x32_10(x0, x1, x2, x3, R.key0, R.key1);
+            // U in [0, 1) from words 2 and 3, formed once per lane for its window
+            const double Ul = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
             const int32_t wend = n_win - wb < kWave ? n_win - wb : kWave;
             // first chunk of the next slot's incidence records, loaded one window ahead
             IncRec nrec;
@@ -785,8 +819,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     const int32_t row = (int32_t)lane_read32((uint32_t)sl.row, j);
                     const int32_t deg = (int32_t)lane_read32((uint32_t)sl.deg, j);
                     const uint32_t r0 = lane_read32(x0, j), r1 = lane_read32(x1, j);
-                    const uint32_t r2 = lane_read32(x2, j), r3 = lane_read32(x3, j);
-                    const double U = (double)((((uint64_t)r2 << 32) | r3) >> 11) * 0x1p-53;
+                    const double U = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(Ul), j));
                     const int64_t zk = (int64_t)(int32_t)uni32((uint32_t)z[k]);
                     int64_t v, d;
                     bool accept;
