@@ -397,12 +397,13 @@ __device__ __forceinline__ double wave_scan_rows(double x) {
 // (the last value if rounding leaves none).
 template <int kRegChunk, int kMaxE, typename Acc>
 __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
-                                                  int64_t zk, double beta, double U, int lane) {
+                                                  int64_t zk, double beta, double U, int lane, bool linear_in) {
     const int64_t c = (W + kWave - 1) / kWave;
     const int64_t j0 = (int64_t)lane * c;
+    const bool linear = kMaxE == 1 || linear_in;   // no term holds z_k to a power above one
     // minimum energy difference over all values (weights are taken relative to it)
     int64_t dmin;
-    if (kMaxE == 1) {
+    if (linear) {
         // dE(v) = a1 (v - z_k) is linear: its minimum over [lo, hi] is at an end of the range
         const int64_t a1 = to_i64<Acc>(C.a[1]);
         dmin = to_i64<Acc>(C.a[1] * (Acc)((a1 >= 0 ? lo : lo + W - 1) - zk));
@@ -419,7 +420,7 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
     }
     // exp(-beta * (dE - dmin)); in 32-bit mode the difference is formed in 32 bits (it fits)
     auto weight = [&](int64_t j) -> double {
-        const int64_t d = poly_delta(C, zk, lo + j);
+        const int64_t d = linear ? to_i64<Acc>(C.a[1] * (Acc)(lo + j - zk)) : poly_delta(C, zk, lo + j);
         const double x = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)d - (uint32_t)dmin)
                                           : (double)(d - dmin);
         return exp_nonpos(-(beta * x));
@@ -833,18 +834,25 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         const uint32_t em = lane_read32(sl.emask, j);
                         row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
                         // closed form where dE is linear in the new value (no exponent above one)
-                        if (kRule == SA_HEAT_BATH_CLOSED && (kMaxE == 1 || (em & ~2u) == 0))
+                        const bool linear = kMaxE == 1 || (em & ~2u) == 0;
+                        if (kRule == SA_HEAT_BATH_CLOSED && linear)
                             v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, r1);
                         else
-                            v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane);
+                            v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane, linear);
                         d = poly_delta(C, zk, v);
                         accept = true;
                     } else {
                         if ((double)r0 * 0x1p-32 < r_opt) {
                             Coeffs<kMaxE, Acc> C;
-                            row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, lane_read32(sl.emask, j), lane, crec, ccoef, C);
-                            // kRegChunk = 1 builds the stationary-point argmin for wide ranges
-                            if (kRegChunk == 1 && W > R.otm_enum_max)
+                            const uint32_t em = lane_read32(sl.emask, j);
+                            row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
+                            if (kMaxE == 1 || (em & ~2u) == 0) {
+                                // dE = a1 (v - z_k): the smallest value for a1 >= 0 (all tie when
+                                // a1 = 0), the largest for a1 < 0, stepping off z_k
+                                const int64_t a1 = to_i64<Acc>(C.a[1]);
+                                v = a1 >= 0 ? (lo == zk ? lo + 1 : lo) : (lo + W - 1 == zk ? lo + W - 2 : lo + W - 1);
+                                d = to_i64<Acc>(C.a[1] * (Acc)(v - zk));
+                            } else if (kRegChunk == 1 && W > R.otm_enum_max)
                                 v = argmin_stationary<kMaxE, Acc>(C, lo, W, zk, lane, d);
                             else
                                 v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
