@@ -17,6 +17,7 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_2511_17245_amd", "csrc")
 sys.path.insert(0, ROOT)
 
 # MI355X published peaks
@@ -85,10 +86,9 @@ def kernel_source_hash() -> str:
     kernels built from exactly these sources."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2511_17245_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(os.listdir(CSRC)):
         if name.endswith((".hip", ".cpp", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
+            with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
