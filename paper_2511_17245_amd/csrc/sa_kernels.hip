@@ -1,17 +1,19 @@
 // sa_kernels.hip -- gfx950 kernels of the single-variable update sweep (Sec. 3.1) for QUIO/HUIO.
 //
-// Mapping: one replica (read) per 64-lane wavefront; the waves of a workgroup are independent
-// replicas of the same instance (no workgroup barriers).  A replica's state z lives in LDS when it
-// fits, else in its row of the output buffer.  For the visited variable k the lanes split the
-// terms containing z_k (each lane forms one term's product of the other factors) and, for the heat
-// bath and the optimal transition, the candidate values v in [l_k, u_k].  Energies and energy
-// differences are exact integers (two's-complement wrap-around arithmetic, exact whenever the true
-// value fits int64, which the host checks); FP64 is used only for exp() in the acceptance test
-// and the heat-bath weights.
+// Mapping: a replica (read) is updated by one 64-lane wavefront, or by G = 2, 4, 8 or 16 waves of
+// a workgroup that update the G mutually non-interacting variables of a schedule window at once
+// (a barrier closes each window; the result equals the sequential sweep).  With G = 1 the waves of
+// a workgroup are independent replicas.  A replica's state z lives in LDS when it fits, else in
+// its row of the output buffer.  For the visited variable k the lanes split the terms containing
+// z_k (each lane forms one term's product of the other factors) and, for the heat bath and the
+// optimal transition, the candidate values v in [l_k, u_k].  Energies and energy differences are
+// exact integers (two's-complement wrap-around arithmetic, exact whenever the true value fits
+// int64, which the host checks); FP64 is used only for the exponentials and logarithms of the
+// acceptance test and the heat-bath draws.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter (k, s, read, instance) and key
-// = seed; the lanes compute the blocks of 64 consecutive variables at once and the update of
-// variable k reads its block from lane k mod 64.
+// = seed; for each block of 64 windows, lane j computes the words of this wave's slot in window
+// j, and the update reads them from lane j.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -316,10 +318,11 @@ __device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE, Acc> &C, int64
 }
 
 // dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
+// linear: no term holds z_k to a power above one, so dE = (sum_t J_t prod(others)) (v - z_k).
 template <typename Acc, typename ZT>
 __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
                                                 int32_t deg, int64_t zk, int64_t v, int lane,
-                                                const IncRec &r0, uint64_t coef0) {
+                                                const IncRec &r0, uint64_t coef0, bool linear) {
     if (P.dense) {
         const Acc a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane)) + (Acc)P.h[k];
         const Acc d = a1 * (Acc)(v - zk) + (Acc)P.d[k] * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk);
@@ -327,6 +330,7 @@ __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z
     }
     int e;
     Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
+    if (linear && deg <= kWave) return to_i64<Acc>(wave_sum<Acc>(prod) * (Acc)(v - zk));
     Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
     for (int32_t c0 = kWave; c0 < deg; c0 += 4 * kWave) {
         IncRec r[4];
@@ -827,7 +831,10 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     if (kRule == SA_METROPOLIS) {
                         v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                         if (v >= zk) v += 1;
-                        d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef);
+                        // (Metropolis kernels are built with kMaxE = 1 for any problem: the
+                        // variable's own exponents decide)
+                        d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef,
+                                                  (lane_read32(sl.emask, j) & ~2u) == 0);
                         accept = metropolis_accept(d, beta, U);
                     } else if (kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED) {
                         Coeffs<kMaxE, Acc> C;
@@ -859,7 +866,8 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;
-                            d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef);
+                            d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef,
+                                                      (lane_read32(sl.emask, j) & ~2u) == 0);
                         }
                         accept = metropolis_accept(d, beta, U);
                     }
