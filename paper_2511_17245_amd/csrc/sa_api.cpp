@@ -319,7 +319,7 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
     sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
                                             plan->info.max_exponent, plan->device, G, plan->narrow_ok,
-                                            a.otm_enum_max);
+                                            a.otm_enum_max, plan->packed.dense);
     sa_plan::Sched *sc = nullptr;
     rc = get_schedule(plan, lc.win_waves, &sc);
     if (rc != SA_OK) {

@@ -158,7 +158,7 @@ int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *s
                   std::string &err);
 // Picks the launch geometry for n_reads replicas of an n-variable problem on `device`.
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device, int win_waves, bool narrow_ok, int32_t otm_enum_max);
+                           int device, int win_waves, bool narrow_ok, int32_t otm_enum_max, bool dense);
 // LDS bytes of one replica's state when its G waves share it (state + per-wave energy slots).
 int64_t shared_state_bytes(int32_t n, int G);
 // Waves of one batch workgroup; a task runs kBatchWaves / G_p reads of problem p.

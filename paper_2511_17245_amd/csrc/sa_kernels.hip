@@ -218,18 +218,36 @@ __device__ __forceinline__ void load_record(const DevProblem &P, int32_t row, in
     }
 }
 
+// Dense form, one window ahead: this lane's first 16 bytes of row k, h_k and the diagonal d_k.
+__device__ __forceinline__ void prefetch_dense(const DevProblem &P, int32_t k, int lane, int4 &first,
+                                               uint64_t &h, int64_t &dk) {
+    first = make_int4(0, 0, 0, 0);
+    h = 0;
+    dk = 0;
+    if (k < 0) return;
+    const int32_t j0 = lane * 16;
+    if (j0 < P.n) {
+        const char *row = (const char *)P.jd + (size_t)k * P.row_stride * P.jbytes;
+        first = *(const int4 *)(row + (size_t)j0 * P.jbytes);
+    }
+    h = (uint64_t)P.h[k];
+    dk = P.d[k];
+}
+
 // Dense form: this lane's part of sum_j J_kj z_j over row k of the coupling matrix.  Lane l reads
 // elements 16l.. of each 1024-element block (one 16-byte load for int8 rows, four for int32); the
 // row's padding is zero, so indexes past N are clamped instead of tested.
+// `first`, when given, holds the lane's first 16 bytes of the row, loaded one window ahead.
 template <typename Acc, typename ZT>
-__device__ __forceinline__ Acc dense_dot(const DevProblem &P, const ZT *z, int32_t k, int lane) {
+__device__ __forceinline__ Acc dense_dot(const DevProblem &P, const ZT *z, int32_t k, int lane,
+                                         const int4 *first) {
     const int32_t n = P.n;
     Acc acc = 0;
     if (P.jbytes == 1) {
         const int8_t *row = (const int8_t *)P.jd + (size_t)k * P.row_stride;
 
         for (int32_t j0 = lane * 16; j0 < n; j0 += kWave * 16) {
-            const int4 q = *(const int4 *)(row + j0);
+            const int4 q = (first && j0 < kWave * 16) ? *first : *(const int4 *)(row + j0);
             const uint32_t w[4] = {(uint32_t)q.x, (uint32_t)q.y, (uint32_t)q.z, (uint32_t)q.w};
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -244,7 +262,8 @@ __device__ __forceinline__ Acc dense_dot(const DevProblem &P, const ZT *z, int32
         for (int32_t j0 = lane * 16; j0 < n; j0 += kWave * 16) {
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) {
-                const int4 q = *(const int4 *)(row + j0 + 4 * q4);
+                const int4 q = (first && q4 == 0 && j0 < kWave * 16) ? *first
+                                                                     : *(const int4 *)(row + j0 + 4 * q4);
                 const int32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -264,6 +283,7 @@ struct Coeffs {
     Acc a[kMaxE + 1];
 };
 
+// r0/coef0: the lane's first incidence record (sparse form), loaded one window ahead.
 template <int kMaxE, typename Acc, typename ZT>
 __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
                                            int32_t deg, uint32_t emask, int lane, const IncRec &r0,
@@ -272,7 +292,7 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int
         // QUIO: a^(1) = h_k + sum_j J_kj z_j, a^(2) = J_kk (Sec. 3.2, the c^(1), c^(2) of QUIO)
 #pragma unroll
         for (int m = 0; m <= kMaxE; ++m) C.a[m] = 0;
-        C.a[1] = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane)) + (Acc)P.h[k];
+        C.a[1] = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, nullptr)) + (Acc)P.h[k];
         if (kMaxE >= 2) C.a[kMaxE >= 2 ? 2 : 1] = (Acc)P.d[k];
         return;
     }
@@ -319,13 +339,18 @@ __device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE, Acc> &C, int64
 
 // dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
 // linear: no term holds z_k to a power above one, so dE = (sum_t J_t prod(others)) (v - z_k).
-template <typename Acc, typename ZT>
+// kDensePre (dense form): r0 holds the lane's first 16 bytes of the coupling row, coef0 = h_k and
+// dk = d_k, all loaded one window ahead; otherwise r0/coef0 are the first incidence record.
+template <typename Acc, typename ZT, bool kDensePre>
 __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
                                                 int32_t deg, int64_t zk, int64_t v, int lane,
-                                                const IncRec &r0, uint64_t coef0, bool linear) {
+                                                const IncRec &r0, uint64_t coef0, int64_t dk, bool linear) {
     if (P.dense) {
-        const Acc a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane)) + (Acc)P.h[k];
-        const Acc d = a1 * (Acc)(v - zk) + (Acc)P.d[k] * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk);
+        const int4 first = make_int4((int)r0.meta, r0.o[0], r0.o[1], r0.o[2]);
+        const Acc a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, kDensePre ? &first : nullptr)) +
+                       (kDensePre ? (Acc)coef0 : (Acc)P.h[k]);
+        const Acc dd = kDensePre ? (Acc)dk : (Acc)P.d[k];
+        const Acc d = a1 * (Acc)(v - zk) + dd * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk);
         return to_i64<Acc>(d);
     }
     int e;
@@ -806,18 +831,31 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
             // U in [0, 1) from words 2 and 3, formed once per lane for its window
             const double Ul = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
             const int32_t wend = n_win - wb < kWave ? n_win - wb : kWave;
-            // first chunk of the next slot's incidence records, loaded one window ahead
+            // first chunk of the next slot's incidence records (the dense-form Metropolis variant,
+            // kRegChunk = 1: of its coupling row, with h_k and d_k), loaded one window ahead
             IncRec nrec;
             uint64_t ncoef;
-            load_record(P, (int32_t)lane_read32((uint32_t)sl.row, 0), (int32_t)lane_read32((uint32_t)sl.deg, 0),
-                        0, lane, nrec, ncoef);
+            int64_t nd = 0;
+            auto prefetch = [&](int32_t jj) {
+                if (kRule == SA_METROPOLIS && kRegChunk == 1) {
+                    int4 q;
+                    prefetch_dense(P, (int32_t)lane_read32((uint32_t)sl.k, jj), lane, q, ncoef, nd);
+                    nrec.meta = (uint32_t)q.x;
+                    nrec.o[0] = q.y;
+                    nrec.o[1] = q.z;
+                    nrec.o[2] = q.w;
+                } else {
+                    load_record(P, (int32_t)lane_read32((uint32_t)sl.row, jj),
+                                (int32_t)lane_read32((uint32_t)sl.deg, jj), 0, lane, nrec, ncoef);
+                }
+            };
+            prefetch(0);
             for (int32_t j = 0; j < wend; ++j) {
                 const int32_t k = (int32_t)lane_read32((uint32_t)sl.k, j);
                 const IncRec crec = nrec;
                 const uint64_t ccoef = ncoef;
-                if (j + 1 < wend)
-                    load_record(P, (int32_t)lane_read32((uint32_t)sl.row, j + 1),
-                                (int32_t)lane_read32((uint32_t)sl.deg, j + 1), 0, lane, nrec, ncoef);
+                const int64_t cd = nd;
+                if (j + 1 < wend) prefetch(j + 1);
                 if (k >= 0) {
                     const int64_t lo = (int32_t)lane_read32((uint32_t)sl.lo, j);
                     const int64_t W = (int32_t)lane_read32((uint32_t)sl.width, j);
@@ -833,7 +871,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         if (v >= zk) v += 1;
                         // (Metropolis kernels are built with kMaxE = 1 for any problem: the
                         // variable's own exponents decide)
-                        d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef,
+                        d = direct_delta<Acc, ZT, kRegChunk == 1>(P, z, k, row, deg, zk, v, lane, crec, ccoef, cd,
                                                   (lane_read32(sl.emask, j) & ~2u) == 0);
                         accept = metropolis_accept(d, beta, U);
                     } else if (kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED) {
@@ -866,7 +904,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;
-                            d = direct_delta<Acc, ZT>(P, z, k, row, deg, zk, v, lane, crec, ccoef,
+                            d = direct_delta<Acc, ZT, false>(P, z, k, row, deg, zk, v, lane, crec, ccoef, cd,
                                                       (lane_read32(sl.emask, j) & ~2u) == 0);
                         }
                         accept = metropolis_accept(d, beta, U);
@@ -1075,7 +1113,7 @@ bool sixteen_waves_ok(int rule, bool in_lds, int reg_chunk, int maxe_class) {
     if (!in_lds || maxe_class > 2) return false;
     if (rule == SA_HEAT_BATH) return reg_chunk >= 1 && reg_chunk <= 8;
     if (rule == SA_HEAT_BATH_CLOSED) return maxe_class == 1;
-    if (rule == SA_OPT_METROPOLIS) return reg_chunk == 0;
+    if (rule == SA_OPT_METROPOLIS || rule == SA_METROPOLIS) return reg_chunk == 0;
     return true;
 }
 
@@ -1110,6 +1148,9 @@ KernelFn pick_kernel_16(int rule, int reg_chunk, int maxe_class, bool narrow) {
 KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool narrow) {
     if (rule == SA_METROPOLIS) {
         if (!in_lds) return anneal_kernel<SA_METROPOLIS, false, 0, 1, uint64_t, 512>;
+        if (reg_chunk == 1)   // dense form: coupling rows prefetched one window ahead
+            return narrow ? anneal_kernel<SA_METROPOLIS, true, 1, 1, uint32_t, 512>
+                          : anneal_kernel<SA_METROPOLIS, true, 1, 1, uint64_t, 512>;
         return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t, 512>
                       : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t, 512>;
     }
@@ -1172,7 +1213,7 @@ int64_t shared_state_bytes(int32_t n, int G) {
 }
 
 LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_width, int32_t max_exp,
-                           int device, int win_waves, bool narrow_ok, int32_t otm_enum_max) {
+                           int device, int win_waves, bool narrow_ok, int32_t otm_enum_max, bool dense) {
     LaunchChoice lc;
     int cus = 256, max_lds = 65536;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -1180,12 +1221,13 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
     const bool heat_bath = rule == SA_HEAT_BATH || rule == SA_HEAT_BATH_CLOSED;
     const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
-    // heat bath: weights per lane kept in registers; optimal transition: 1 = stationary-point argmin
+    // heat bath: weights per lane kept in registers; optimal transition: 1 = stationary-point
+    // argmin; Metropolis: 1 = dense form with prefetched coupling rows
     const bool otm_wide = rule == SA_OPT_METROPOLIS && max_width > otm_enum_max;
     const int reg_in_lds =
         heat_bath && !(rule == SA_HEAT_BATH_CLOSED && max_exp <= 1)
             ? (chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0)
-            : (otm_wide ? 1 : 0);
+            : (otm_wide || (rule == SA_METROPOLIS && dense) ? 1 : 0);
     if (win_waves == 16 && !(shared_state_bytes(n, 16) <= max_lds &&
                              sixteen_waves_ok(rule, true, reg_in_lds, maxe_class_of(max_exp))))
         win_waves = 8;  // no 16-wave build of this variant: the next width gives the same result
