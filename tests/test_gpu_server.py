@@ -23,6 +23,8 @@ def requests(n=10, sweeps=40, reads=5):
         w.instance_id = 1000 + i
         if i % 3 == 0:
             w.beta = oracle.Poly(w.problem).schedule(sweeps)[0]
+        if i % 5 == 4:
+            w.rule = sa.HEAT_BATH_CLOSED   # closed-form draws for linear variables, in the mix too
     return items
 
 
