@@ -268,8 +268,10 @@ int32_t sa_server_cancel(sa_server *server, uint64_t ticket);
 typedef struct {
     int64_t submitted, completed, canceled, failed;
     int64_t active, queued, chunks, updates;
-    size_t mem_in_use;
+    size_t mem_in_use;          /* device bytes held: admitted requests and cached plans */
     double elapsed_s;
+    int64_t plans_reused;       /* requests served by a plan cached from an earlier request with the
+                                   same instance, bounds and rule (content hash) */
 } sa_server_stats;
 int32_t sa_server_get_stats(sa_server *server, sa_server_stats *stats);
 /* Cancels what has not finished, joins the threads and frees everything. */

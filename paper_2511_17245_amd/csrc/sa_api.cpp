@@ -184,6 +184,7 @@ int stage_beta(sa_plan *plan, const std::vector<double> &beta, hipStream_t strea
 }
 
 int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out) {
+    std::lock_guard<std::mutex> lk(plan->sched_mu);
     sa_plan::Sched &sc = plan->sched[G];
     if (!sc.dev) {
         std::vector<sa::SchedRec> host;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,7 @@ struct sa_plan {
         int32_t n_active = 0;  // variables that are not fixed
     };
     Sched sched[17];  // index G = 1, 2, 4, 8, 16
+    std::mutex sched_mu;  // guards the lazy building of sched (a server's preparers share plans)
     ~sa_plan() {
         if (beta_dev) (void)hipFree(beta_dev);
         for (auto &sc : sched)

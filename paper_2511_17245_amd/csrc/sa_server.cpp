@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -49,6 +50,8 @@ struct Request {
     sa_result result{};
     sa_plan *plan = nullptr;
     bool own_plan = false;
+    bool cached = false;              // plan shared through the server's plan cache
+    std::array<uint64_t, 3> cache_key{};
     std::vector<double> beta;
     // device state of an admitted request
     void *mem = nullptr;  // beta | states | energies
@@ -98,6 +101,19 @@ struct sa_server {
     // chunk launch buffers (scheduler thread only)
     sa::DevArena chunk_mem;
     size_t chunk_cap = 0;
+    // plans of recently submitted instances, reused by later requests with the same instance,
+    // bounds and rule (content hash).  A plan's device bytes count in mem_used while at least one
+    // admitted request uses it; idle cached plans are bounded by the cache limits instead.
+    struct Cached {
+        sa_plan *plan = nullptr;
+        int64_t refs = 0;      // requests holding the plan (prepared, admitted or running)
+        int64_t active = 0;    // admitted requests among them
+        uint64_t last_use = 0;
+        size_t bytes = 0;
+    };
+    std::map<std::array<uint64_t, 3>, Cached> plan_cache;
+    uint64_t cache_tick = 0;
+    int64_t plans_reused = 0;
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -116,6 +132,45 @@ void finish_locked(sa_server *S, Request *r, int32_t status) {
     S->cv_done.notify_all();
 }
 
+constexpr size_t kMaxCachedPlans = 64;
+
+// Frees cached plans no request holds, least recently used first, down to the cache limits
+// (entry count, and a quarter of the memory budget).  S->mu held.
+void evict_plans_locked(sa_server *S) {
+    size_t cached_bytes = 0;
+    for (auto &kv : S->plan_cache) cached_bytes += kv.second.bytes;
+    for (;;) {
+        const bool over = S->plan_cache.size() > kMaxCachedPlans || cached_bytes > S->opts.mem_budget_bytes / 4;
+        if (!over) return;
+        auto victim = S->plan_cache.end();
+        for (auto it = S->plan_cache.begin(); it != S->plan_cache.end(); ++it)
+            if (it->second.refs == 0 &&
+                (victim == S->plan_cache.end() || it->second.last_use < victim->second.last_use))
+                victim = it;
+        if (victim == S->plan_cache.end()) return;   // every cached plan is in use
+        cached_bytes -= victim->second.bytes;
+        delete victim->second.plan;
+        S->plan_cache.erase(victim);
+    }
+}
+
+
+// Gives up the request's plan: deletes an owned one, releases a cached one.  S->mu held.
+void drop_plan_locked(sa_server *S, Request *r) {
+    if (r->own_plan && r->plan) delete r->plan;
+    if (r->cached) {
+        auto it = S->plan_cache.find(r->cache_key);
+        if (it != S->plan_cache.end()) {
+            it->second.refs--;
+            it->second.last_use = ++S->cache_tick;
+        }
+        r->cached = false;
+        evict_plans_locked(S);
+    }
+    r->plan = nullptr;
+    r->own_plan = false;
+}
+
 void release_device(sa_server *S, Request *r) {
     if (r->mem) {
         (void)hipFree(r->mem);
@@ -123,12 +178,44 @@ void release_device(sa_server *S, Request *r) {
     }
     if (r->accounted) {
         S->mem_used -= r->footprint;
+        if (r->cached) {
+            auto it = S->plan_cache.find(r->cache_key);
+            if (it != S->plan_cache.end() && --it->second.active == 0) S->mem_used -= it->second.bytes;
+        }
         r->accounted = false;
     }
-    if (r->own_plan && r->plan) {
-        delete r->plan;
-        r->plan = nullptr;
-    }
+    drop_plan_locked(S, r);
+}
+
+// Content hash of a submitted problem (two independent 64-bit streams plus the rule).
+std::array<uint64_t, 3> problem_key(const Request &r) {
+    uint64_t h1 = 0x243F6A8885A308D3ull, h2 = 0x13198A2E03707344ull;
+    auto mix = [&](uint64_t w) {
+        h1 = (h1 ^ w) * 0x9E3779B97F4A7C15ull;
+        h1 ^= h1 >> 29;
+        h2 = (h2 + w) * 0xC2B2AE3D27D4EB4Full;
+        h2 = (h2 << 31) | (h2 >> 33);
+    };
+    auto bytes = [&](const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t w;
+            std::memcpy(&w, c + i, 8);
+            mix(w);
+        }
+        uint64_t tail = 0;
+        std::memcpy(&tail, c + i, n - i);
+        mix(tail ^ ((uint64_t)n << 56));
+    };
+    mix((uint64_t)r.n_vars);
+    mix((uint64_t)r.n_terms);
+    bytes(r.term_ptr.data(), sizeof(int64_t) * r.term_ptr.size());
+    bytes(r.factor_var.data(), sizeof(int32_t) * r.factor_var.size());
+    bytes(r.coef.data(), sizeof(int64_t) * r.coef.size());
+    bytes(r.lo.data(), sizeof(int32_t) * r.lo.size());
+    bytes(r.hi.data(), sizeof(int32_t) * r.hi.size());
+    return {h1, h2, (uint64_t)(uint32_t)r.rule};
 }
 
 void prep_loop(sa_server *S) {
@@ -150,15 +237,46 @@ void prep_loop(sa_server *S) {
         int rc = SA_OK;
         std::string err;
         if (!r->plan) {
-            sa_instance inst{r->n_vars, r->n_terms, r->term_ptr.data(), r->factor_var.data(), r->coef.data()};
-            sa_bounds bounds{r->lo.data(), r->hi.data()};
-            sa_plan *p = nullptr;
-            rc = sa::build_plan(&inst, &bounds, r->rule, &p);
-            if (rc == SA_OK) {
-                r->plan = p;
-                r->own_plan = true;
-            } else {
-                err = sa_last_error();
+            // a plan of the same instance, bounds and rule may be cached from an earlier request
+            const std::array<uint64_t, 3> key = problem_key(*r);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                auto it = S->plan_cache.find(key);
+                if (it != S->plan_cache.end()) {
+                    it->second.refs++;
+                    r->plan = it->second.plan;
+                    r->cached = true;
+                    r->cache_key = key;
+                    S->plans_reused++;
+                }
+            }
+            if (!r->plan) {
+                sa_instance inst{r->n_vars, r->n_terms, r->term_ptr.data(), r->factor_var.data(), r->coef.data()};
+                sa_bounds bounds{r->lo.data(), r->hi.data()};
+                sa_plan *p = nullptr;
+                rc = sa::build_plan(&inst, &bounds, r->rule, &p);
+                if (rc == SA_OK) {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    auto it = S->plan_cache.find(key);
+                    if (it != S->plan_cache.end()) {
+                        // another preparer cached the same instance meanwhile: use that one
+                        delete p;
+                        it->second.refs++;
+                        r->plan = it->second.plan;
+                        S->plans_reused++;
+                    } else {
+                        auto &e = S->plan_cache[key];
+                        e.plan = p;
+                        e.refs = 1;
+                        e.last_use = ++S->cache_tick;
+                        e.bytes = p->arena.bytes;
+                        r->plan = p;
+                    }
+                    r->cached = true;
+                    r->cache_key = key;
+                } else {
+                    err = sa_last_error();
+                }
             }
         }
         if (rc == SA_OK) {
@@ -179,6 +297,7 @@ void prep_loop(sa_server *S) {
         }
         if (rc == SA_OK) {
             const size_t zb = sizeof(int32_t) * (size_t)r->n_reads * (size_t)r->plan->dp.n;
+            // a cached plan's arena is counted once, while admitted requests use it (admission)
             r->footprint = align256(sizeof(double) * r->beta.size()) + align256(zb) +
                            align256(sizeof(int64_t) * (size_t)r->n_reads) +
                            (r->own_plan ? r->plan->arena.bytes : 0);
@@ -187,16 +306,10 @@ void prep_loop(sa_server *S) {
         S->in_prep--;
         if (rc != SA_OK) {
             r->error = err;
-            if (r->own_plan) {
-                delete r->plan;
-                r->plan = nullptr;
-            }
+            drop_plan_locked(S, r);
             finish_locked(S, r, rc);
         } else if (r->cancel) {
-            if (r->own_plan) {
-                delete r->plan;
-                r->plan = nullptr;
-            }
+            drop_plan_locked(S, r);
             finish_locked(S, r, SA_ECANCELED);
         } else {
             r->phase = Phase::Prepared;
@@ -378,16 +491,29 @@ void scheduler_loop(sa_server *S) {
                         finish_locked(S, r, SA_ECANCELED);
                         continue;
                     }
-                    if (r->footprint > S->opts.mem_budget_bytes) {
+                    // the plan's bytes count with the first admitted request that uses it
+                    size_t plan_bytes = 0, plan_need = 0;
+                    if (r->cached) {
+                        auto it = S->plan_cache.find(r->cache_key);
+                        if (it != S->plan_cache.end()) {
+                            plan_bytes = it->second.bytes;
+                            plan_need = it->second.active == 0 ? plan_bytes : 0;
+                        }
+                    }
+                    if (r->footprint + plan_bytes > S->opts.mem_budget_bytes) {
                         S->ready.erase(S->ready.begin());
                         r->error = "request footprint exceeds the server's memory budget";
                         release_device(S, r);
                         finish_locked(S, r, SA_ENOMEM);
                         continue;
                     }
-                    if (S->mem_used + r->footprint > S->opts.mem_budget_bytes) break;
+                    if (S->mem_used + r->footprint + plan_need > S->opts.mem_budget_bytes) break;
                     S->ready.erase(S->ready.begin());
-                    S->mem_used += r->footprint;
+                    S->mem_used += r->footprint + plan_need;
+                    if (r->cached) {
+                        auto it = S->plan_cache.find(r->cache_key);
+                        if (it != S->plan_cache.end()) it->second.active++;
+                    }
                     r->accounted = true;
                     r->phase = Phase::Active;
                     r->t_admit = S->now();
@@ -609,6 +735,7 @@ int32_t sa_server_get_stats(sa_server *S, sa_server_stats *st) {
     st->updates = S->updates_done;
     st->mem_in_use = S->mem_used;
     st->elapsed_s = S->now();
+    st->plans_reused = S->plans_reused;
     return SA_OK;
 }
 
@@ -634,6 +761,8 @@ void sa_server_destroy(sa_server *S) {
             }
         }
     }
+    for (auto &kv : S->plan_cache) delete kv.second.plan;
+    S->plan_cache.clear();
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
 }

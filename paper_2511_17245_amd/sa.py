@@ -94,7 +94,8 @@ class sa_timing(C.Structure):
 class sa_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("canceled", C.c_int64),
                 ("failed", C.c_int64), ("active", C.c_int64), ("queued", C.c_int64), ("chunks", C.c_int64),
-                ("updates", C.c_int64), ("mem_in_use", C.c_size_t), ("elapsed_s", C.c_double)]
+                ("updates", C.c_int64), ("mem_in_use", C.c_size_t), ("elapsed_s", C.c_double),
+                ("plans_reused", C.c_int64)]
 
 
 _lib = None

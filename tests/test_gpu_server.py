@@ -88,6 +88,24 @@ def test_memory_budget_admission():
     srv.close()
 
 
+def test_repeated_instances_share_a_cached_plan():
+    # requests over the same instance (different seeds and ids) reuse one prepared plan; results
+    # are still those of each request alone
+    base = I.cfg3_huio(rule="otm", n=300, m=3000, n_sweeps=30, n_reads=4)
+    items = []
+    for i in range(9):
+        w = I.Workload(base.problem, sa.OPT_METROPOLIS if i % 3 else sa.HEAT_BATH, 30, 4, 100 + i, 500 + i)
+        items.append(w)
+    out, timings, stats = serve(items, chunk_sweeps=10)
+    say("stats", stats)
+    assert all(t["status"] == sa.OK for t in timings)
+    # two rules, two plans; at most one extra build per preparer racing on the same instance
+    assert stats["plans_reused"] >= len(items) - 2 - 4
+    for i, w in enumerate(items):
+        z, e = alone(w)
+        assert np.array_equal(out[i][0], z) and np.array_equal(out[i][1], e), f"request {i}"
+
+
 def test_cancel_leaves_others_untouched():
     items = requests(n=6, sweeps=30, reads=4)
     long = I.cfg3_huio(rule="otm", n=1500, m=15000, n_sweeps=100000, n_reads=8)
