@@ -81,15 +81,19 @@ def workload(args):
     return w
 
 
+# the sources that define the device program and the data it reads: kernels, their argument
+# layout, the instance packing and the launch choice
+KERNEL_SOURCES = ("sa_kernels.hip", "sa_internal.h", "sa_host.cpp")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP library sources: HBM traffic measured with counters applies only to the
-    kernels built from exactly these sources."""
+    """Hash of the kernel sources: HBM traffic measured with counters applies only to the kernels
+    built from exactly these sources."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp", ".h")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
