@@ -489,6 +489,18 @@ def bench_serving(args):
     lat = np.array([t["t_done"] - t["t_submit"] for t in ok])
     span = max(t["t_done"] for t in ok) - min(t["t_submit"] for t in ok)
     upd = float(sum(t["updates"] for t in ok))
+    # where the time goes, per request kind: waiting (preparation and admission) and running
+    by_kind = {}
+    for kind, sel in (("huio", lambda w: w.rule != sa.HEAT_BATH), ("dense_heat_bath", lambda w: w.rule == sa.HEAT_BATH)):
+        idx = [i for i, w in enumerate(reqs) if sel(w) and tim[i]["status"] == sa.OK]
+        if not idx:
+            continue
+        wait = np.array([tim[i]["t_admit"] - tim[i]["t_submit"] for i in idx])
+        run = np.array([tim[i]["t_done"] - tim[i]["t_admit"] for i in idx])
+        tot = wait + run
+        by_kind[kind] = {"count": len(idx), "p50": float(np.percentile(tot, 50)), "p99": float(np.percentile(tot, 99)),
+                         "wait_p50": float(np.percentile(wait, 50)), "wait_p99": float(np.percentile(wait, 99)),
+                         "run_p50": float(np.percentile(run, 50)), "run_p99": float(np.percentile(run, 99))}
     # alone-versus-mix identity on a sample of requests
     rng = np.random.Generator(np.random.PCG64(555))
     sample = rng.choice(n, size=min(12, n), replace=False)
@@ -516,6 +528,7 @@ def bench_serving(args):
                    "chunk_sweeps": 50},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
+        "latency_by_kind_s": by_kind,
         "completed": len(ok), "server": stats, "alone_vs_mix_identical": bool(same),
     }
     print(json.dumps(out), flush=True)
