@@ -56,8 +56,8 @@ def parse():
                     help="oracle reads behind the target energy and the CPU time (0: automatic)")
     ap.add_argument("--no-closed-form", action="store_true",
                     help="cfg2: skip timing the closed-form heat-bath draw beside the enumeration")
-    ap.add_argument("--cpu-reads", type=int, default=32)
-    ap.add_argument("--cpu-sweeps", type=int, default=100)
+    ap.add_argument("--cpu-reads", type=int, default=16)
+    ap.add_argument("--cpu-sweeps", type=int, default=0, help="0: the whole schedule")
     return ap.parse_args()
 
 
@@ -83,7 +83,9 @@ def workload(args):
 
 # the sources that define the device program and the data it reads: kernels, their argument
 # layout, the instance packing and the launch choice
-KERNEL_SOURCES = ("sa_kernels.hip", "sa_internal.h", "sa_host.cpp")
+KERNEL_SOURCES = ("sa_device.h", "sa_kernels.hip", "sa_kernels_heat_bath.hip", "sa_kernels_heat_bath_closed.hip",
+                  "sa_kernels_metropolis.hip", "sa_kernels_otm.hip", "sa_kernels_batch.hip",
+                  "sa_kernels_batch16.hip", "sa_kernel_table.h", "sa_internal.h", "sa_host.cpp")
 
 
 def kernel_source_hash() -> str:
@@ -128,14 +130,15 @@ def cpu_baseline(w, beta, n_reads, n_sweeps):
     P = oracle.Poly(w.problem)
     threads = oracle.default_threads()
     b = np.ascontiguousarray(beta[:n_sweeps])
-    # the sample runs the first n_sweeps of the real schedule, so the high-temperature phase
-    # (most accepted moves, most coefficient updates) is represented
+    # the sample runs the first n_sweeps of the real schedule (by default all of it), so every
+    # temperature phase is represented
     t0 = time.perf_counter()
     P.anneal(w.rule, b, n_reads, w.seed, w.instance_id, cache_mode=1, n_threads=threads)
     dt = time.perf_counter() - t0
     upd = n_reads * n_sweeps * w.problem.n_vars
     return {"value": upd / dt, "unit": "updates/s", "cores": min(threads, n_reads), "kind": "oracle",
-            "sample": f"{n_reads} reads x first {n_sweeps} of {w.n_sweeps} sweeps of the same workload "
+            "sample": f"{n_reads} reads x {'all' if n_sweeps == w.n_sweeps else 'first ' + str(n_sweeps) + ' of'} "
+                      f"{w.n_sweeps} sweeps of the same workload "
                       f"({upd:.3g} updates, {dt:.1f} s, coefficient-cache mode)"}
 
 
@@ -646,7 +649,8 @@ def main():
         cplan.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, beta, min(args.cpu_reads, R), min(args.cpu_sweeps, S))
+        out["cpu_baseline"] = cpu_baseline(w, beta, min(args.cpu_reads, R),
+                                           S if args.cpu_sweeps <= 0 else min(args.cpu_sweeps, S))
     print(json.dumps(out), flush=True)
 
 

@@ -1,1077 +1,11 @@
-// sa_kernels.hip -- gfx950 kernels of the single-variable update sweep (Sec. 3.1) for QUIO/HUIO.
-//
-// Mapping: a replica (read) is updated by one 64-lane wavefront, or by G = 2, 4, 8 or 16 waves of
-// a workgroup that update the G mutually non-interacting variables of a schedule window at once
-// (a barrier closes each window; the result equals the sequential sweep).  With G = 1 the waves of
-// a workgroup are independent replicas.  A replica's state z lives in LDS when it fits, else in
-// its row of the output buffer.  For the visited variable k the lanes split the terms containing
-// z_k (each lane forms one term's product of the other factors) and, for the heat bath and the
-// optimal transition, the candidate values v in [l_k, u_k].  Energies and energy differences are
-// exact integers (two's-complement wrap-around arithmetic, exact whenever the true value fits
-// int64, which the host checks); FP64 is used only for the exponentials and logarithms of the
-// acceptance test and the heat-bath draws.
-//
-// Random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter (k, s, read, instance) and key
-// = seed; for each block of 64 windows, lane j computes the words of this wave's slot in window
-// j, and the update reads them from lane j.
-#include <hip/hip_runtime.h>
-
-#include <climits>
-#include <cstdint>
-
-#include "sa_internal.h"
+// sa_kernels.hip -- launch geometry and dispatch of the plain annealing kernels, and the energy
+// kernel.  The annealing kernels themselves (sa_device.h) are compiled per rule in
+// sa_kernels_<rule>.hip; the batched kernel in sa_kernels_batch.hip.
+#include "sa_device.h"
+#include "sa_kernel_table.h"
 
 namespace sa {
 namespace {
-
-constexpr int kWave = 64;
-
-// ------------------------------------------------------------------------------------------------
-// Philox4x32-10 block function.
-// ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
-                                              uint32_t &c3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        const uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
-        const uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
-// Wavefront collectives.  Integer reductions are order-independent (wrap-around sums, min), so any
-// exchange pattern gives the same value.
-// ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t uni32(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-}
-__device__ __forceinline__ uint32_t lane_read32(uint32_t x, int lane) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
-}
-
-__device__ __forceinline__ uint64_t lane_read64(uint64_t x, int lane) {
-    return ((uint64_t)lane_read32((uint32_t)(x >> 32), lane) << 32) | lane_read32((uint32_t)x, lane);
-}
-
-// DPP move of a 64-bit value (two 32-bit halves); lanes without a valid source take `identity`.
-template <int kCtrl, int kRowMask, int kBankMask>
-__device__ __forceinline__ uint64_t dpp64(uint64_t x, uint64_t identity) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)identity, (int)(uint32_t)x,
-                                                              kCtrl, kRowMask, kBankMask, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(identity >> 32),
-                                                              (int)(uint32_t)(x >> 32), kCtrl, kRowMask,
-                                                              kBankMask, false);
-    return ((uint64_t)hi << 32) | lo;
-}
-// DPP move of a 64-bit value over all rows; lanes whose source lies outside their row read zero
-// (bound_ctrl), so no old value is needed.
-template <int kCtrl>
-__device__ __forceinline__ uint64_t dpp64_zero(uint64_t x) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)x, kCtrl, 0xf, 0xf, true);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), kCtrl, 0xf, 0xf, true);
-    return ((uint64_t)hi << 32) | lo;
-}
-template <int kCtrl, int kRowMask, int kBankMask>
-__device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t identity) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, kCtrl, kRowMask, kBankMask, false);
-}
-
-// GFX9 DPP controls: row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143,
-// wave_shr:1 = 0x138.  The six steps below form an inclusive scan whose lane 63 holds the
-// reduction of all 64 lanes (rows of 16 lanes, then the row broadcasts).
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-    x += dpp64<0x111, 0xf, 0xf>(x, 0);
-    x += dpp64<0x112, 0xf, 0xf>(x, 0);
-    x += dpp64<0x114, 0xf, 0xf>(x, 0);
-    x += dpp64<0x118, 0xf, 0xf>(x, 0);
-    x += dpp64<0x142, 0xa, 0xf>(x, 0);
-    x += dpp64<0x143, 0xc, 0xf>(x, 0);
-    return lane_read64(x, kWave - 1);
-}
-
-__device__ __forceinline__ int64_t min64(int64_t a, uint64_t b) { return (int64_t)b < a ? (int64_t)b : a; }
-
-__device__ __forceinline__ int64_t wave_min_i64(int64_t x) {
-    const uint64_t id = (uint64_t)INT64_MAX;
-    x = min64(x, dpp64<0x111, 0xf, 0xf>((uint64_t)x, id));
-    x = min64(x, dpp64<0x112, 0xf, 0xf>((uint64_t)x, id));
-    x = min64(x, dpp64<0x114, 0xf, 0xf>((uint64_t)x, id));
-    x = min64(x, dpp64<0x118, 0xf, 0xf>((uint64_t)x, id));
-    x = min64(x, dpp64<0x142, 0xa, 0xf>((uint64_t)x, id));
-    x = min64(x, dpp64<0x143, 0xc, 0xf>((uint64_t)x, id));
-    return (int64_t)lane_read64((uint64_t)x, kWave - 1);
-}
-
-__device__ __forceinline__ int32_t min32(int32_t a, uint32_t b) { return (int32_t)b < a ? (int32_t)b : a; }
-
-__device__ __forceinline__ int32_t wave_min_i32(int32_t x) {
-    const uint32_t id = (uint32_t)INT32_MAX;
-    x = min32(x, dpp32<0x111, 0xf, 0xf>((uint32_t)x, id));
-    x = min32(x, dpp32<0x112, 0xf, 0xf>((uint32_t)x, id));
-    x = min32(x, dpp32<0x114, 0xf, 0xf>((uint32_t)x, id));
-    x = min32(x, dpp32<0x118, 0xf, 0xf>((uint32_t)x, id));
-    x = min32(x, dpp32<0x142, 0xa, 0xf>((uint32_t)x, id));
-    x = min32(x, dpp32<0x143, 0xc, 0xf>((uint32_t)x, id));
-    return (int32_t)lane_read32((uint32_t)x, kWave - 1);
-}
-
-// Lane l receives lane l-1's value (lane 0 receives `first`): DPP wave_shr:1.
-__device__ __forceinline__ double wave_shift_up1(double x, double first) {
-    const uint64_t b = dpp64<0x138, 0xf, 0xf>((uint64_t)__double_as_longlong(x),
-                                              (uint64_t)__double_as_longlong(first));
-    return __longlong_as_double((long long)b);
-}
-
-// Orders a lane's LDS/global state write before later reads by other lanes of the same wave.
-template <bool kStateInLds>
-__device__ __forceinline__ void state_write_fence() {
-    if (kStateInLds) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-}
-
-// Integer arithmetic of energy differences is done modulo 2^32 (Acc = uint32_t) or 2^64
-// (Acc = uint64_t).  Sums and products of a ring are exact modulo its size, so a result whose
-// true value fits the signed range is exact whatever the intermediate wrap-arounds; the host
-// picks 32 bits only when every |dE| of the problem is below 2^30 (differences of two values
-// then fit too).
-template <typename Acc>
-__device__ __forceinline__ int64_t to_i64(Acc x) {
-    if (sizeof(Acc) == 4) return (int64_t)(int32_t)(uint32_t)x;
-    return (int64_t)(uint64_t)x;
-}
-
-template <typename Acc>
-__device__ __forceinline__ Acc wave_sum(Acc x);
-template <>
-__device__ __forceinline__ uint64_t wave_sum<uint64_t>(uint64_t x) { return wave_sum_u64(x); }
-template <>
-__device__ __forceinline__ uint32_t wave_sum<uint32_t>(uint32_t x) {
-    x += dpp32<0x111, 0xf, 0xf>(x, 0);
-    x += dpp32<0x112, 0xf, 0xf>(x, 0);
-    x += dpp32<0x114, 0xf, 0xf>(x, 0);
-    x += dpp32<0x118, 0xf, 0xf>(x, 0);
-    x += dpp32<0x142, 0xa, 0xf>(x, 0);
-    x += dpp32<0x143, 0xc, 0xf>(x, 0);
-    return lane_read32(x, kWave - 1);
-}
-
-// x^e with wrap-around
-template <typename Acc>
-__device__ __forceinline__ Acc upow(Acc x, int e) {
-    Acc r = 1;
-    for (int i = 0; i < e; ++i) r *= x;
-    return r;
-}
-
-// J_t times the product of the term's other factors, for one incidence record of the row being
-// visited.  Sets e to the exponent of the visited variable in the term.  A zero record (meta = 0,
-// coef = 0) contributes nothing, so lanes beyond the row hold one.
-template <typename Acc, typename ZT>
-__device__ __forceinline__ Acc record_product(const DevProblem &P, const ZT *z, const IncRec &r,
-                                              uint64_t coef, int &e) {
-    e = (int)(r.meta & 0xFFu);
-    const int no = (int)(r.meta >> 8);
-    Acc prod = (Acc)coef;
-    if (P.max_other <= 1) {
-        // pair terms only (QUIO): at most one other factor
-        const int64_t z0 = z[r.o[0]];
-        prod *= no > 0 ? (Acc)z0 : (Acc)1;
-    } else if (no <= 3) {
-        // all three reads issued together (unused slots hold index 0, a valid variable)
-        const int64_t z0 = z[r.o[0]], z1 = z[r.o[1]], z2 = z[r.o[2]];
-        prod *= no > 0 ? (Acc)z0 : (Acc)1;
-        prod *= no > 1 ? (Acc)z1 : (Acc)1;
-        prod *= no > 2 ? (Acc)z2 : (Acc)1;
-    } else {
-        const int32_t *o = P.overflow + r.o[0];
-        for (int f = 0; f < no; ++f) prod *= (Acc)(int64_t)z[o[f]];
-    }
-    return prod;
-}
-
-// Loads this lane's record of chunk [c0, c0 + 64) of a row (a zero record past the row's end).
-__device__ __forceinline__ void load_record(const DevProblem &P, int32_t row, int32_t deg, int32_t c0,
-                                            int lane, IncRec &r, uint64_t &coef) {
-    if (lane < deg - c0) {
-        r = P.inc[row + c0 + lane];
-        coef = (uint64_t)P.inc_coef[row + c0 + lane];
-    } else {
-        r.meta = 0;
-        r.o[0] = r.o[1] = r.o[2] = 0;
-        coef = 0;
-    }
-}
-
-// Dense form, one window ahead: this lane's first 16 bytes of row k, h_k and the diagonal d_k.
-__device__ __forceinline__ void prefetch_dense(const DevProblem &P, int32_t k, int lane, int4 &first,
-                                               uint64_t &h, int64_t &dk) {
-    first = make_int4(0, 0, 0, 0);
-    h = 0;
-    dk = 0;
-    if (k < 0) return;
-    const int32_t j0 = lane * 16;
-    if (j0 < P.n) {
-        const char *row = (const char *)P.jd + (size_t)k * P.row_stride * P.jbytes;
-        first = *(const int4 *)(row + (size_t)j0 * P.jbytes);
-    }
-    h = (uint64_t)P.h[k];
-    dk = P.d[k];
-}
-
-// Dense form: this lane's part of sum_j J_kj z_j over row k of the coupling matrix.  Lane l reads
-// elements 16l.. of each 1024-element block (one 16-byte load for int8 rows, four for int32); the
-// row's padding is zero, so indexes past N are clamped instead of tested.
-// `first`, when given, holds the lane's first 16 bytes of the row, loaded one window ahead.
-template <typename Acc, typename ZT>
-__device__ __forceinline__ Acc dense_dot(const DevProblem &P, const ZT *z, int32_t k, int lane,
-                                         const int4 *first) {
-    const int32_t n = P.n;
-    Acc acc = 0;
-    if (P.jbytes == 1) {
-        const int8_t *row = (const int8_t *)P.jd + (size_t)k * P.row_stride;
-
-        for (int32_t j0 = lane * 16; j0 < n; j0 += kWave * 16) {
-            const int4 q = (first && j0 < kWave * 16) ? *first : *(const int4 *)(row + j0);
-            const uint32_t w[4] = {(uint32_t)q.x, (uint32_t)q.y, (uint32_t)q.z, (uint32_t)q.w};
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int32_t jv = (int32_t)(int8_t)(w[u >> 2] >> (8 * (u & 3)));
-                const int32_t j = j0 + u < n ? j0 + u : n - 1;
-                acc += (Acc)(int64_t)jv * (Acc)(int64_t)z[j];
-            }
-        }
-    } else {
-        const int32_t *row = (const int32_t *)P.jd + (size_t)k * P.row_stride;
-
-        for (int32_t j0 = lane * 16; j0 < n; j0 += kWave * 16) {
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const int4 q = (first && q4 == 0 && j0 < kWave * 16) ? *first
-                                                                     : *(const int4 *)(row + j0 + 4 * q4);
-                const int32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int32_t j = j0 + 4 * q4 + u < n ? j0 + 4 * q4 + u : n - 1;
-                    acc += (Acc)(int64_t)w[u] * (Acc)(int64_t)z[j];
-                }
-            }
-        }
-    }
-    return acc;
-}
-
-// Uniform coefficients a_k^(m) (Sec. 3.2, T_k = sum_m a_k^(m) z_k^m) for m = 1..kMaxE; every
-// index is static so the coefficients stay in registers.
-template <int kMaxE, typename Acc>
-struct Coeffs {
-    Acc a[kMaxE + 1];
-};
-
-// r0/coef0: the lane's first incidence record (sparse form), loaded one window ahead.
-template <int kMaxE, typename Acc, typename ZT>
-__device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
-                                           int32_t deg, uint32_t emask, int lane, const IncRec &r0,
-                                           uint64_t coef0, Coeffs<kMaxE, Acc> &C) {
-    if (P.dense) {
-        // QUIO: a^(1) = h_k + sum_j J_kj z_j, a^(2) = J_kk (Sec. 3.2, the c^(1), c^(2) of QUIO)
-#pragma unroll
-        for (int m = 0; m <= kMaxE; ++m) C.a[m] = 0;
-        C.a[1] = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, nullptr)) + (Acc)P.h[k];
-        if (kMaxE >= 2) C.a[kMaxE >= 2 ? 2 : 1] = (Acc)P.d[k];
-        return;
-    }
-    Acc part[kMaxE + 1];
-#pragma unroll
-    for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
-    {
-        int e;
-        const Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
-#pragma unroll
-        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
-    }
-    // further chunks (dense rows): four chunks' records are loaded before any is used
-    for (int32_t c0 = kWave; c0 < deg; c0 += 4 * kWave) {
-        IncRec r[4];
-        uint64_t coef[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) load_record(P, row, deg, c0 + u * kWave, lane, r[u], coef[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int e;
-            const Acc prod = record_product<Acc, ZT>(P, z, r[u], coef[u], e);
-#pragma unroll
-            for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
-        }
-    }
-    C.a[0] = 0;
-#pragma unroll
-    for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? wave_sum<Acc>(part[m]) : (Acc)0;
-}
-
-// dE(v) = sum_m a^(m) (v^m - z_k^m)  (Sec. 3.2)
-template <int kMaxE, typename Acc>
-__device__ __forceinline__ int64_t poly_delta(const Coeffs<kMaxE, Acc> &C, int64_t zk, int64_t v) {
-    Acc d = C.a[1] * (Acc)(v - zk), vp = (Acc)v, zp = (Acc)zk;
-#pragma unroll
-    for (int m = 2; m <= kMaxE; ++m) {
-        vp *= (Acc)v;
-        zp *= (Acc)zk;
-        d += C.a[m] * (vp - zp);
-    }
-    return to_i64<Acc>(d);
-}
-
-// dE of one proposed value, directly from the row: sum over terms of J_t prod(others) (v^e - z^e).
-// linear: no term holds z_k to a power above one, so dE = (sum_t J_t prod(others)) (v - z_k).
-// kDensePre (dense form): r0 holds the lane's first 16 bytes of the coupling row, coef0 = h_k and
-// dk = d_k, all loaded one window ahead; otherwise r0/coef0 are the first incidence record.
-template <typename Acc, typename ZT, bool kDensePre>
-__device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
-                                                int32_t deg, int64_t zk, int64_t v, int lane,
-                                                const IncRec &r0, uint64_t coef0, int64_t dk, bool linear) {
-    if (P.dense) {
-        const int4 first = make_int4((int)r0.meta, r0.o[0], r0.o[1], r0.o[2]);
-        const Acc a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, kDensePre ? &first : nullptr)) +
-                       (kDensePre ? (Acc)coef0 : (Acc)P.h[k]);
-        const Acc dd = kDensePre ? (Acc)dk : (Acc)P.d[k];
-        const Acc d = a1 * (Acc)(v - zk) + dd * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk);
-        return to_i64<Acc>(d);
-    }
-    int e;
-    Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
-    if (linear && deg <= kWave) return to_i64<Acc>(wave_sum<Acc>(prod) * (Acc)(v - zk));
-    Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
-    for (int32_t c0 = kWave; c0 < deg; c0 += 4 * kWave) {
-        IncRec r[4];
-        uint64_t coef[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) load_record(P, row, deg, c0 + u * kWave, lane, r[u], coef[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            prod = record_product<Acc, ZT>(P, z, r[u], coef[u], e);
-            acc += prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));
-        }
-    }
-    return to_i64<Acc>(wave_sum<Acc>(acc));
-}
-
-// e^x for x <= 0 (every exponential of the annealer has a non-positive argument): x = n ln 2 + r
-// with |r| <= ln(2)/2, e^r by its Taylor polynomial to r^13 (truncation below 2^-57 relative), then
-// scaled by 2^n; 0 below -745.2, where e^x is under half the smallest subnormal.  Within about an
-// ulp, like the host library the oracle uses; a last-bit difference moves a draw only when a
-// uniform number falls within that ulp of a threshold.
-__device__ __forceinline__ double exp_nonpos(double x) {
-    const double xc = x > -746.0 ? x : -746.0;
-    const double n = rint(xc * 1.4426950408889634);     // 1 / ln 2
-    double r = fma(-n, 0.6931471803691238, xc);          // ln 2 rounded to 32 bits (n * it exact)
-    r = fma(-n, 1.9082149292705877e-10, r);              // the rest of ln 2
-    double p = 1.0 / 6227020800.0;                       // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    const double e = __builtin_amdgcn_ldexp(p, (int)n);
-    return x < -745.2 ? 0.0 : e;
-}
-
-// Metropolis acceptance min[1, exp(-dE/T)] (Sec. 3.3.1), T = 1/beta; U in [0,1).
-__device__ __forceinline__ bool metropolis_accept(int64_t d, double beta, double U) {
-    if (d <= 0) return true;
-    return U < exp_nonpos(-(beta * (double)d));
-}
-
-// Inclusive scan of one double per lane in the order of the DPP network: inside each row of 16
-// lanes a Kogge-Stone scan (row_shr 1, 2, 4, 8), then rows 1 and 3 add the last lane of rows 0
-// and 2 (row_bcast:15), then rows 2 and 3 add lane 31 (row_bcast:31).  Lanes without a source add
-// +0.0, which leaves a non-negative value unchanged.
-__device__ __forceinline__ double wave_scan_rows(double x) {
-    auto step = [](double v, uint64_t shifted) { return v + __longlong_as_double((long long)shifted); };
-    x = step(x, dpp64_zero<0x111>((uint64_t)__double_as_longlong(x)));
-    x = step(x, dpp64_zero<0x112>((uint64_t)__double_as_longlong(x)));
-    x = step(x, dpp64_zero<0x114>((uint64_t)__double_as_longlong(x)));
-    x = step(x, dpp64_zero<0x118>((uint64_t)__double_as_longlong(x)));
-    x = step(x, dpp64<0x142, 0xa, 0xf>((uint64_t)__double_as_longlong(x), 0));
-    x = step(x, dpp64<0x143, 0xc, 0xf>((uint64_t)__double_as_longlong(x), 0));
-    return x;
-}
-
-// Heat-bath choice (Sec. 3.3.2) among all W values, with the fixed summation order: value j of the
-// range belongs to lane j / c (c = ceil(W/64)); lane sums are left to right; the lanes' sums are
-// combined by wave_scan_rows; the first value whose cumulative weight exceeds U * total is drawn
-// (the last value if rounding leaves none).
-template <int kRegChunk, int kMaxE, typename Acc>
-__device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
-                                                  int64_t zk, double beta, double U, int lane, bool linear_in) {
-    const int64_t c = (W + kWave - 1) / kWave;
-    const int64_t j0 = (int64_t)lane * c;
-    const bool linear = kMaxE == 1 || linear_in;   // no term holds z_k to a power above one
-    // minimum energy difference over all values (weights are taken relative to it)
-    int64_t dmin;
-    if (linear) {
-        // dE(v) = a1 (v - z_k) is linear: its minimum over [lo, hi] is at an end of the range
-        const int64_t a1 = to_i64<Acc>(C.a[1]);
-        dmin = to_i64<Acc>(C.a[1] * (Acc)((a1 >= 0 ? lo : lo + W - 1) - zk));
-    } else {
-        dmin = INT64_MAX;
-        for (int64_t i = 0; i < c; ++i) {
-            const int64_t j = j0 + i;
-            if (j < W) {
-                const int64_t d = poly_delta(C, zk, lo + j);
-                dmin = d < dmin ? d : dmin;
-            }
-        }
-        dmin = wave_min_i64(dmin);
-    }
-    // exp(-beta * (dE - dmin)); in 32-bit mode the difference is formed in 32 bits (it fits)
-    auto weight = [&](int64_t j) -> double {
-        const int64_t d = linear ? to_i64<Acc>(C.a[1] * (Acc)(lo + j - zk)) : poly_delta(C, zk, lo + j);
-        const double x = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)d - (uint32_t)dmin)
-                                          : (double)(d - dmin);
-        return exp_nonpos(-(beta * x));
-    };
-
-    double w[kRegChunk > 0 ? kRegChunk : 1];
-    double lane_sum = 0.0;
-    if (kRegChunk > 0) {
-#pragma unroll
-        for (int i = 0; i < (kRegChunk > 0 ? kRegChunk : 1); ++i) {
-            // evaluated for every slot (a clamped index past the range) so that the exps of a lane
-            // are independent instructions; slots past the range or the chunk weigh zero
-            const int64_t j = j0 + i;
-            const double wv = weight(j < W ? j : W - 1);
-            const double wi = (i < c && j < W) ? wv : 0.0;
-            w[i] = wi;
-            lane_sum += wi;
-        }
-    } else {
-        for (int64_t i = 0; i < c; ++i) {
-            const int64_t j = j0 + i;
-            if (j < W) lane_sum += weight(j);
-        }
-    }
-    const double incl = wave_scan_rows(lane_sum);
-    const double total = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(incl), kWave - 1));
-    const double before = wave_shift_up1(incl, 0.0);
-    const double thr = U * total;
-
-    int32_t hit = -1;
-    double run = 0.0;
-    if (kRegChunk > 0) {
-#pragma unroll
-        for (int i = 0; i < (kRegChunk > 0 ? kRegChunk : 1); ++i) {
-            if (i < c) {
-                if (j0 + i < W) {
-                    run += w[i];
-                    if (hit < 0 && before + run > thr) hit = i;
-                }
-            }
-        }
-    } else {
-        for (int64_t i = 0; i < c; ++i) {
-            const int64_t j = j0 + i;
-            if (j < W) {
-                run += weight(j);
-                if (before + run > thr) {
-                    hit = (int32_t)i;
-                    break;
-                }
-            }
-        }
-    }
-    const uint64_t mask = __ballot(hit >= 0);
-    if (mask == 0) return lo + W - 1;
-    const int src = __ffsll((unsigned long long)mask) - 1;
-    return lo + (int64_t)src * c + (int64_t)(int32_t)lane_read32((uint32_t)hit, src);
-}
-
-// Optimal transition (Sec. 3.3.3): the nonzero change of smallest dE, ties to the smallest value.
-template <int kMaxE, typename Acc>
-__device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
-                                                  int64_t zk, int lane, int64_t &dbest) {
-    int64_t best = INT64_MAX;
-    int32_t bv = INT32_MAX;
-    for (int64_t i = lane; i < W; i += kWave) {
-        const int64_t v = lo + i;
-        if (v == zk) continue;
-        const int64_t d = poly_delta(C, zk, v);
-        if (d < best) {
-            best = d;
-            bv = (int32_t)v;
-        }
-    }
-    dbest = wave_min_i64(best);
-    return wave_min_i32(best == dbest ? bv : INT32_MAX);
-}
-
-// Optimal transition over a wide range (Sec. 3.3.3 restricts the rule to energy differences of
-// degree <= 4, whose minimisers lie next to stationary points).  With p(v) = sum_m a_m v^m,
-// dE(v) = p(v) - p(z_k).  The smallest minimiser v* over [lo, hi] minus {z_k} is an end of the
-// range, z_k - 1 or z_k + 1, or else p(v*-1) > p(v*) <= p(v*+1), so the real polynomial has a
-// stationary point t with |t - v*| < 1.  Every real root of the first derivative (and, in case
-// rounding hides a nearly double root, of the second and third derivatives) is found in double
-// precision; the 64 integers around each such centre, around both ends and around z_k are then
-// evaluated exactly, and the wave takes the lexicographic (dE, v) minimum.  The result equals the
-// enumeration whenever each computed root is within 30 of the true one.
-
-// Real roots of a x^2 + b x + c (a = 0: the linear root), preceded by the vertex -b/2a.
-__device__ __forceinline__ int quadratic_centres(double a, double b, double c, double *r) {
-    if (a == 0.0) {
-        if (b == 0.0) return 0;
-        r[0] = -c / b;
-        return 1;
-    }
-    int n = 0;
-    r[n++] = -b / (2.0 * a);
-    const double disc = b * b - 4.0 * a * c;
-    if (disc >= 0.0) {
-        const double q = -0.5 * (b + copysign(sqrt(disc), b));
-        r[n++] = q / a;
-        if (q != 0.0) r[n++] = c / q;
-    }
-    return n;
-}
-
-// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 (c3 != 0): trigonometric form for three real roots,
-// Cardano's for one, each then improved by two Newton steps.
-__device__ __forceinline__ int cubic_roots(double c3, double c2, double c1, double c0, double *r) {
-    const double A = c2 / c3, B = c1 / c3, C = c0 / c3;
-    const double A3 = A / 3.0;
-    const double p = B - A * A3;                 // depressed cubic y^3 + p y + q, x = y - A/3
-    const double q = (2.0 * A3 * A3 - B) * A3 + C;
-    const double D = 0.25 * q * q + p * p * p / 27.0;
-    int n = 0;
-    if (D <= 0.0 && p < 0.0) {
-        const double m = 2.0 * sqrt(-p / 3.0);
-        double cs = -4.0 * q / (m * m * m);
-        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-        const double th = acos(cs) / 3.0;
-        const double tau = 2.0943951023931957;   // 2 pi / 3
-        r[n++] = m * cos(th) - A3;
-        r[n++] = m * cos(th - tau) - A3;
-        r[n++] = m * cos(th + tau) - A3;
-    } else {
-        const double sd = sqrt(D > 0.0 ? D : 0.0);
-        const double u = cbrt(-0.5 * q - copysign(sd, q));
-        r[n++] = (u != 0.0 ? u - p / (3.0 * u) : 0.0) - A3;
-    }
-    for (int i = 0; i < n; ++i) {
-        double x = r[i];
-        for (int it = 0; it < 2; ++it) {
-            const double f = ((c3 * x + c2) * x + c1) * x + c0;
-            const double g = (3.0 * c3 * x + 2.0 * c2) * x + c1;
-            const double xn = g != 0.0 ? x - f / g : x;
-            x = isfinite(xn) ? xn : x;
-        }
-        r[i] = x;
-    }
-    return n;
-}
-
-template <int kMaxE, typename Acc>
-__device__ __forceinline__ int64_t argmin_stationary(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
-                                                     int64_t zk, int lane, int64_t &dbest) {
-    const int64_t hi = lo + W - 1;
-    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int m = 1; m <= (kMaxE < 4 ? kMaxE : 4); ++m) a[m] = (double)to_i64<Acc>(C.a[m]);
-    double cen[12];
-    int nc = 0;
-    cen[nc++] = (double)(lo + 31);
-    cen[nc++] = (double)(hi - 32);
-    cen[nc++] = (double)zk;
-    // first derivative 4 a4 x^3 + 3 a3 x^2 + 2 a2 x + a1; second 12 a4 x^2 + 6 a3 x + 2 a2
-    if (a[4] != 0.0) {
-        nc += cubic_roots(4.0 * a[4], 3.0 * a[3], 2.0 * a[2], a[1], cen + nc);
-        nc += quadratic_centres(12.0 * a[4], 6.0 * a[3], 2.0 * a[2], cen + nc);
-    } else {
-        nc += quadratic_centres(3.0 * a[3], 2.0 * a[2], a[1], cen + nc);
-        if (a[3] != 0.0) cen[nc++] = -a[2] / (3.0 * a[3]);
-    }
-    int64_t best = INT64_MAX;
-    int32_t bv = INT32_MAX;
-    for (int i = 0; i < nc; ++i) {
-        // window [b, b + 63] around the centre, inside the range
-        const double c = cen[i];
-        int64_t b;
-        if (!(c > (double)lo + 31.0)) b = lo;
-        else if (!(c < (double)hi - 32.0)) b = hi - 63;
-        else b = (int64_t)floor(c) - 31;
-        b = b < lo ? lo : b;
-        const int64_t v = b + lane;
-        if (v <= hi && v != zk) {
-            const int64_t d = poly_delta(C, zk, v);
-            if (d < best || (d == best && v < bv)) {
-                best = d;
-                bv = (int32_t)v;
-            }
-        }
-    }
-    dbest = wave_min_i64(best);
-    return wave_min_i32(best == dbest ? bv : INT32_MAX);
-}
-
-// expm1(x) for x <= 0 (the closed-form heat bath's expm1(-c W)).  Below -40, e^x is under half an
-// ulp of 1 and the value is -1 exactly.  On [-0.35, 0] the Taylor series of e^x - 1 to x^14 (error
-// below 2^-60 relative); otherwise e^x - 1, which cancels nothing because e^x <= 0.71.
-__device__ __forceinline__ double expm1_nonpos(double x) {
-    if (x < -40.0) return -1.0;
-    if (x < -0.35) return exp_nonpos(x) - 1.0;
-    // Horner on 1/k!, k = 14 .. 2, then x + x^2 (...)
-    double p = 1.0 / 87178291200.0;            // 1/14!
-    p = fma(p, x, 1.0 / 6227020800.0);         // 1/13!
-    p = fma(p, x, 1.0 / 479001600.0);          // 1/12!
-    p = fma(p, x, 1.0 / 39916800.0);           // 1/11!
-    p = fma(p, x, 1.0 / 3628800.0);            // 1/10!
-    p = fma(p, x, 1.0 / 362880.0);             // 1/9!
-    p = fma(p, x, 1.0 / 40320.0);              // 1/8!
-    p = fma(p, x, 1.0 / 5040.0);               // 1/7!
-    p = fma(p, x, 1.0 / 720.0);                // 1/6!
-    p = fma(p, x, 1.0 / 120.0);                // 1/5!
-    p = fma(p, x, 1.0 / 24.0);                 // 1/4!
-    p = fma(p, x, 1.0 / 6.0);                  // 1/3!
-    p = fma(p, x, 0.5);                        // 1/2!
-    return fma(p * x, x, x);
-}
-
-// log1p(y) for -1 < y <= 0 (the closed-form heat bath's log1p(U m)).  u = 1 + y rounded; log(u)
-// from u = f 2^e with f in [sqrt(1/2), sqrt(2)) and log f = 2 atanh(s), s = (f - 1)/(f + 1),
-// |s| <= 0.1716, by its odd series to s^21 (error below 2^-62 relative); the rounding of u is
-// put back to first order, log1p(y) = log(u) + (y - (u - 1)) / u (Kahan's correction).
-__device__ __forceinline__ double log1p_nonpos(double y) {
-    if (y == 0.0) return 0.0;
-    if (y <= -1.0) return -__builtin_huge_val();
-    const double u = 1.0 + y;
-    const double corr = (y - (u - 1.0)) * __builtin_amdgcn_rcp(u);
-    int e = __builtin_amdgcn_frexp_exp(u);
-    double f = __builtin_amdgcn_frexp_mant(u);  // [0.5, 1)
-    if (f < 0.70710678118654752) {
-        f = f + f;
-        e -= 1;
-    }
-    const double s = (f - 1.0) / (f + 1.0);
-    const double s2 = s * s;
-    double r = 1.0 / 21.0;
-    r = fma(r, s2, 1.0 / 19.0);
-    r = fma(r, s2, 1.0 / 17.0);
-    r = fma(r, s2, 1.0 / 15.0);
-    r = fma(r, s2, 1.0 / 13.0);
-    r = fma(r, s2, 1.0 / 11.0);
-    r = fma(r, s2, 1.0 / 9.0);
-    r = fma(r, s2, 1.0 / 7.0);
-    r = fma(r, s2, 1.0 / 5.0);
-    r = fma(r, s2, 1.0 / 3.0);
-    const double ln2_hi = 0.6931471803691238;    // ln 2 rounded to 32 bits: e * ln2_hi is exact
-    const double ln2_lo = 1.9082149292705877e-10;  // ln 2 - ln2_hi
-    const double ed = (double)e;
-    const double two_s = s + s;
-    // log u = e ln2_hi + (2 s + (2 s s^2 r + e ln2_lo)) + corr
-    return fma(ed, ln2_hi, two_s + (fma(two_s * s2, r, ed * ln2_lo) + corr));
-}
-
-// Heat bath for a variable whose energy difference is linear, dE(v) = a (v - z_k) (Sec. 3.3.2,
-// multilinear case): the inverse of the cumulative distribution in O(1).  Index i = v - lo has
-// probability proportional to exp(-beta a i); with c = beta |a| and g(q) = -log1p(q expm1(-c W)) / c
-// the paper's x = -(T/a) ln[1 - U (1 - exp(-a W / T))] is g(U) for a > 0 and W - g(1 - U) for a < 0
-// (the same value without overflowing exp(c W)); v = lo + ceil(x) - 1, clamped to the box.  a = 0
-// or beta = 0 is the uniform distribution, drawn from x1 by a multiply-high.  Wave-uniform.
-// expm1 and log1p are the functions above (about an ulp, like the host library); a last-bit
-// difference moves a draw only when x lies within a few ulps of an integer.
-__device__ __forceinline__ int64_t heat_bath_closed(int64_t a, int64_t lo, int64_t W, double beta, double U,
-                                                    uint32_t x1) {
-    const double c = beta * (double)(a < 0 ? -a : a);
-    if (a == 0 || !(c > 0.0)) return lo + (int64_t)(((uint64_t)x1 * (uint64_t)W) >> 32);
-    const double Wd = (double)W;
-    const double m = expm1_nonpos(-(c * Wd));
-    double x;
-    if (a > 0)
-        x = -log1p_nonpos(U * m) / c;
-    else
-        x = Wd + log1p_nonpos((1.0 - U) * m) / c;
-    if (!(x > 0.0)) return lo;
-    if (x >= Wd) return lo + W - 1;
-    return lo + (int64_t)ceil(x) - 1;
-}
-
-// ------------------------------------------------------------------------------------------------
-// The annealing kernel.
-//
-// G = A.win_waves waves per replica.  G = 1: every wave of the workgroup is an independent replica.
-// G > 1: the workgroup is one replica whose state is shared in LDS; in each window of the schedule
-// wave g updates the window's g-th variable, and a barrier closes the window.  The variables of a
-// window share no term, so this equals the sequential index-order sweep exactly.
-// ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ void window_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// What one replica's sweeps need (shared by the plain and the batched kernels).
-struct ReplicaCtx {
-    DevProblem P;
-    const double *beta;
-    int32_t n_sweeps, s_begin, s_end;
-    uint32_t key0, key1, instance_id, read;
-    double otm_r;
-    int32_t otm_enum_max;   // widest range whose optimal transition is enumerated
-    const SchedRec *sched;  // this wave's schedule slots (window-major for one wave)
-    int32_t n_win;
-    bool shared;            // the replica's waves cooperate (barrier after each window)
-    bool active;            // false: an idle team that only keeps the workgroup's barriers
-};
-
-// Initial state (given, or uniform on each box, Sec. 3.1) written by threads tid, tid+nthr, ...
-template <typename ZT>
-__device__ __forceinline__ void init_state(const DevProblem &P, ZT *z, const int32_t *zi, uint32_t read,
-                                           uint32_t inst, uint32_t key0, uint32_t key1, int tid, int nthr) {
-    const int32_t n = P.n;
-    if (zi) {
-        if ((const void *)zi != (const void *)z)
-            for (int32_t k = tid; k < n; k += nthr) z[k] = (ZT)zi[k];
-    } else {
-        for (int32_t k = tid; k < n; k += nthr) {
-            uint32_t x0 = (uint32_t)k, x1 = 0xFFFFFFFFu, x2 = read, x3 = inst;
-            philox4x32_10(x0, x1, x2, x3, key0, key1);
-            const VarRec vr = P.var[k];
-            z[k] = (ZT)(vr.lo + (int32_t)(((uint64_t)x0 * (uint64_t)(uint32_t)vr.width) >> 32));
-        }
-    }
-}
-
-// This wave's share of E(z) = sum_t J_t prod z (threads tid, tid+nthr, ... take the terms).
-template <typename ZT>
-__device__ __forceinline__ int64_t energy_part(const DevProblem &P, const ZT *z, int tid, int nthr) {
-    if (P.dense) {
-        // rows k = g, g + G, ... of the upper triangle, lanes across the row
-        const int lane = tid & (kWave - 1), g = tid / kWave, G = nthr / kWave;
-        uint64_t acc = 0;
-        for (int32_t k = g; k < P.n; k += G) {
-            const int64_t zk = z[k];
-            if (lane == 0) acc += (uint64_t)zk * (uint64_t)(P.h[k] + P.d[k] * zk);
-            uint64_t racc = 0;
-            if (P.jbytes == 1) {
-                const int8_t *row = (const int8_t *)P.jd + (size_t)k * P.row_stride;
-                for (int32_t j = k + 1 + lane; j < P.n; j += kWave) racc += (uint64_t)(int64_t)row[j] * (uint64_t)(int64_t)z[j];
-            } else {
-                const int32_t *row = (const int32_t *)P.jd + (size_t)k * P.row_stride;
-                for (int32_t j = k + 1 + lane; j < P.n; j += kWave) racc += (uint64_t)(int64_t)row[j] * (uint64_t)(int64_t)z[j];
-            }
-            acc += racc * (uint64_t)zk;
-        }
-        return (int64_t)wave_sum_u64(acc);
-    }
-    uint64_t eacc = 0;
-    for (int32_t t = tid; t < P.n_terms; t += nthr) {
-        uint64_t prod = (uint64_t)P.t_coef[t];
-        for (int32_t f = P.t_off[t]; f < P.t_off[t + 1]; ++f) prod *= (uint64_t)(int64_t)z[P.t_var[f]];
-        eacc += prod;
-    }
-    return (int64_t)wave_sum_u64(eacc);
-}
-
-// Sweeps [s_begin, s_end) of one replica (index order, Sec. 3.1): this wave's slots of the
-// schedule.  Returns the sum of the energy changes this wave applied.
-template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc, typename ZT>
-__device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int lane) {
-    const DevProblem &P = R.P;
-    const int32_t n_win = R.n_win;
-    const SchedRec *mine = R.sched;
-    int64_t E = 0;
-    if (!R.active) {
-        if (R.shared)
-            for (int32_t s = R.s_begin; s < R.s_end; ++s)
-                for (int32_t w = 0; w < n_win; ++w) window_barrier();
-        return 0;
-    }
-    for (int32_t s = R.s_begin; s < R.s_end; ++s) {
-        const double beta = R.beta[s];
-        const double r_opt =
-            R.otm_r >= 0.0 ? R.otm_r : (R.n_sweeps > 1 ? (double)s / (double)(R.n_sweeps - 1) : 0.0);
-        for (int32_t wb = 0; wb < n_win; wb += kWave) {
-            // per block of 64 windows: lane j holds this wave's slot of window wb+j and its draws
-            const int32_t wl = wb + lane;
-            SchedRec sl;
-            if (wl < n_win) {
-                sl = mine[wl];
-            } else {
-                sl.k = -1;
-                sl.lo = 0;
-                sl.width = 1;
-                sl.row = 0;
-                sl.deg = 0;
-                sl.emask = 0;
-            }
-            uint32_t x0 = (uint32_t)sl.k, x1 = (uint32_t)s, x2 = R.read, x3 = R.instance_id;
-            philox4x32_10(x0, x1, x2, x3, R.key0, R.key1);
-            // U in [0, 1) from words 2 and 3, formed once per lane for its window
-            const double Ul = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
-            const int32_t wend = n_win - wb < kWave ? n_win - wb : kWave;
-            // first chunk of the next slot's incidence records (the dense-form Metropolis variant,
-            // kRegChunk = 1: of its coupling row, with h_k and d_k), loaded one window ahead
-            IncRec nrec;
-            uint64_t ncoef;
-            int64_t nd = 0;
-            auto prefetch = [&](int32_t jj) {
-                if (kRule == SA_METROPOLIS && kRegChunk == 1) {
-                    int4 q;
-                    prefetch_dense(P, (int32_t)lane_read32((uint32_t)sl.k, jj), lane, q, ncoef, nd);
-                    nrec.meta = (uint32_t)q.x;
-                    nrec.o[0] = q.y;
-                    nrec.o[1] = q.z;
-                    nrec.o[2] = q.w;
-                } else {
-                    load_record(P, (int32_t)lane_read32((uint32_t)sl.row, jj),
-                                (int32_t)lane_read32((uint32_t)sl.deg, jj), 0, lane, nrec, ncoef);
-                }
-            };
-            prefetch(0);
-            for (int32_t j = 0; j < wend; ++j) {
-                const int32_t k = (int32_t)lane_read32((uint32_t)sl.k, j);
-                const IncRec crec = nrec;
-                const uint64_t ccoef = ncoef;
-                const int64_t cd = nd;
-                if (j + 1 < wend) prefetch(j + 1);
-                if (k >= 0) {
-                    const int64_t lo = (int32_t)lane_read32((uint32_t)sl.lo, j);
-                    const int64_t W = (int32_t)lane_read32((uint32_t)sl.width, j);
-                    const int32_t row = (int32_t)lane_read32((uint32_t)sl.row, j);
-                    const int32_t deg = (int32_t)lane_read32((uint32_t)sl.deg, j);
-                    const uint32_t r0 = lane_read32(x0, j), r1 = lane_read32(x1, j);
-                    const double U = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(Ul), j));
-                    const int64_t zk = (int64_t)(int32_t)uni32((uint32_t)z[k]);
-                    int64_t v, d;
-                    bool accept;
-                    if (kRule == SA_METROPOLIS) {
-                        v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
-                        if (v >= zk) v += 1;
-                        // (Metropolis kernels are built with kMaxE = 1 for any problem: the
-                        // variable's own exponents decide)
-                        d = direct_delta<Acc, ZT, kRegChunk == 1>(P, z, k, row, deg, zk, v, lane, crec, ccoef, cd,
-                                                  (lane_read32(sl.emask, j) & ~2u) == 0);
-                        accept = metropolis_accept(d, beta, U);
-                    } else if (kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED) {
-                        Coeffs<kMaxE, Acc> C;
-                        const uint32_t em = lane_read32(sl.emask, j);
-                        row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
-                        // closed form where dE is linear in the new value (no exponent above one)
-                        const bool linear = kMaxE == 1 || (em & ~2u) == 0;
-                        if (kRule == SA_HEAT_BATH_CLOSED && linear)
-                            v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, r1);
-                        else
-                            v = heat_bath_pick<kRegChunk, kMaxE, Acc>(C, lo, W, zk, beta, U, lane, linear);
-                        d = poly_delta(C, zk, v);
-                        accept = true;
-                    } else {
-                        if ((double)r0 * 0x1p-32 < r_opt) {
-                            Coeffs<kMaxE, Acc> C;
-                            const uint32_t em = lane_read32(sl.emask, j);
-                            row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
-                            if (kMaxE == 1 || (em & ~2u) == 0) {
-                                // dE = a1 (v - z_k): the smallest value for a1 >= 0 (all tie when
-                                // a1 = 0), the largest for a1 < 0, stepping off z_k
-                                const int64_t a1 = to_i64<Acc>(C.a[1]);
-                                v = a1 >= 0 ? (lo == zk ? lo + 1 : lo) : (lo + W - 1 == zk ? lo + W - 2 : lo + W - 1);
-                                d = to_i64<Acc>(C.a[1] * (Acc)(v - zk));
-                            } else if (kRegChunk == 1 && W > R.otm_enum_max)
-                                v = argmin_stationary<kMaxE, Acc>(C, lo, W, zk, lane, d);
-                            else
-                                v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
-                        } else {
-                            v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
-                            if (v >= zk) v += 1;
-                            d = direct_delta<Acc, ZT, false>(P, z, k, row, deg, zk, v, lane, crec, ccoef, cd,
-                                                      (lane_read32(sl.emask, j) & ~2u) == 0);
-                        }
-                        accept = metropolis_accept(d, beta, U);
-                    }
-                    if (accept && v != zk) {
-                        z[k] = (ZT)v;  // every lane stores the same value
-                        E += d;
-                        if (!R.shared) state_write_fence<kStateInLds>();
-                    }
-                }
-                if (R.shared) window_barrier();
-            }
-        }
-    }
-    return E;
-}
-
-// ------------------------------------------------------------------------------------------------
-// Plain launch: one instance, n_reads replicas.
-// ------------------------------------------------------------------------------------------------
-// kThreads: 512 (up to 8 waves per replica) or 1024 (16 waves; fewer registers per lane, so only
-// the variants that need no more than 128 VGPRs are built that way).
-template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc, int kThreads>
-__global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
-    extern __shared__ int32_t lds_state[];
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    const int wave = (int)(threadIdx.x / kWave);
-    const int G = A.win_waves;
-    const bool shared = G > 1;
-    const int read = shared ? (int)blockIdx.x : (int)blockIdx.x * A.waves_per_group + wave;
-    const int g = shared ? wave : 0;
-    if (read >= A.n_reads) return;  // uniform over the replica's waves; no barrier is skipped
-    const DevProblem &P = A.P;
-    const int32_t n = P.n;
-    int32_t *z = kStateInLds ? lds_state + (shared ? 0 : (size_t)wave * n) : A.z_out + (size_t)read * n;
-    const int tid = g * kWave + lane, nthr = G * kWave;  // threads of this replica
-
-    init_state(P, z, A.z_init ? A.z_init + (size_t)read * n : nullptr, (uint32_t)read, A.instance_id,
-               A.key0, A.key1, tid, nthr);
-    if (shared) window_barrier();
-    else state_write_fence<kStateInLds>();
-    int64_t E = energy_part(P, z, tid, nthr);
-
-    ReplicaCtx R;
-    R.P = P;
-    R.beta = A.beta;
-    R.n_sweeps = A.n_sweeps;
-    R.s_begin = A.s_begin;
-    R.s_end = A.s_end;
-    R.key0 = A.key0;
-    R.key1 = A.key1;
-    R.instance_id = A.instance_id;
-    R.read = (uint32_t)read;
-    R.otm_r = A.otm_r;
-    R.otm_enum_max = A.otm_enum_max;
-    R.sched = A.sched + (size_t)g * A.n_win;
-    R.n_win = A.n_win;
-    R.shared = shared;
-    R.active = true;
-    E += sweep_replica<kRule, kStateInLds, kRegChunk, kMaxE, Acc, int32_t>(R, z, lane);
-
-    if (shared) {
-        // combine the waves' energy parts; LDS slots follow the state
-        int64_t *parts = (int64_t *)(lds_state + (((size_t)n + 1) & ~(size_t)1));
-        if (lane == 0) parts[g] = E;
-        window_barrier();
-        if (g == 0) {
-            E = 0;
-            for (int q = 0; q < G; ++q) E += parts[q];
-        }
-    }
-    if (kStateInLds) {
-        int32_t *zo = A.z_out + (size_t)read * n;
-        for (int32_t k = tid; k < n; k += nthr) zo[k] = z[k];
-    }
-    if (g == 0 && lane == 0) A.e_out[read] = E;
-}
-
-// ------------------------------------------------------------------------------------------------
-// Batched launch: one persistent kernel anneals many problems.  A workgroup of kBatchWaves waves
-// repeatedly takes the next task from a global counter (tasks are ordered longest first).  A task
-// is kBatchWaves / G_p consecutive reads of one problem p: each read is annealed by a team of G_p
-// waves (G_p = 1: independent waves; G_p > 1: cooperating waves over the problem's window schedule,
-// as in the plain kernel).  Rule and heat-bath chunk class are dispatched per task; the exponent
-// class, integer width and state width are those of the whole batch.
-// ------------------------------------------------------------------------------------------------
-template <int kMaxE, typename Acc, typename ZT>
-__global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B) {
-    extern __shared__ int32_t lds_state[];
-    __shared__ uint32_t task_slot;
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    const int wave = (int)(threadIdx.x / kWave);
-    int64_t *parts = (int64_t *)(lds_state + B.parts_words);
-    constexpr int kOtmE = kMaxE < 4 ? kMaxE : 4;
-    for (;;) {
-        if (threadIdx.x == 0) task_slot = atomicAdd(B.counter, 1u);
-        window_barrier();
-        const uint32_t t = task_slot;
-        window_barrier();  // every wave has the task before the slot can change again
-        if (t >= (uint32_t)B.n_tasks) break;  // uniform over the workgroup
-        const BatchTask task = B.tasks[t];
-        const BatchInst &D = B.insts[task.inst];
-        const DevProblem P = D.P;
-        const int G = D.team;
-        const int team = wave / G, g = wave % G;
-        const int32_t read_i = task.read + team;
-        const bool active = read_i < D.n_reads;
-        const uint32_t read = (uint32_t)read_i;
-        ZT *z = (ZT *)lds_state + (size_t)team * D.slot_stride;
-        const int tid = g * kWave + lane, nthr = G * kWave;
-        int32_t *zo = D.z_out + (size_t)read * P.n;
-        if (active) init_state(P, z, D.resume ? zo : nullptr, read, D.instance_id, D.key0, D.key1, tid, nthr);
-        window_barrier();
-        int64_t E = active ? energy_part(P, z, tid, nthr) : 0;
-        ReplicaCtx R;
-        R.P = P;
-        R.beta = D.beta;
-        R.n_sweeps = D.n_sweeps;
-        R.s_begin = D.s_begin;
-        R.s_end = B.sweep_limit > 0 && B.sweep_limit < D.s_end ? B.sweep_limit : D.s_end;
-        R.key0 = D.key0;
-        R.key1 = D.key1;
-        R.instance_id = D.instance_id;
-        R.read = read;
-        R.otm_r = -1.0;
-        R.otm_enum_max = kOtmEnumMax;
-        R.sched = D.sched + (size_t)g * D.n_win;
-        R.n_win = D.n_win;
-        R.shared = G > 1;
-        R.active = active;
-        if (D.rule == SA_METROPOLIS) {
-            E += sweep_replica<SA_METROPOLIS, true, 0, 1, Acc, ZT>(R, z, lane);
-        } else if (D.rule == SA_HEAT_BATH) {
-            switch (D.chunk) {
-                case 1: E += sweep_replica<SA_HEAT_BATH, true, 1, kMaxE, Acc, ZT>(R, z, lane); break;
-                case 2: E += sweep_replica<SA_HEAT_BATH, true, 2, kMaxE, Acc, ZT>(R, z, lane); break;
-                case 8: E += sweep_replica<SA_HEAT_BATH, true, 8, kMaxE, Acc, ZT>(R, z, lane); break;
-                default: E += sweep_replica<SA_HEAT_BATH, true, 0, kMaxE, Acc, ZT>(R, z, lane); break;
-            }
-        } else if (D.rule == SA_HEAT_BATH_CLOSED) {
-            switch (D.chunk) {
-                case 1: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 1, kMaxE, Acc, ZT>(R, z, lane); break;
-                case 2: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 2, kMaxE, Acc, ZT>(R, z, lane); break;
-                case 8: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 8, kMaxE, Acc, ZT>(R, z, lane); break;
-                default: E += sweep_replica<SA_HEAT_BATH_CLOSED, true, 0, kMaxE, Acc, ZT>(R, z, lane); break;
-            }
-        } else {
-            E += sweep_replica<SA_OPT_METROPOLIS, true, 0, kOtmE, Acc, ZT>(R, z, lane);
-        }
-        if (lane == 0) parts[wave] = E;
-        window_barrier();
-        if (active) {
-            if (g == 0 && lane == 0) {
-                int64_t tot = 0;
-                for (int q = 0; q < G; ++q) tot += parts[team * G + q];
-                D.e_out[read] = tot;
-            }
-            for (int32_t k = tid; k < P.n; k += nthr) zo[k] = (int32_t)z[k];
-        }
-        window_barrier();  // the slots' last reads come before the next task's writes
-    }
-}
-
-// Sets the batch's task counter to zero (a kernel, so that graph replays stay plain kernel nodes).
-__global__ void reset_counter_kernel(uint32_t *counter) {
-    if (threadIdx.x == 0) *counter = 0u;
-}
 
 // Energies of stored states, one wavefront per state.
 __global__ void __launch_bounds__(256) energy_kernel(DevProblem P, const int32_t *states,
@@ -1083,28 +17,7 @@ __global__ void __launch_bounds__(256) energy_kernel(DevProblem P, const int32_t
     if (lane == 0) out[idx] = E;
 }
 
-using KernelFn = void (*)(AnnealArgs);
-
-// Heat bath: the weights of ceil(W/64) <= kRegChunk values per lane stay in registers (the
-// unrolled loops then cost kRegChunk steps); wider ranges recompute them (kRegChunk = 0).
-template <int kRule, int kMaxE, typename Acc>
-KernelFn pick_heat_bath_lds(int reg_chunk) {
-    switch (reg_chunk) {
-        case 1: return anneal_kernel<kRule, true, 1, kMaxE, Acc, 512>;
-        case 2: return anneal_kernel<kRule, true, 2, kMaxE, Acc, 512>;
-        case 8: return anneal_kernel<kRule, true, 8, kMaxE, Acc, 512>;
-        case 32: return anneal_kernel<kRule, true, 32, kMaxE, Acc, 512>;
-        default: return anneal_kernel<kRule, true, 0, kMaxE, Acc, 512>;
-    }
-}
-template <int kRule, int kMaxE, typename Acc>
-KernelFn pick_heat_bath_lds_16(int reg_chunk) {
-    switch (reg_chunk) {
-        case 1: return anneal_kernel<kRule, true, 1, kMaxE, Acc, 1024>;
-        case 2: return anneal_kernel<kRule, true, 2, kMaxE, Acc, 1024>;
-        default: return anneal_kernel<kRule, true, 8, kMaxE, Acc, 1024>;
-    }
-}
+using KernelFn = AnnealKernelFn;
 
 // Variants built for 16 waves per replica (their register needs fit 128 VGPRs): states in LDS,
 // every exponent <= 2, at most 8 heat-bath weights per lane, and the closed-form heat bath only
@@ -1117,87 +30,15 @@ bool sixteen_waves_ok(int rule, bool in_lds, int reg_chunk, int maxe_class) {
     return true;
 }
 
-KernelFn pick_kernel_16(int rule, int reg_chunk, int maxe_class, bool narrow) {
+KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool narrow, bool sixteen) {
     switch (rule) {
-        case SA_METROPOLIS:
-            return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t, 1024>
-                          : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t, 1024>;
-        case SA_OPT_METROPOLIS:
-            if (maxe_class == 1)
-                return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t, 1024>
-                              : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t, 1024>;
-            return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint32_t, 1024>
-                          : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint64_t, 1024>;
-        case SA_HEAT_BATH:
-            if (maxe_class == 1)
-                return narrow ? pick_heat_bath_lds_16<SA_HEAT_BATH, 1, uint32_t>(reg_chunk)
-                              : pick_heat_bath_lds_16<SA_HEAT_BATH, 1, uint64_t>(reg_chunk);
-            return narrow ? pick_heat_bath_lds_16<SA_HEAT_BATH, 2, uint32_t>(reg_chunk)
-                          : pick_heat_bath_lds_16<SA_HEAT_BATH, 2, uint64_t>(reg_chunk);
-        case SA_HEAT_BATH_CLOSED:
-            return narrow ? anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint32_t, 1024>
-                          : anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint64_t, 1024>;
-        default:
-            return nullptr;
+        case SA_METROPOLIS: return metropolis_kernel(in_lds, reg_chunk, narrow, sixteen);
+        case SA_HEAT_BATH: return heat_bath_kernel(in_lds, reg_chunk, maxe_class, narrow, sixteen);
+        case SA_HEAT_BATH_CLOSED: return heat_bath_closed_kernel(in_lds, reg_chunk, maxe_class, narrow, sixteen);
+        case SA_OPT_METROPOLIS: return otm_kernel(in_lds, reg_chunk, maxe_class, narrow, sixteen);
+        default: return nullptr;
     }
 }
-
-// Kernel variants: rule x exponent class x (heat bath) register chunk x integer width, for states
-// in LDS; 32-bit arithmetic is instantiated for the quadratic classes (QUIO).  States in device
-// memory (very large N) use one generic 64-bit variant per rule.
-KernelFn pick_kernel(int rule, bool in_lds, int reg_chunk, int maxe_class, bool narrow) {
-    if (rule == SA_METROPOLIS) {
-        if (!in_lds) return anneal_kernel<SA_METROPOLIS, false, 0, 1, uint64_t, 512>;
-        if (reg_chunk == 1)   // dense form: coupling rows prefetched one window ahead
-            return narrow ? anneal_kernel<SA_METROPOLIS, true, 1, 1, uint32_t, 512>
-                          : anneal_kernel<SA_METROPOLIS, true, 1, 1, uint64_t, 512>;
-        return narrow ? anneal_kernel<SA_METROPOLIS, true, 0, 1, uint32_t, 512>
-                      : anneal_kernel<SA_METROPOLIS, true, 0, 1, uint64_t, 512>;
-    }
-    if (rule == SA_HEAT_BATH) {
-        if (!in_lds) return anneal_kernel<SA_HEAT_BATH, false, 0, kMaxExpPoly, uint64_t, 512>;
-        switch (maxe_class) {
-            case 1: return narrow ? pick_heat_bath_lds<SA_HEAT_BATH, 1, uint32_t>(reg_chunk)
-                                  : pick_heat_bath_lds<SA_HEAT_BATH, 1, uint64_t>(reg_chunk);
-            case 2: return narrow ? pick_heat_bath_lds<SA_HEAT_BATH, 2, uint32_t>(reg_chunk)
-                                  : pick_heat_bath_lds<SA_HEAT_BATH, 2, uint64_t>(reg_chunk);
-            case 4: return pick_heat_bath_lds<SA_HEAT_BATH, 4, uint64_t>(reg_chunk);
-            default: return pick_heat_bath_lds<SA_HEAT_BATH, kMaxExpPoly, uint64_t>(reg_chunk);
-        }
-    }
-    if (rule == SA_HEAT_BATH_CLOSED) {
-        // every variable linear (class 1): no enumeration code at all
-        if (!in_lds) return anneal_kernel<SA_HEAT_BATH_CLOSED, false, 0, kMaxExpPoly, uint64_t, 512>;
-        switch (maxe_class) {
-            case 1: return narrow ? anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint32_t, 512>
-                                  : anneal_kernel<SA_HEAT_BATH_CLOSED, true, 0, 1, uint64_t, 512>;
-            case 2: return narrow ? pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, 2, uint32_t>(reg_chunk)
-                                  : pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, 2, uint64_t>(reg_chunk);
-            case 4: return pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, 4, uint64_t>(reg_chunk);
-            default: return pick_heat_bath_lds<SA_HEAT_BATH_CLOSED, kMaxExpPoly, uint64_t>(reg_chunk);
-        }
-    }
-    if (rule == SA_OPT_METROPOLIS) {
-        if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 1, 4, uint64_t, 512>;
-        if (reg_chunk == 1) {
-            // ranges wider than the enumeration limit: the stationary-point argmin is built in
-            switch (maxe_class) {
-                case 1: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 1, uint64_t, 512>;
-                case 2: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 2, uint64_t, 512>;
-                default: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 4, uint64_t, 512>;
-            }
-        }
-        switch (maxe_class) {
-            case 1: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint32_t, 512>
-                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 1, uint64_t, 512>;
-            case 2: return narrow ? anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint32_t, 512>
-                                  : anneal_kernel<SA_OPT_METROPOLIS, true, 0, 2, uint64_t, 512>;
-            default: return anneal_kernel<SA_OPT_METROPOLIS, true, 0, 4, uint64_t, 512>;
-        }
-    }
-    return nullptr;
-}
-
 
 }  // namespace
 
@@ -1261,8 +102,7 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
 
 int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
                   std::string &err) {
-    KernelFn fn = lc.win_waves == 16 ? pick_kernel_16(rule, lc.reg_chunk, lc.maxe_class, lc.narrow)
-                                     : pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class, lc.narrow);
+    KernelFn fn = pick_kernel(rule, lc.state_in_lds, lc.reg_chunk, lc.maxe_class, lc.narrow, lc.win_waves == 16);
     if (!fn) {
         err = "unknown rule";
         return SA_EINVAL;
@@ -1301,43 +141,3 @@ int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, 
 
 }  // namespace sa
 
-namespace sa {
-
-int launch_batch(const BatchArgs &b, const BatchLaunch &bl, void *stream, std::string &err) {
-    using Fn = void (*)(BatchArgs);
-    Fn fn;
-    if (bl.z16) {
-        switch (bl.maxe_class) {
-            case 1: fn = bl.narrow ? batch_kernel<1, uint32_t, int16_t> : batch_kernel<1, uint64_t, int16_t>; break;
-            case 2: fn = bl.narrow ? batch_kernel<2, uint32_t, int16_t> : batch_kernel<2, uint64_t, int16_t>; break;
-            case 4: fn = batch_kernel<4, uint64_t, int16_t>; break;
-            default: fn = batch_kernel<kMaxExpPoly, uint64_t, int16_t>; break;
-        }
-    } else {
-        switch (bl.maxe_class) {
-            case 1: fn = bl.narrow ? batch_kernel<1, uint32_t, int32_t> : batch_kernel<1, uint64_t, int32_t>; break;
-            case 2: fn = bl.narrow ? batch_kernel<2, uint32_t, int32_t> : batch_kernel<2, uint64_t, int32_t>; break;
-            case 4: fn = batch_kernel<4, uint64_t, int32_t>; break;
-            default: fn = batch_kernel<kMaxExpPoly, uint64_t, int32_t>; break;
-        }
-    }
-    const int lds = b.lds_words * (int)sizeof(int32_t);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) {
-            err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
-            return SA_EDEVICE;
-        }
-    }
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, b.counter);
-    hipLaunchKernelGGL(fn, dim3((unsigned)bl.groups), dim3((unsigned)(kBatchWaves * kWave)), (size_t)lds,
-                       (hipStream_t)stream, b);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        err = std::string("batch launch: ") + hipGetErrorString(e);
-        return SA_EDEVICE;
-    }
-    return SA_OK;
-}
-
-}  // namespace sa
