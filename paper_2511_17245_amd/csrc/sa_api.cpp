@@ -38,26 +38,29 @@ int upload_packed(const sa::Packed &pk, sa_plan *plan) {
     struct Part {
         const void *src;
         size_t bytes;
+        size_t extra;   // zero bytes reserved after the copied ones
         size_t off;
     };
+    // the incidence records and their coefficients are followed by one zero record, which lanes
+    // past the end of a row read
     std::vector<Part> parts = {
-        {pk.var.data(), pk.var.size() * sizeof(sa::VarRec), 0},
-        {pk.emask.data(), pk.emask.size() * sizeof(uint32_t), 0},
-        {pk.inc.data(), pk.inc.size() * sizeof(sa::IncRec), 0},
-        {pk.inc_coef.data(), pk.inc_coef.size() * sizeof(int64_t), 0},
-        {pk.overflow.data(), pk.overflow.size() * sizeof(int32_t), 0},
-        {pk.t_off.data(), pk.t_off.size() * sizeof(int32_t), 0},
-        {pk.t_var.data(), pk.t_var.size() * sizeof(int32_t), 0},
-        {pk.t_coef.data(), pk.t_coef.size() * sizeof(int64_t), 0},
+        {pk.var.data(), pk.var.size() * sizeof(sa::VarRec), 0, 0},
+        {pk.emask.data(), pk.emask.size() * sizeof(uint32_t), 0, 0},
+        {pk.inc.data(), pk.inc.size() * sizeof(sa::IncRec), sizeof(sa::IncRec), 0},
+        {pk.inc_coef.data(), pk.inc_coef.size() * sizeof(int64_t), sizeof(int64_t), 0},
+        {pk.overflow.data(), pk.overflow.size() * sizeof(int32_t), 0, 0},
+        {pk.t_off.data(), pk.t_off.size() * sizeof(int32_t), 0, 0},
+        {pk.t_var.data(), pk.t_var.size() * sizeof(int32_t), 0, 0},
+        {pk.t_coef.data(), pk.t_coef.size() * sizeof(int64_t), 0, 0},
         {pk.jbytes == 1 ? (const void *)pk.jd8.data() : (const void *)pk.jd32.data(),
-         pk.jbytes == 1 ? pk.jd8.size() : pk.jd32.size() * sizeof(int32_t), 0},
-        {pk.h.data(), pk.h.size() * sizeof(int64_t), 0},
-        {pk.d.data(), pk.d.size() * sizeof(int64_t), 0},
+         pk.jbytes == 1 ? pk.jd8.size() : pk.jd32.size() * sizeof(int32_t), 0, 0},
+        {pk.h.data(), pk.h.size() * sizeof(int64_t), 0, 0},
+        {pk.d.data(), pk.d.size() * sizeof(int64_t), 0, 0},
     };
     size_t total = 0;
     for (auto &p : parts) {
         p.off = total;
-        total += align256(p.bytes > 0 ? p.bytes : 1);
+        total += align256(p.bytes + p.extra > 0 ? p.bytes + p.extra : 1);
     }
     hipError_t e = hipMalloc(&plan->arena.base, total);
     if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
@@ -80,6 +83,7 @@ int upload_packed(const sa::Packed &pk, sa_plan *plan) {
     d.t_var = (const int32_t *)(b + parts[6].off);
     d.t_coef = (const int64_t *)(b + parts[7].off);
     d.max_other = pk.max_other;
+    d.inc_pad = (int32_t)pk.inc.size();
     d.dense = pk.dense ? 1 : 0;
     d.jbytes = pk.jbytes;
     d.row_stride = pk.row_stride;

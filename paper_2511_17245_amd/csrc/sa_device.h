@@ -200,17 +200,13 @@ __device__ __forceinline__ Acc record_product(const DevProblem &P, const ZT *z, 
     return prod;
 }
 
-// Loads this lane's record of chunk [c0, c0 + 64) of a row (a zero record past the row's end).
+// Loads this lane's record of chunk [c0, c0 + 64) of a row; lanes past the row's end read the zero
+// record kept after the last row, so every lane loads.
 __device__ __forceinline__ void load_record(const DevProblem &P, int32_t row, int32_t deg, int32_t c0,
                                             int lane, IncRec &r, uint64_t &coef) {
-    if (lane < deg - c0) {
-        r = P.inc[row + c0 + lane];
-        coef = (uint64_t)P.inc_coef[row + c0 + lane];
-    } else {
-        r.meta = 0;
-        r.o[0] = r.o[1] = r.o[2] = 0;
-        coef = 0;
-    }
+    const int32_t idx = lane < deg - c0 ? row + c0 + lane : P.inc_pad;
+    r = P.inc[idx];
+    coef = (uint64_t)P.inc_coef[idx];
 }
 
 // Dense form, one window ahead: this lane's first 16 bytes of row k, h_k and the diagonal d_k.
@@ -294,11 +290,12 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int
     Acc part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
+    // kMaxE = 1: every record holds z_k to the first power (the zero record contributes 0)
     {
         int e;
         const Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
 #pragma unroll
-        for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
     }
     // further chunks (dense rows): four chunks' records are loaded before any is used
     for (int32_t c0 = kWave; c0 < deg; c0 += 4 * kWave) {
@@ -311,7 +308,7 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int
             int e;
             const Acc prod = record_product<Acc, ZT>(P, z, r[u], coef[u], e);
 #pragma unroll
-            for (int m = 1; m <= kMaxE; ++m) part[m] += (e == m) ? prod : (Acc)0;
+            for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
         }
     }
     C.a[0] = 0;
@@ -857,7 +854,10 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
             IncRec nrec;
             uint64_t ncoef;
             int64_t nd = 0;
+            int32_t nrow = 0, ndeg = 0;   // the prefetched slot's row and row length
             auto prefetch = [&](int32_t jj) {
+                nrow = (int32_t)lane_read32((uint32_t)sl.row, jj);
+                ndeg = (int32_t)lane_read32((uint32_t)sl.deg, jj);
                 if (kRule == SA_METROPOLIS && kRegChunk == 1) {
                     int4 q;
                     prefetch_dense(P, (int32_t)lane_read32((uint32_t)sl.k, jj), lane, q, ncoef, nd);
@@ -866,17 +866,18 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     nrec.o[1] = q.z;
                     nrec.o[2] = q.w;
                 } else {
-                    load_record(P, (int32_t)lane_read32((uint32_t)sl.row, jj),
-                                (int32_t)lane_read32((uint32_t)sl.deg, jj), 0, lane, nrec, ncoef);
+                    load_record(P, nrow, ndeg, 0, lane, nrec, ncoef);
                 }
             };
-            auto visit = [&](int32_t j, const IncRec &crec, uint64_t ccoef, int64_t cd) {
+            // next(): issues the next slot's prefetch where the rule has finished with the
+            // current records (the closed-form heat bath: once its coefficients are formed)
+            auto visit = [&](int32_t j, const IncRec &crec, uint64_t ccoef, int64_t cd, int32_t row, int32_t deg,
+                             auto &&next) {
                 const int32_t k = (int32_t)lane_read32((uint32_t)sl.k, j);
+                if (k < 0) next();
                 if (k >= 0) {
                     const int64_t lo = (int32_t)lane_read32((uint32_t)sl.lo, j);
                     const int64_t W = (int32_t)lane_read32((uint32_t)sl.width, j);
-                    const int32_t row = (int32_t)lane_read32((uint32_t)sl.row, j);
-                    const int32_t deg = (int32_t)lane_read32((uint32_t)sl.deg, j);
                     const uint32_t r0 = lane_read32(x0, j), r1 = lane_read32(x1, j);
                     const double U = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(Ul), j));
                     const int64_t zk = (int64_t)(int32_t)uni32((uint32_t)z[k]);
@@ -894,6 +895,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         Coeffs<kMaxE, Acc> C;
                         const uint32_t em = lane_read32(sl.emask, j);
                         row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
+                        next();
                         // closed form where dE is linear in the new value (no exponent above one)
                         const bool linear = kMaxE == 1 || (em & ~2u) == 0;
                         if (kRule == SA_HEAT_BATH_CLOSED && linear)
@@ -935,11 +937,20 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
             };
             prefetch(0);
             for (int32_t j = 0; j < wend; ++j) {
-                const IncRec crec = nrec;
-                const uint64_t ccoef = ncoef;
-                const int64_t cd = nd;
-                if (j + 1 < wend) prefetch(j + 1);
-                visit(j, crec, ccoef, cd);
+                if constexpr (kRule == SA_HEAT_BATH_CLOSED) {
+                    // the loads overwrite the records in place: the draw hides their latency, and
+                    // no registers are copied between slots (measured faster for this rule only)
+                    visit(j, nrec, ncoef, nd, nrow, ndeg, [&] {
+                        if (j + 1 < wend) prefetch(j + 1);
+                    });
+                } else {
+                    const IncRec crec = nrec;
+                    const uint64_t ccoef = ncoef;
+                    const int64_t cd = nd;
+                    const int32_t crow = nrow, cdeg = ndeg;
+                    if (j + 1 < wend) prefetch(j + 1);
+                    visit(j, crec, ccoef, cd, crow, cdeg, [] {});
+                }
             }
         }
     }

@@ -105,13 +105,14 @@ struct DevProblem {
     int32_t n_terms;
     const VarRec *var;
     const uint32_t *emask;
-    const IncRec *inc;
+    const IncRec *inc;       // incidence records, then one zero record at index inc_pad
     const int64_t *inc_coef;
     const int32_t *overflow;
     const int32_t *t_off;
     const int32_t *t_var;
     const int64_t *t_coef;
     int32_t max_other;       // most other factors of any incidence
+    int32_t inc_pad;         // index of the zero record (coefficient 0, no factors)
     // dense QUIO form (dense != 0)
     int32_t dense;
     int32_t jbytes;
