@@ -948,7 +948,9 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     const uint64_t ccoef = ncoef;
                     const int64_t cd = nd;
                     const int32_t crow = nrow, cdeg = ndeg;
-                    if (j + 1 < wend) prefetch(j + 1);
+                    // unconditional (the last slot loads its own records again), so that the
+                    // records need no copy on a path without the prefetch
+                    prefetch(j + 1 < wend ? j + 1 : j);
                     visit(j, crec, ccoef, cd, crow, cdeg, [] {});
                 }
             }
