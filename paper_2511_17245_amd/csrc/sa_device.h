@@ -940,9 +940,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                 if constexpr (kRule == SA_HEAT_BATH_CLOSED) {
                     // the loads overwrite the records in place: the draw hides their latency, and
                     // no registers are copied between slots (measured faster for this rule only)
-                    visit(j, nrec, ncoef, nd, nrow, ndeg, [&] {
-                        if (j + 1 < wend) prefetch(j + 1);
-                    });
+                    visit(j, nrec, ncoef, nd, nrow, ndeg, [&] { prefetch(j + 1 < wend ? j + 1 : j); });
                 } else {
                     const IncRec crec = nrec;
                     const uint64_t ccoef = ncoef;
