@@ -27,6 +27,8 @@ PEAK_HBM_GBS = 8000.0
 # two additions of the blocked cumulative sum (running sum + block offset).  The exp evaluation
 # is counted as the FP64 operations the gfx950 exp sequence executes (FMA = 2 flops).
 FP64_FLOPS_PER_WEIGHT = 30.0
+# VALU issue: a wave64 VALU instruction occupies one of the 4 SIMDs of a compute unit for 4 cycles
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4   # 10^9 wave instructions/s
 
 
 def parse():
@@ -99,8 +101,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key):
-    """HBM bytes per launch from the committed counter summary, or None when the kernels changed
+def counter_record(workload_key):
+    """The committed counter summary of a workload's kernel, or None when the kernels changed
     since it was taken (or none exists)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -109,7 +111,13 @@ def measured_traffic(workload_key):
         rec = json.load(f).get(workload_key)
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec
+
+
+def measured_traffic(workload_key):
+    """HBM bytes per launch from the committed counter summary (None as counter_record)."""
+    rec = counter_record(workload_key)
+    return None if rec is None else rec["hbm_bytes_per_launch"]
 
 
 def copy_probe(mib):
@@ -626,6 +634,14 @@ def main():
                    "wall_s": wall},
         "roofline": roof,
     }
+    crec = counter_record(f"{args.config}:{S}:{R}")
+    if crec and crec.get("valu_insts_per_update"):
+        # the binding resource of the heat bath: VALU instructions per update (counters, same
+        # kernel sources) at this run's update rate, against the issue peak of the chip
+        vi = crec["valu_insts_per_update"] * value / 1e9
+        out["valu_issue"] = {"achieved": vi, "peak": VALU_ISSUE_PEAK_G, "unit": "G wave-instructions/s",
+                             "frac": vi / VALU_ISSUE_PEAK_G, "insts_per_update": crec["valu_insts_per_update"],
+                             "source": crec.get("profile")}
     if args.config == "cfg2" and not args.no_closed_form:
         # the paper's O(1) heat-bath draw on the same workload (its variables are all linear)
         cplan = sa.Plan(prob, sa.HEAT_BATH_CLOSED)

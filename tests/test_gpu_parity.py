@@ -77,6 +77,12 @@ def small_cases():
     yield "dense_int32_couplings_n70", I.dense_quio(70, -20, 20, 1000, 1000, r), 40, 24, RULES
     yield "dense_no_diagonal_n150", I.fully_connected(150, 1, 3), 30, 16, RULES
     yield "many_reads_n50", I.random_huio(50, 200, [2, 3], -3, 3, 3, r), 20, 2048, RULES
+    # sparse form with one variable in 300+ terms: its row spans six 64-record chunks (the first
+    # chunk prefetched, the rest loaded four at a time, lanes past the end on the zero record)
+    hub = I.random_huio(400, 1600, [1, 2, 3], -6, 6, 4, r)
+    hub_terms = list(hub.terms()) + [(int(c), [0, i]) for i, c in zip(range(1, 301), r.integers(1, 6, 300))]
+    hub_terms += [(2, [0, 5, 9]), (-3, [7, 7, 0]), (1, [0, 0])]
+    yield "hub_rows_over_256", I.from_terms(400, hub_terms, -6, 6), 40, 32, RULES
 
 
 @pytest.mark.parametrize("case", list(small_cases()), ids=lambda c: c[0])
