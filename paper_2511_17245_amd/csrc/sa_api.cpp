@@ -133,6 +133,7 @@ int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, s
     plan->auto_status = sa::auto_temperatures(canon, &plan->t_init, &plan->t_final, plan->auto_error);
     rc = upload_packed(pk, plan.get());
     if (rc != SA_OK) return rc;
+    plan->dp.coef32 = sa::coefs_fit_32(canon) ? 1 : 0;
     sa_plan_info &in = plan->info;
     in.n_vars = pk.n;
     in.n_terms = pk.n_terms;

@@ -287,6 +287,20 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int
         if (kMaxE >= 2) C.a[kMaxE >= 2 ? 2 : 1] = (Acc)P.d[k];
         return;
     }
+    if (sizeof(Acc) == 8 && P.coef32 && deg <= kWave) {
+        // every coefficient fits 32 bits: products and wave sums in 32-bit arithmetic, then
+        // sign-extended (exact: the true values are below 2^31)
+        uint32_t part32[kMaxE + 1];
+        int e;
+        const uint32_t prod = record_product<uint32_t, ZT>(P, z, r0, coef0, e);
+#pragma unroll
+        for (int m = 1; m <= kMaxE; ++m) part32[m] = (kMaxE == 1 || e == m) ? prod : 0u;
+        C.a[0] = 0;
+#pragma unroll
+        for (int m = 1; m <= kMaxE; ++m)
+            C.a[m] = (emask & (1u << m)) ? (Acc)(int64_t)(int32_t)wave_sum<uint32_t>(part32[m]) : (Acc)0;
+        return;
+    }
     Acc part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
@@ -346,6 +360,11 @@ __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z
         return to_i64<Acc>(d);
     }
     int e;
+    if (sizeof(Acc) == 8 && P.coef32 && linear && deg <= kWave) {
+        // a1 fits 32 bits: the products and the wave sum in 32-bit arithmetic, dE in 64-bit
+        const uint32_t p32 = record_product<uint32_t, ZT>(P, z, r0, coef0, e);
+        return (int64_t)(int32_t)wave_sum<uint32_t>(p32) * (v - zk);
+    }
     Acc prod = record_product<Acc, ZT>(P, z, r0, coef0, e);
     if (linear && deg <= kWave) return to_i64<Acc>(wave_sum<Acc>(prod) * (Acc)(v - zk));
     Acc acc = prod * (upow<Acc>((Acc)v, e) - upow<Acc>((Acc)zk, e));

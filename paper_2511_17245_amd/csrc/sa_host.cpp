@@ -188,6 +188,30 @@ bool dE_fits_32(const Canonical &c) {
     return true;
 }
 
+bool coefs_fit_32(const Canonical &c) {
+    // per variable k: sum over the terms holding z_k of |J| * prod over the other factors of
+    // zmax^e, which bounds every coefficient a_k^(m) and every partial sum of it
+    const __int128 limit = (__int128)1 << 31;
+    std::vector<__int128> per_var(c.n, 0);
+    for (int64_t t = 0; t < c.n_terms(); ++t) {
+        const __int128 absj = c.t_coef[t] < 0 ? -(__int128)c.t_coef[t] : (__int128)c.t_coef[t];
+        for (int64_t f = c.t_off[t]; f < c.t_off[t + 1]; ++f) {
+            if (f > c.t_off[t] && c.t_var[f] == c.t_var[f - 1]) continue;
+            const int32_t k = c.t_var[f];
+            __int128 b = absj;
+            for (int64_t g = c.t_off[t]; g < c.t_off[t + 1] && b < limit; ++g) {
+                const int32_t i = c.t_var[g];
+                if (i == k) continue;
+                b *= std::max(std::llabs((long long)c.lo[i]), std::llabs((long long)c.hi[i]));
+            }
+            if (b >= limit) return false;
+            per_var[k] += b;
+            if (per_var[k] >= limit) return false;
+        }
+    }
+    return true;
+}
+
 int auto_temperatures(const Canonical &c, double *t_init, double *t_final, std::string &err) {
     // dE_max ~ max_k sum over terms holding z_k^m of |J| * prod_{other factors} zmax^e * (u_k - l_k)^m
     // dE_min ~ min |J| over the (merged, nonzero) coefficients.

@@ -40,6 +40,8 @@ int check_int64_bound(const Canonical &c, std::string &err, double *bound_out);
 // True when max_k sum_{t containing k} |J_t| prod_{factors} zmax^e < 2^29, so every energy
 // difference |dE| < 2^30 and the difference of two of them fit 32-bit signed arithmetic.
 bool dE_fits_32(const Canonical &c);
+// every coefficient a_k^(m) (and each incidence record's product) below 2^31 in magnitude
+bool coefs_fit_32(const Canonical &c);
 // Sec. 3.4 temperature range (T_init, T_final); SA_EINVAL if the problem has no energy scale.
 int auto_temperatures(const Canonical &c, double *t_init, double *t_final, std::string &err);
 // Geometric cooling of Sec. 3.1 between the two temperatures, as inverse temperatures.
@@ -113,6 +115,7 @@ struct DevProblem {
     const int64_t *t_coef;
     int32_t max_other;       // most other factors of any incidence
     int32_t inc_pad;         // index of the zero record (coefficient 0, no factors)
+    int32_t coef32;          // every coefficient a_k^(m) fits int32 (coefs_fit_32)
     // dense QUIO form (dense != 0)
     int32_t dense;
     int32_t jbytes;
