@@ -83,6 +83,8 @@ def small_cases():
     hub_terms = list(hub.terms()) + [(int(c), [0, i]) for i, c in zip(range(1, 301), r.integers(1, 6, 300))]
     hub_terms += [(2, [0, 5, 9]), (-3, [7, 7, 0]), (1, [0, 0])]
     yield "hub_rows_over_256", I.from_terms(400, hub_terms, -6, 6), 40, 32, RULES
+    # coefficients above 2^31 (|z| <= 2000, degree 4): the 64-bit kernels' full 64-bit path
+    yield "huio_wide_64bit_coefs", I.random_huio(60, 240, [1, 2, 3, 4], -2000, 2000, 5, r), 10, 8, RULES
 
 
 @pytest.mark.parametrize("case", list(small_cases()), ids=lambda c: c[0])
