@@ -122,6 +122,29 @@ def test_cooperating_waves_match_sequential_sweep(rule):
             assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]}/G={G} {launch}")
 
 
+def test_degenerate_instances():
+    # terms that cancel (no canonical term: every dE is 0), every variable fixed (no update), and
+    # the widest range the ABI accepts (u - l = 2^31 - 2) with one read and one or three sweeps
+    cancel = I.from_terms(4, [(3, [0, 1]), (-3, [1, 0]), (2, [2, 2]), (-2, [2, 2])], -3, 4)
+    fixed = I.from_terms(3, [(3, [0, 1]), (-2, [1, 2, 2])], 2, 2)
+    wide = I.from_terms(2, [(1, [0]), (1, [0, 1]), (-1, [1])], [-2 ** 30, -3], [2 ** 30 - 2, 3])
+    beta5 = np.linspace(0.1, 2.0, 5)
+    cases = [("cancelling_terms", cancel, beta5, 3, RULES), ("all_fixed", fixed, beta5, 2, RULES),
+             ("widest_range_one_sweep", wide, np.array([1e-9]), 1,
+              [sa.METROPOLIS, sa.OPT_METROPOLIS, sa.HEAT_BATH_CLOSED]),
+             ("widest_range_three_sweeps", wide, np.array([1e-9, 1e-6, 1e-3]), 4,
+              [sa.METROPOLIS, sa.OPT_METROPOLIS, sa.HEAT_BATH_CLOSED])]
+    for name, prob, beta, reads, rules in cases:
+        P = oracle.Poly(prob)
+        for rule in rules:
+            say("degenerate", name, sa.RULE_NAMES[rule])
+            zg, eg, launch = gpu_run(prob, rule, beta, reads, seed=9)
+            zo, eo = P.anneal(rule, beta, reads, seed=9)
+            assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]} {launch}")
+    zg, eg, _ = gpu_run(fixed, sa.HEAT_BATH, beta5, 2, seed=9)
+    assert (zg == 2).all() and (eg == -4).all()
+
+
 def test_cfg1_full_all_reads():
     w = I.cfg1_dense_quio()
     P = oracle.Poly(w.problem)
