@@ -283,7 +283,11 @@ __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int
         // QUIO: a^(1) = h_k + sum_j J_kj z_j, a^(2) = J_kk (Sec. 3.2, the c^(1), c^(2) of QUIO)
 #pragma unroll
         for (int m = 0; m <= kMaxE; ++m) C.a[m] = 0;
-        C.a[1] = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, nullptr)) + (Acc)P.h[k];
+        if (sizeof(Acc) == 8 && P.coef32)   // a^(1) fits 32 bits: the row product in 32-bit
+            C.a[1] = (Acc)(int64_t)(int32_t)(wave_sum<uint32_t>(dense_dot<uint32_t, ZT>(P, z, k, lane, nullptr)) +
+                                             (uint32_t)P.h[k]);
+        else
+            C.a[1] = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, nullptr)) + (Acc)P.h[k];
         if (kMaxE >= 2) C.a[kMaxE >= 2 ? 2 : 1] = (Acc)P.d[k];
         return;
     }
@@ -353,8 +357,14 @@ __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z
                                                 const IncRec &r0, uint64_t coef0, int64_t dk, bool linear) {
     if (P.dense) {
         const int4 first = make_int4((int)r0.meta, r0.o[0], r0.o[1], r0.o[2]);
-        const Acc a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, kDensePre ? &first : nullptr)) +
-                       (kDensePre ? (Acc)coef0 : (Acc)P.h[k]);
+        Acc a1;
+        if (sizeof(Acc) == 8 && P.coef32)   // a^(1) fits 32 bits: the row product in 32-bit
+            a1 = (Acc)(int64_t)(int32_t)(wave_sum<uint32_t>(dense_dot<uint32_t, ZT>(P, z, k, lane,
+                                                                                   kDensePre ? &first : nullptr)) +
+                                         (uint32_t)(kDensePre ? coef0 : (uint64_t)P.h[k]));
+        else
+            a1 = wave_sum<Acc>(dense_dot<Acc, ZT>(P, z, k, lane, kDensePre ? &first : nullptr)) +
+                 (kDensePre ? (Acc)coef0 : (Acc)P.h[k]);
         const Acc dd = kDensePre ? (Acc)dk : (Acc)P.d[k];
         const Acc d = a1 * (Acc)(v - zk) + dd * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk);
         return to_i64<Acc>(d);

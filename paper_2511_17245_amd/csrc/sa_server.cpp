@@ -133,6 +133,9 @@ void finish_locked(sa_server *S, Request *r, int32_t status) {
 }
 
 constexpr size_t kMaxCachedPlans = 64;
+// Cost units (cost_of_update x variables) of the median sweep a chunk is sized by, at most: about
+// one sweep of a 2000-variable sparse request.
+constexpr double kSweepCostCap = 8192.0;
 
 // Frees cached plans no request holds, least recently used first, down to the cache limits
 // (entry count, and a quarter of the memory budget).  S->mu held.
@@ -357,7 +360,9 @@ int run_chunk(sa_server *S, const std::vector<Request *> &act, std::string &err)
     for (int i = 0; i < n; ++i) per_sweep[i] = act[i]->plan->dp.n * cost_of_update(*act[i]->plan);
     std::vector<double> sorted(per_sweep);
     std::nth_element(sorted.begin(), sorted.begin() + n / 2, sorted.end());
-    const double budget_time = C * sorted[n / 2];
+    // capped, so that a chunk of heavy requests alone stays short: requests are admitted only
+    // between chunks, and a long chunk would hold back every arrival behind it
+    const double budget_time = C * std::min(sorted[n / 2], kSweepCostCap);
     std::vector<int32_t> sweeps(n);
     for (int i = 0; i < n; ++i) {
         const int32_t left = act[i]->n_sweeps - act[i]->next_sweep;
