@@ -489,6 +489,9 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
         }
         dmin = wave_min_i64(dmin);
     }
+    // kRegChunk = 0 evaluates the weights in groups of kGroup independent exponentials (their
+    // latencies overlap); they are still added one by one in value order
+    constexpr uint32_t kGroup = 4;
     // exp(-beta * (dE - dmin)); in 32-bit mode the difference is formed in 32 bits (it fits)
     auto weight = [&](uint32_t j) -> double {
         double x;
@@ -516,9 +519,16 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             lane_sum = i == 0 ? w[0] : lane_sum + w[i];
         }
     } else {
-        for (uint32_t i = 0; i < c; ++i) {
-            const uint32_t j = j0 + i;
-            if (j < W32) lane_sum += weight(j);
+        for (uint32_t i = 0; i < c; i += kGroup) {
+            double wv[kGroup];
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                const uint32_t j = j0 + i + u;
+                const double x = weight(j < W32 ? j : W32 - 1u);
+                wv[u] = (i + u < c && j < W32) ? x : 0.0;   // adding +0.0 leaves the sum unchanged
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) lane_sum += wv[u];
         }
     }
     const double incl = wave_scan_rows(lane_sum, cy);
@@ -538,13 +548,18 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
         }
     } else {
         double run = 0.0;
-        for (uint32_t i = 0; i < c; ++i) {
-            const uint32_t j = j0 + i;
-            if (j < W32) {
-                run += weight(j);
-                if (before + run > thr) {
-                    hit = (int32_t)i;
-                    break;
+        for (uint32_t i = 0; i < c && hit < 0; i += kGroup) {
+            double wv[kGroup];
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                const uint32_t j = j0 + i + u;
+                wv[u] = weight(j < W32 ? j : W32 - 1u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                if (hit < 0 && i + u < c && j0 + i + u < W32) {
+                    run += wv[u];
+                    if (before + run > thr) hit = (int32_t)(i + u);
                 }
             }
         }
@@ -1082,7 +1097,10 @@ __global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B)
         int32_t *zo = D.z_out + (size_t)read * P.n;
         if (active) init_state(P, z, D.resume ? zo : nullptr, read, D.instance_id, D.key0, D.key1, tid, nthr);
         window_barrier();
-        int64_t E = active ? energy_part(P, z, tid, nthr) : 0;
+        // a resumed replica continues from the exact energy its previous chunk wrote (the team's
+        // first wave carries it); a new one sums its terms
+        int64_t E = 0;
+        if (active) E = D.resume ? (g == 0 ? D.e_out[read] : 0) : energy_part(P, z, tid, nthr);
         ReplicaCtx R;
         R.P = P;
         R.beta = D.beta;

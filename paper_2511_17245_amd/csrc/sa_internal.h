@@ -179,7 +179,7 @@ struct BatchInst {
     int32_t n_reads;
     int32_t n_sweeps;
     int32_t s_begin, s_end;  // sweeps of this launch (a server chunk, or the whole schedule)
-    int32_t resume;          // 1: start from the states in z_out (written by an earlier chunk)
+    int32_t resume;          // 1: start from the states in z_out and energies in e_out (an earlier chunk's)
     int32_t rule;
     int32_t chunk;           // heat bath: register chunk class (1, 2, 8; 0 = recompute)
     uint32_t key0, key1, instance_id;

@@ -4,11 +4,11 @@
 // prepared plan is shared).  Prep threads canonicalise, pack and upload them.  One scheduler thread
 // owns the device work: it admits prepared requests in arrival order while a slot is free and
 // their device footprint (plan, states, schedule) fits the memory budget, then advances every
-// admitted request by one chunk of sweeps in a single launch of the batched kernel.  States stay
-// on the device between chunks (each chunk resumes from them), so requests that arrive while
-// others run join at the next chunk boundary, and a request's result does not depend on which
-// requests shared its chunks: the draws are keyed by (variable, sweep, read, instance id) and the
-// energy is recomputed exactly at every chunk start.
+// admitted request by one chunk of sweeps in a single launch of the batched kernel.  States and
+// their exact energies stay on the device between chunks (each chunk resumes from them), so
+// requests that arrive while others run join at the next chunk boundary, and a request's result
+// does not depend on which requests shared its chunks: the draws are keyed by (variable, sweep,
+// read, instance id) and the energy changes are exact integers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
