@@ -547,22 +547,32 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             hit = (hit < 0 && pass) ? i : hit;
         }
     } else {
-        double run = 0.0;
-        for (uint32_t i = 0; i < c && hit < 0; i += kGroup) {
-            double wv[kGroup];
-#pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u) {
-                const uint32_t j = j0 + i + u;
-                wv[u] = weight(j < W32 ? j : W32 - 1u);
+        // The drawn value lies in the first block (lane) whose last value passes the threshold:
+        // a block's cumulative weights never decrease, and the last one is before + lane_sum (the
+        // same additions in the same order).  Only that block is walked again, 64 values at a
+        // time: one weight per lane, then every lane forms the block's running sum up to its own
+        // value in value order (adding +0.0 for the later values leaves it unchanged).
+        const uint64_t bmask = __ballot(j0 < W32 && before + lane_sum > thr);
+        if (bmask == 0) return lo + W - 1;
+        const int L = __ffsll((unsigned long long)bmask) - 1;
+        const double bL = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(before), L));
+        const uint32_t jL = (uint32_t)L * c;
+        const uint32_t nL = c < W32 - jL ? c : W32 - jL;
+        double carry = 0.0;   // running sum of the block's values before this part
+        for (uint32_t p0 = 0; p0 < nL; p0 += kWave) {
+            const uint32_t m = nL - p0 < (uint32_t)kWave ? nL - p0 : (uint32_t)kWave;
+            const uint32_t jl = jL + p0 + ((uint32_t)lane < m ? (uint32_t)lane : m - 1u);
+            const double wl = weight(jl);
+            double run = carry;
+            for (uint32_t t = 0; t < m; ++t) {
+                const double wt = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(wl), (int)t));
+                run += t <= (uint32_t)lane ? wt : 0.0;
             }
-#pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u) {
-                if (hit < 0 && i + u < c && j0 + i + u < W32) {
-                    run += wv[u];
-                    if (before + run > thr) hit = (int32_t)(i + u);
-                }
-            }
+            const uint64_t hm = __ballot((uint32_t)lane < m && bL + run > thr);
+            if (hm) return lo + (int64_t)(jL + p0) + (int64_t)(__ffsll((unsigned long long)hm) - 1);
+            carry = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(run), (int)(m - 1)));
         }
+        return lo + (int64_t)jL + (int64_t)nL - 1;   // the block's last value passes (not reached)
     }
     const uint64_t mask = __ballot(hit >= 0);
     if (mask == 0) return lo + W - 1;
