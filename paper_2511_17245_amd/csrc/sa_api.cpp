@@ -227,13 +227,16 @@ using sa::stage_beta;
 using sa::resolve_schedule;
 
 // Waves per replica.  The sweep is latency-bound (one dependent chain per replica), so the widest
-// window G in {8, 4, 2} is taken whose waves stay busy (mean window size >= 0.6 G), whose shared
-// state fits in LDS and which keeps at most 8 waves per SIMD in flight; otherwise G = 1.
+// window G in {16, 8, 4, 2} is taken whose waves stay busy (mean window size >= 0.6 G), whose
+// shared state fits in LDS and whose n_reads x G waves are all resident at once; otherwise G = 1.
+// The annealing variants use 84 to 128 VGPRs, which leaves room for 4 waves per SIMD: a wider G
+// would run the replicas in two rounds (measured slower, e.g. 8 against 4 waves per replica for
+// 1024 replicas of the N = 2000 HUIO problem: 573 against 508 ms).
 int auto_waves_per_replica(sa_plan *plan, int32_t n_reads, int device) {
     int cus = 256, max_lds = 65536;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    const int64_t max_waves = (int64_t)cus * 4 * 8;
+    const int64_t max_waves = (int64_t)cus * 4 * 4;
     for (int G = 16; G > 1; G /= 2) {
         if ((int64_t)n_reads * G > max_waves) continue;
         if (sa::shared_state_bytes(plan->dp.n, G) > max_lds) continue;
