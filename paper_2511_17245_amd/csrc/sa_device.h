@@ -393,28 +393,28 @@ __device__ __forceinline__ int64_t direct_delta(const DevProblem &P, const ZT *z
 }
 
 // e^x for x <= 0 (every exponential of the annealer has a non-positive argument): x = n ln 2 + r
-// with |r| <= ln(2)/2, e^r by its Taylor polynomial to r^13 (truncation below 2^-57 relative), then
-// scaled by 2^n.  The scaling rounds once, so below -745.2, where e^x is under half the smallest
-// subnormal, the result is 0 (arguments under -746 are clamped there first).  Within about an
-// ulp, like the host library the oracle uses; a last-bit difference moves a draw only when a
-// uniform number falls within that ulp of a threshold.
+// with |r| <= ln(2)/2, e^r by the degree-11 polynomial that interpolates it at the 12 Chebyshev
+// nodes of that interval (relative error below 2^-55.7; gen_exp_poly.py derives the coefficients
+// and checks the routine: at most about 0.83 ulp), then scaled by 2^n.  The scaling rounds once,
+// so below -745.2, where e^x is under half the smallest subnormal, the result is 0 (arguments
+// under -746 are clamped there first).  Within about an ulp, like the host library the oracle
+// uses; a last-bit difference moves a draw only when a uniform number falls within that ulp of a
+// threshold.
 __device__ __forceinline__ double exp_nonpos(double x) {
     const double xc = x > -746.0 ? x : -746.0;
     const double n = rint(xc * 1.4426950408889634);     // 1 / ln 2
     double r = fma(-n, 0.6931471803691238, xc);          // ln 2 rounded to 32 bits (n * it exact)
     r = fma(-n, 1.9082149292705877e-10, r);              // the rest of ln 2
-    double p = 1.0 / 6227020800.0;                       // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
+    double p = 2.5110037605963777e-08;
+    p = fma(p, r, 2.763263963904103e-07);
+    p = fma(p, r, 2.755724091857897e-06);
+    p = fma(p, r, 2.4801485482328494e-05);
+    p = fma(p, r, 0.00019841269890047113);
+    p = fma(p, r, 0.0013888888952314775);
+    p = fma(p, r, 0.008333333333319601);
+    p = fma(p, r, 0.0416666666664881);
+    p = fma(p, r, 0.1666666666666668);
+    p = fma(p, r, 0.5000000000000019);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
     return __builtin_amdgcn_ldexp(p, (int)n);
