@@ -145,6 +145,38 @@ def test_degenerate_instances():
     assert (zg == 2).all() and (eg == -4).all()
 
 
+def random_instances():
+    # seeded small instances across the kernels' paths: narrow and wide ranges (32-bit and 64-bit
+    # energy differences, 32-bit and 64-bit coefficients), linear and power terms, fixed
+    # variables, short and long rows, exponents up to 4 (every rule takes them)
+    r = rng(2718)
+    for i in range(24):
+        n = int(r.integers(1, 70))
+        span = int([1, 3, 20, 300, 5000][i % 5])
+        lo = int(r.integers(-span, 1))
+        hi = lo + int(r.integers(0, 2 * span + 1))
+        prob = I.tiny_random(r, n, lo, hi, int(r.integers(1, 4 * n + 2)), int(r.integers(1, 5)),
+                             jmax=int([3, 9, 200][i % 3]), name=f"random{i}")
+        prob.lower[r.random(n) < 0.1] = hi    # some variables fixed
+        yield f"random{i}_n{n}_w{hi - lo + 1}", prob
+
+
+@pytest.mark.parametrize("case", list(random_instances()), ids=lambda c: c[0])
+def test_random_instances_all_reads(case):
+    name, prob = case
+    P = oracle.Poly(prob)
+    try:
+        beta, _, _ = P.schedule(12)
+    except oracle.OracleError:
+        # no energy scale for the automatic schedule (every variable fixed): a given one
+        beta = np.geomspace(0.01, 2.0, 12)
+    for rule in RULES:
+        say(name, sa.RULE_NAMES[rule])
+        zg, eg, launch = gpu_run(prob, rule, beta, 9, seed=404 + rule, instance_id=7)
+        zo, eo = P.anneal(rule, beta, 9, seed=404 + rule, instance_id=7)
+        assert_same(zg, eg, zo, eo, f"{name}/{sa.RULE_NAMES[rule]} {launch}")
+
+
 def test_cfg1_full_all_reads():
     w = I.cfg1_dense_quio()
     P = oracle.Poly(w.problem)
