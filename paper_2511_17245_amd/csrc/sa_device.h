@@ -508,7 +508,31 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
     constexpr int kR = kRegChunk > 0 ? kRegChunk : 1;
     double w[kR];
     double lane_sum = 0.0;
-    if (kRegChunk > 0) {
+    // Linear dE, eight or more values per lane: once beta |a1| 64 >= 745.2, every value at
+    // distance 64 or more from the minimising end weighs exactly 0 (exp_nonpos of an argument at
+    // or below -745.2 is 0, and the rounded products beta |a1| d grow with d).  Lane d then
+    // evaluates the weight of the value at distance d, and each slot takes its weight from that
+    // lane: one exponential per lane instead of kRegChunk, the same numbers.  (With two values
+    // per lane the exchange costs more than the exponential it saves: measured slower.)
+    constexpr bool kGather = kRegChunk >= 8;
+    const bool gather = kGather && linear && beta * ((double)slope * 64.0) >= 745.2;
+    if (kGather && gather) {
+        const uint32_t dl = (uint32_t)lane < W32 ? (uint32_t)lane : W32 - 1u;
+        const double wl = weight(from_top ? W32 - 1u - dl : dl);
+        const uint32_t lo32 = (uint32_t)__double_as_longlong(wl);
+        const uint32_t hi32 = (uint32_t)((uint64_t)__double_as_longlong(wl) >> 32);
+#pragma unroll
+        for (int i = 0; i < kR; ++i) {
+            const uint32_t j = j0 + (uint32_t)i;
+            const bool valid = (uint32_t)i < c && j < W32;
+            const uint32_t d = from_top ? W32 - 1u - j : j;
+            const int src = (int)((valid && d < (uint32_t)kWave ? d : 0u) << 2);
+            const uint64_t bits = ((uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)hi32) << 32) |
+                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)lo32);
+            w[i] = (valid && d < (uint32_t)kWave) ? __longlong_as_double((long long)bits) : 0.0;
+            lane_sum = i == 0 ? w[0] : lane_sum + w[i];
+        }
+    } else if (kRegChunk > 0) {
 #pragma unroll
         for (int i = 0; i < kR; ++i) {
             // evaluated for every slot (at a clamped index past the range) so that the exps of a
