@@ -104,10 +104,14 @@ def test_cooperating_waves_match_sequential_sweep(rule):
     # G waves per replica update the variables of a window (no shared term) at the same time;
     # the result must equal the sequential index-order sweep for every G
     r = rng(55)
+    # a path (each variable couples to the next): most windows hold one variable
+    path = I.from_terms(300, [(int(c), [i, i + 1]) for i, c in enumerate(r.integers(-9, 10, 299))]
+                        + [(1, [i]) for i in range(0, 300, 7)], -4, 4)
     cases = [("dense", I.dense_quio(90, -5, 5, 10, 10, r)),
              ("er_quio", I.erdos_renyi_quio(700, 5.0, -20, 20, 10, 10, r)),
              ("huio_powers", I.random_huio(400, 1200, [1, 2, 3, 4], -6, 6, 4, r)),
-             ("ml_long", I.multilinear(150, 7, 2))]
+             ("ml_long", I.multilinear(150, 7, 2)),
+             ("path", path)]
     for name, prob in cases:
         P = oracle.Poly(prob)
         beta, _, _ = P.schedule(25)
