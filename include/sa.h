@@ -6,8 +6,9 @@
  * Optimization", arXiv:2511.17245.  The library runs the paper's single-variable update sweep
  * (Sec. 3.1) with the energy difference of Sec. 3.2 and the three transition rules of Sec. 3.3
  * (Metropolis, heat bath, optimal-transition Metropolis; the heat bath also with the closed-form
- * draw of Sec. 3.3.2 for linear energy differences) as HIP kernels, one replica (read) per
- * 64-lane wavefront.
+ * draw of Sec. 3.3.2 for linear energy differences) as HIP kernels.  A replica (read) is
+ * updated by one 64-lane wavefront, or by a team of up to 16 wavefronts that update variables
+ * sharing no term at the same time (the result is the sequential sweep's either way).
  *
  * Conventions shared by every entry point
  *  - All functions return an int32_t status (SA_OK or a negative SA_E* code).  On failure no
