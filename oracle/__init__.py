@@ -64,14 +64,30 @@ def lib():
                                  p, p, p]
         L.sao_anneal.restype = C.c_int
         L.sao_anneal_reads.argtypes = [p, C.c_int, p, i32, i32, i32, i32, p, u64, u32, dbl, C.c_int,
-                                       C.c_int, p, p, p]
+                                       C.c_int, p, p, p, p]
         L.sao_anneal_reads.restype = C.c_int
         L.sao_single_step.argtypes = [p, C.c_int, p, i32, i32, dbl, dbl, i32, u64, u32, p]
         L.sao_single_step.restype = C.c_int
+        L.sao_state_hash.argtypes = [i32, p]
+        L.sao_state_hash.restype = u64
+        L.sao_mix64.argtypes = [u64]
+        L.sao_mix64.restype = u64
+        L.sao_explain_step.argtypes = [p, C.c_int, p, i32, i32, u32, dbl, dbl, u64, u32, C.POINTER(StepInfo)]
+        L.sao_explain_step.restype = C.c_int
         L.sao_default_threads.argtypes = []
         L.sao_default_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+class StepInfo(C.Structure):
+    """What one update computed (``sao_step_info``)."""
+    _fields_ = [("v", C.c_int64), ("dE", C.c_int64), ("accepted", C.c_int32), ("branch", C.c_int32),
+                ("U", C.c_double), ("threshold", C.c_double), ("total", C.c_double),
+                ("c_prev", C.c_double), ("c_at", C.c_double), ("margin", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class OracleError(RuntimeError):
@@ -160,22 +176,15 @@ class Poly:
         return beta, ti.value, tf.value
 
     def anneal(self, rule, beta, n_reads, seed, instance_id=0, s_begin=0, s_end=None,
-               otm_r=-1.0, cache_mode=0, n_threads=0, z_init=None):
-        beta = np.ascontiguousarray(beta, np.float64)
-        S = int(beta.shape[0])
-        s_end = S if s_end is None else int(s_end)
-        z = np.zeros((n_reads, self.n), np.int32)
-        e = np.zeros(n_reads, np.int64)
-        zi = None if z_init is None else np.ascontiguousarray(z_init, np.int32).reshape(n_reads, self.n)
-        rc = lib().sao_anneal(self.h, int(rule), _ptr(beta), S, int(s_begin), s_end, int(n_reads),
-                              int(seed) & 0xFFFFFFFFFFFFFFFF, int(instance_id) & 0xFFFFFFFF,
-                              float(otm_r), int(cache_mode), int(n_threads), _ptr(zi), _ptr(z), _ptr(e))
-        if rc != OK:
-            raise OracleError(rc, "anneal")
-        return z, e
+               otm_r=-1.0, cache_mode=0, n_threads=0, z_init=None, trace=False):
+        """Final states and tracked energies of reads 0..n_reads-1; with trace=True also the state
+        hash after every sweep of the run (n_reads x (s_end - s_begin), uint64)."""
+        return self.anneal_reads(rule, beta, np.arange(n_reads, dtype=np.uint32), seed, instance_id,
+                                 otm_r, cache_mode, n_threads, s_begin=s_begin, s_end=s_end,
+                                 z_init=z_init, trace=trace)
 
     def anneal_reads(self, rule, beta, read_ids, seed, instance_id=0, otm_r=-1.0, cache_mode=0,
-                     n_threads=0):
+                     n_threads=0, s_begin=0, s_end=None, z_init=None, trace=False):
         """Chains of the given read ids only (rows in the order of read_ids)."""
         beta = np.ascontiguousarray(beta, np.float64)
         ids = np.ascontiguousarray(read_ids, np.uint32)
@@ -183,12 +192,28 @@ class Poly:
         z = np.zeros((n, self.n), np.int32)
         e = np.zeros(n, np.int64)
         S = int(beta.shape[0])
-        rc = lib().sao_anneal_reads(self.h, int(rule), _ptr(beta), S, 0, S, n, _ptr(ids),
+        s_end = S if s_end is None else int(s_end)
+        zi = None if z_init is None else np.ascontiguousarray(z_init, np.int32).reshape(n, self.n)
+        h = np.zeros((n, max(s_end - int(s_begin), 0)), np.uint64) if trace else None
+        rc = lib().sao_anneal_reads(self.h, int(rule), _ptr(beta), S, int(s_begin), s_end, n, _ptr(ids),
                                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(instance_id) & 0xFFFFFFFF,
-                                    float(otm_r), int(cache_mode), int(n_threads), None, _ptr(z), _ptr(e))
+                                    float(otm_r), int(cache_mode), int(n_threads), _ptr(zi), _ptr(z),
+                                    _ptr(e), _ptr(h) if trace and h.size else None)
         if rc != OK:
             raise OracleError(rc, "anneal_reads")
-        return z, e
+        return (z, e, h) if trace else (z, e)
+
+    def explain_step(self, rule, z, k, s, read, beta, r_opt, seed, instance_id=0) -> dict:
+        """The update of variable k at sweep s of read `read` from state z: drawn or proposed value,
+        its energy change, the uniform number, the decision threshold and its margin."""
+        z = np.ascontiguousarray(z, np.int32)
+        info = StepInfo()
+        rc = lib().sao_explain_step(self.h, int(rule), _ptr(z), int(k), int(s), int(read) & 0xFFFFFFFF,
+                                    float(beta), float(r_opt), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                    int(instance_id) & 0xFFFFFFFF, C.byref(info))
+        if rc != OK:
+            raise OracleError(rc, "explain_step")
+        return info.as_dict()
 
     def single_step(self, rule, z, k, s, beta, r_opt, n_reads, seed, instance_id=0):
         z = np.ascontiguousarray(z, np.int32)
@@ -199,6 +224,17 @@ class Poly:
         if rc != OK:
             raise OracleError(rc, "single_step")
         return v
+
+
+def state_hash(z) -> int:
+    """Hash of one state (``sao_state_hash``)."""
+    z = np.ascontiguousarray(z, np.int32).reshape(-1)
+    return int(lib().sao_state_hash(int(z.shape[0]), _ptr(z)))
+
+
+def mix64(x: int) -> int:
+    """The state hash's mixing function (``sao_mix64``)."""
+    return int(lib().sao_mix64(int(x) & 0xFFFFFFFFFFFFFFFF))
 
 
 def philox(ctr, key):

@@ -9,8 +9,8 @@
  *  - random numbers: Philox4x32-10, counter (k, s, r, instance), key = seed;
  *  - Metropolis proposal: uniform over the u_k - l_k values other than z_k;
  *  - acceptance: dE <= 0 accepts, otherwise U < exp(-(beta * dE)) with U in [0, 1);
- *  - heat bath: weights exp(-beta (dE_v - min dE)) over all u_k - l_k + 1 values, summed in a
- *    fixed 64-block order (below); first cumulative weight above U * total is chosen;
+ *  - heat bath: weights exp(-beta (dE_v - min dE)) over all u_k - l_k + 1 values, summed one
+ *    value at a time in increasing value order; first cumulative weight above U * total is chosen;
  *  - optimal transition: argmin over the nonzero changes, ties to the smallest new value, with
  *    probability r = s/(S-1); otherwise the Metropolis proposal; Metropolis acceptance;
  *  - variables with l_k = u_k are skipped; zero coefficients are dropped.
@@ -82,6 +82,25 @@ static double uniform53(const uint32_t x[4]) {
     uint64_t bits = ((uint64_t)x[2] << 32) | (uint64_t)x[3];
     return (double)(bits >> 11) * 0x1p-53;
 }
+
+/* State hash for tracing: H(z) = sum over k of mix(k * 2^32 + (uint32)z_k) modulo 2^64, with mix
+ * the 64-bit finaliser of SplitMix64 (Stafford's "variant 13" constants).  A sum is used so that
+ * any partition of the variables gives the same value; the hash only localises the first sweep
+ * at which two runs of the same chain part. */
+static uint64_t mix64(uint64_t x) {
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static uint64_t state_hash(int32_t n, const int32_t *z) {
+    uint64_t h = 0;
+    for (int32_t k = 0; k < n; ++k) h += mix64(((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)z[k]);
+    return h;
+}
+
+uint64_t sao_state_hash(int32_t n, const int32_t *z) { return (n > 0 && z) ? state_hash(n, z) : 0; }
+uint64_t sao_mix64(uint64_t x) { return mix64(x); }
 
 /* ------------------------------------------------------------------------------------------ */
 /* Canonicalisation (Sec. 2: terms with the same index multiset are one term).                 */
@@ -439,54 +458,52 @@ static int64_t metropolis_proposal(uint32_t x1, int64_t lo, int64_t W, int64_t z
     return v;
 }
 
-/* Heat bath (Sec. 3.3.2): P(v) = exp(-beta dE_v) / sum_j exp(-beta dE_j) over all W values
- * including the current one.  Weights are taken relative to the minimum dE (same ratios).
- * Summation order: value j belongs to block b = j / c with c = ceil(W/64); the 64 block sums
- * (left to right inside a block) are combined by an inclusive scan over four rows of 16 blocks:
- * inside every row a Kogge-Stone scan with strides 1, 2, 4, 8; then rows 1 and 3 add the last
- * entry of rows 0 and 2; then rows 2 and 3 add the (new) last entry of row 1.  Value j's
- * cumulative weight is (scan of block b-1) + (running sum inside b). */
+/* Heat bath (Sec. 3.3.2): P(v) = exp(-beta dE_v) / sum_j exp(-beta dE_j) over all W values,
+ * the current one included.  The weights are taken relative to the minimum dE, which leaves the
+ * ratios unchanged and keeps every weight in (0, 1].  The draw inverts the cumulative
+ * distribution in value order: C_v = w_lo + ... + w_v, added one value at a time from the
+ * lower bound up, and the first v with C_v > U * C_hi is chosen (the last value when rounding
+ * puts U * C_hi at or above every C_v). */
 static int64_t heat_bath_choose(chain_ctx *c, int64_t lo, int64_t W, int32_t maxe, int64_t zk,
-                                double beta, double U) {
+                                double beta, double U, sao_step_info *info) {
     const int64_t *a = c->a;
     double *w = c->w;
-    int64_t cpl = (W + 63) / 64;
     int64_t dmin = INT64_MAX;
     for (int64_t j = 0; j < W; ++j) {
         int64_t d = delta_from_coeffs(a, maxe, zk, lo + j);
         if (d < dmin) dmin = d;
     }
+    double total = 0.0;
     for (int64_t j = 0; j < W; ++j) {
         int64_t d = delta_from_coeffs(a, maxe, zk, lo + j);
         w[j] = exp(-(beta * (double)(d - dmin)));
+        total += w[j];
     }
-    double incl[64], tmp[64];
-    for (int b = 0; b < 64; ++b) {
-        double s = 0.0;
-        for (int64_t j = b * cpl; j < (b + 1) * cpl && j < W; ++j) s += w[j];
-        incl[b] = s;
-    }
-    for (int stride = 1; stride < 16; stride *= 2) {
-        memcpy(tmp, incl, sizeof tmp);
-        for (int b = 0; b < 64; ++b)
-            if (b % 16 >= stride) incl[b] = tmp[b] + tmp[b - stride];
-    }
-    double row0 = incl[15], row2 = incl[47];
-    for (int b = 16; b < 32; ++b) incl[b] = incl[b] + row0;
-    for (int b = 48; b < 64; ++b) incl[b] = incl[b] + row2;
-    double rows01 = incl[31];
-    for (int b = 32; b < 64; ++b) incl[b] = incl[b] + rows01;
-    double total = incl[63];
     double thr = U * total;
-    for (int b = 0; b < 64; ++b) {
-        double before = b > 0 ? incl[b - 1] : 0.0;
-        double run = 0.0;
-        for (int64_t j = b * cpl; j < (b + 1) * cpl && j < W; ++j) {
-            run += w[j];
-            if (before + run > thr) return lo + j;
+    double cum = 0.0;
+    int64_t pick = W - 1;
+    for (int64_t j = 0; j < W; ++j) {
+        cum += w[j];
+        if (cum > thr) {
+            pick = j;
+            break;
         }
     }
-    return lo + W - 1; /* rounding put U*total at or above every cumulative weight */
+    if (info) {
+        /* the decision's distance from a flip: the cumulative weight nearest to the threshold */
+        double run = 0.0, best = INFINITY;
+        info->total = total;
+        info->threshold = thr;
+        for (int64_t j = 0; j < W; ++j) {
+            if (j == pick) info->c_prev = run;
+            run += w[j];
+            if (j == pick) info->c_at = run;
+            double gap = fabs(run - thr);
+            if (gap < best) best = gap;
+        }
+        info->margin = total > 0.0 ? best / total : 0.0;
+    }
+    return lo + pick;
 }
 
 /* Heat bath for a variable whose energy difference is linear in the change, dE(v) = a (v - z_k)
@@ -521,7 +538,7 @@ static int64_t heat_bath_closed(int64_t a, int64_t lo, int64_t W, double beta, d
 
 /* Returns 1 if z_k changed; *dE is the energy change applied. */
 static int update_variable(chain_ctx *c, int32_t *z, int32_t k, uint32_t s, uint32_t read,
-                           double beta, double r_opt, int64_t *dE) {
+                           double beta, double r_opt, int64_t *dE, sao_step_info *info) {
     const sao_poly *p = c->p;
     int64_t lo = p->lo[k], W = (int64_t)p->hi[k] - lo + 1;
     *dE = 0;
@@ -548,7 +565,7 @@ static int update_variable(chain_ctx *c, int32_t *z, int32_t k, uint32_t s, uint
         d = delta_from_coeffs(a, maxe, zk, v);
         accept = 1;
     } else if (c->rule == SAO_HEAT_BATH || c->rule == SAO_HEAT_BATH_CLOSED) {
-        v = heat_bath_choose(c, lo, W, maxe, zk, beta, U);
+        v = heat_bath_choose(c, lo, W, maxe, zk, beta, U, info);
         d = delta_from_coeffs(a, maxe, zk, v);
         accept = 1;
     } else {
@@ -569,6 +586,17 @@ static int update_variable(chain_ctx *c, int32_t *z, int32_t k, uint32_t s, uint
         }
         d = delta_from_coeffs(a, maxe, zk, v);
         accept = metropolis_accept(d, beta, U);
+        if (info) info->branch = (double)x[0] * 0x1p-32 < r_opt;
+    }
+    if (info) {
+        info->v = v;
+        info->dE = d;
+        info->accepted = accept && v != zk;
+        info->U = U;
+        if (c->rule == SAO_METROPOLIS || c->rule == SAO_OPT_METROPOLIS) {
+            info->threshold = d <= 0 ? 1.0 : exp(-(beta * (double)d));
+            info->margin = d <= 0 ? INFINITY : fabs(U - info->threshold);
+        }
     }
     if (!accept || v == zk) return 0;
     if (c->cache) cache_apply_move(c, z, k, v);
@@ -593,6 +621,7 @@ typedef struct {
     const uint32_t *read_ids; /* NULL: row i is read i */
     int32_t *z_out;
     int64_t *e_out;
+    uint64_t *hash_out; /* NULL, or (s_end - s_begin) state hashes per read */
     int tid, nthreads;
     int status;
     /* single-step mode */
@@ -662,8 +691,10 @@ static void *anneal_worker(void *arg) {
                            : (j->S > 1 ? (double)s / (double)(j->S - 1) : 0.0);
             for (int32_t k = 0; k < p->n; ++k) { /* index order (Sec. 3.1) */
                 int64_t d;
-                if (update_variable(&c, z, k, (uint32_t)s, r, beta, r_opt, &d)) E += d;
+                if (update_variable(&c, z, k, (uint32_t)s, r, beta, r_opt, &d, NULL)) E += d;
             }
+            if (j->hash_out)
+                j->hash_out[(int64_t)row * (j->s1 - j->s0) + (s - j->s0)] = state_hash(p->n, z);
         }
         if (E != energy(p, z)) {
             j->status = SAO_EINTERNAL;
@@ -693,7 +724,7 @@ static void *single_step_worker(void *arg) {
     int32_t k = j->k_fixed;
     for (int32_t r = j->tid; r < j->n_reads; r += j->nthreads) {
         int64_t d;
-        update_variable(&c, z, k, (uint32_t)j->s_fixed, (uint32_t)r, j->beta_fixed, j->r_fixed, &d);
+        update_variable(&c, z, k, (uint32_t)j->s_fixed, (uint32_t)r, j->beta_fixed, j->r_fixed, &d, NULL);
         j->v_out[r] = z[k];
         z[k] = j->z_fixed[k];
     }
@@ -759,13 +790,14 @@ int sao_anneal(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps
                uint32_t instance_id, double otm_r, int cache_mode, int n_threads,
                const int32_t *z_init, int32_t *z_out, int64_t *e_out) {
     return sao_anneal_reads(p, rule, beta, n_sweeps, s_begin, s_end, n_reads, NULL, seed,
-                            instance_id, otm_r, cache_mode, n_threads, z_init, z_out, e_out);
+                            instance_id, otm_r, cache_mode, n_threads, z_init, z_out, e_out, NULL);
 }
 
 int sao_anneal_reads(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps,
                      int32_t s_begin, int32_t s_end, int32_t n_reads, const uint32_t *read_ids,
                      uint64_t seed, uint32_t instance_id, double otm_r, int cache_mode,
-                     int n_threads, const int32_t *z_init, int32_t *z_out, int64_t *e_out) {
+                     int n_threads, const int32_t *z_init, int32_t *z_out, int64_t *e_out,
+                     uint64_t *hash_out) {
     if (!p || !beta || !z_out || !e_out || n_reads < 1 || n_sweeps < 1) return SAO_EINVAL;
     if (s_begin < 0 || s_end < s_begin || s_end > n_sweeps) return SAO_EINVAL;
     int rc = check_rule(p, rule);
@@ -794,6 +826,7 @@ int sao_anneal_reads(const sao_poly *p, int rule, const double *beta, int32_t n_
     j.read_ids = read_ids;
     j.z_out = z_out;
     j.e_out = e_out;
+    j.hash_out = hash_out;
     return run_jobs(&j, n_threads, anneal_worker);
 }
 
@@ -817,4 +850,28 @@ int sao_single_step(const sao_poly *p, int rule, const int32_t *z, int32_t k, in
     j.r_fixed = r_opt;
     j.v_out = v_out;
     return run_jobs(&j, 0, single_step_worker);
+}
+
+int sao_explain_step(const sao_poly *p, int rule, const int32_t *z, int32_t k, int32_t s,
+                     uint32_t read, double beta, double r_opt, uint64_t seed, uint32_t instance_id,
+                     sao_step_info *out) {
+    if (!p || !z || !out || k < 0 || k >= p->n || s < 0) return SAO_EINVAL;
+    int rc = check_rule(p, rule);
+    if (rc != SAO_OK) return rc;
+    memset(out, 0, sizeof *out);
+    chain_ctx c;
+    rc = ctx_init(&c, p, rule, seed, instance_id, 0);
+    int32_t *zz = (int32_t *)malloc(sizeof(int32_t) * p->n);
+    if (rc != SAO_OK || !zz) {
+        ctx_free(&c);
+        free(zz);
+        return rc != SAO_OK ? rc : SAO_ENOMEM;
+    }
+    memcpy(zz, z, sizeof(int32_t) * p->n);
+    int64_t d;
+    out->v = z[k];
+    update_variable(&c, zz, k, (uint32_t)s, read, beta, r_opt, &d, out);
+    ctx_free(&c);
+    free(zz);
+    return SAO_OK;
 }

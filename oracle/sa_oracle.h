@@ -81,12 +81,22 @@ int sao_anneal(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps
                uint32_t instance_id, double otm_r, int cache_mode, int n_threads,
                const int32_t *z_init, int32_t *z_out, int64_t *e_out);
 
-/* As sao_anneal, but output row i is the chain with read id read_ids[i] (so a sample of the
- * reads of a large run can be reproduced one by one). */
+/* As sao_anneal, but output row i is the chain with read id read_ids[i] (read_ids NULL: read i),
+ * so a sample of the reads of a large run can be reproduced one by one.  hash_out, when not
+ * NULL, receives (s_end - s_begin) state hashes per read (row-major): the hash of the state
+ * after each sweep, as sao_state_hash defines it. */
 int sao_anneal_reads(const sao_poly *p, int rule, const double *beta, int32_t n_sweeps,
                      int32_t s_begin, int32_t s_end, int32_t n_reads, const uint32_t *read_ids,
                      uint64_t seed, uint32_t instance_id, double otm_r, int cache_mode,
-                     int n_threads, const int32_t *z_init, int32_t *z_out, int64_t *e_out);
+                     int n_threads, const int32_t *z_init, int32_t *z_out, int64_t *e_out,
+                     uint64_t *hash_out);
+
+/* Hash of a state: sum over k of mix(k * 2^32 + (uint32_t)z[k]) modulo 2^64, where mix is the
+ * 64-bit finaliser of SplitMix64.  Order-independent (a sum), so that runs partitioned in any
+ * way can report it; used only to find the first sweep at which two runs of a chain part. */
+uint64_t sao_state_hash(int32_t n, const int32_t *z);
+/* The mixing function of the state hash (exported so that tests can pin it). */
+uint64_t sao_mix64(uint64_t x);
 
 /* For each read r in [0, n_reads): from the state z, perform the single update of variable
  * k at sweep index s with inverse temperature beta and OTM parameter r_opt, and report the
@@ -94,6 +104,26 @@ int sao_anneal_reads(const sao_poly *p, int rule, const double *beta, int32_t n_
 int sao_single_step(const sao_poly *p, int rule, const int32_t *z, int32_t k, int32_t s,
                     double beta, double r_opt, int32_t n_reads, uint64_t seed,
                     uint32_t instance_id, int32_t *v_out);
+
+/* What one update computed, for explaining a parting of two runs of a chain. */
+typedef struct {
+    int64_t v;          /* value drawn (heat bath) or proposed (Metropolis, OTM) */
+    int64_t dE;         /* energy change of moving z_k to v */
+    int32_t accepted;   /* 1 if z_k moved to v */
+    int32_t branch;     /* OTM: 1 if the optimal-transition branch was taken */
+    double U;           /* the uniform number of the update */
+    double threshold;   /* Metropolis, OTM: exp(-beta dE) (1 for dE <= 0); heat bath: U * total */
+    double total;       /* heat bath: sum of the weights exp(-beta (dE_v - min dE)) */
+    double c_prev;      /* heat bath: cumulative weight before the drawn value */
+    double c_at;        /* heat bath: cumulative weight at the drawn value */
+    double margin;      /* distance of the decision from a flip: heat bath min_v |C_v - U total| / total,
+                           Metropolis and OTM |U - threshold| (infinite when dE <= 0) */
+} sao_step_info;
+
+/* Recomputes the update of variable k at sweep s of read `read` from state z and reports it. */
+int sao_explain_step(const sao_poly *p, int rule, const int32_t *z, int32_t k, int32_t s,
+                     uint32_t read, double beta, double r_opt, uint64_t seed, uint32_t instance_id,
+                     sao_step_info *out);
 
 /* Hardware threads the oracle would use for n_threads <= 0. */
 int sao_default_threads(void);

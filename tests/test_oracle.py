@@ -624,3 +624,139 @@ def test_heat_bath_single_step_wide_ranges(lo, hi):
         dE = brute.deltas(p, z, 0)
         c = _one_step_distribution(P, oracle.HEAT_BATH, z, 0, beta, 0.0, 80_000)
         _assert_matches(c, _heat_bath_kernel(dE, beta))
+
+
+# ---------------------------------------------------------------------------------------------
+# Heat bath: the draw is the inverse of the cumulative distribution in value order
+# ---------------------------------------------------------------------------------------------
+
+def test_heat_bath_enumeration_is_the_exact_inverse_cdf():
+    # Sec. 3.3.2: P(v) = exp(-beta dE_v) / sum_j exp(-beta dE_j).  The oracle draws
+    # v = min{v : CDF(v) > U} with the CDF accumulated from the lower bound up; the CDF here is
+    # evaluated at 40 digits from brute-force energy differences.  A draw may differ only where U
+    # lies within rounding of a CDF step.  Squares make dE non-linear, so every weight is a
+    # different exponential.
+    import mpmath
+    mpmath.mp.dps = 40
+    seed, s = 4321, 7
+    cases = [([(2, [0, 0]), (-3, [0, 1]), (5, [0])], -10, 10, 0.05),
+             ([(-1, [0, 0]), (4, [0, 1]), (-7, [0])], 0, 40, 0.01),
+             ([(1, [0, 0, 0]), (-30, [0, 0]), (2, [0, 1])], -20, 20, 0.002),
+             ([(3, [0, 0]), (1, [0, 1])], -50, 50, 0.0004)]
+    for terms, lo, hi, beta in cases:
+        p = I.from_terms(2, terms, [lo, -3], [hi, 3])
+        z = np.array([(lo + hi) // 2 + 1, 2], np.int32)
+        P = oracle.Poly(p)
+        dE = brute.deltas(p, z, 0)
+        vals = sorted(dE)
+        n = 3000
+        v = P.single_step(oracle.HEAT_BATH, z, 0, s, beta, 0.0, n, seed=seed)
+        w = [mpmath.exp(-mpmath.mpf(beta) * dE[x]) for x in vals]
+        tot = mpmath.fsum(w)
+        cdf, run = [], mpmath.mpf(0)
+        for x in w:
+            run += x
+            cdf.append(run / tot)
+        checked = 0
+        for r in range(n):
+            x = oracle.philox([0, s, r, 0], [seed & 0xFFFFFFFF, seed >> 32])
+            U = mpmath.mpf(int(((int(x[2]) << 32) | int(x[3])) >> 11)) / 2 ** 53
+            i = next(j for j in range(len(vals)) if cdf[j] > U)
+            if min(abs(cdf[j] - U) for j in (i - 1, i) if j >= 0) < 1e-12:
+                continue
+            assert int(v[r]) == vals[i], (terms, lo, hi, beta, r)
+            checked += 1
+        assert checked > 0.99 * n
+
+
+# ---------------------------------------------------------------------------------------------
+# Optimal transition: the default r_s = s / (S - 1) of Sec. 3.3.3
+# ---------------------------------------------------------------------------------------------
+
+def test_otm_default_r_is_s_over_S_minus_1():
+    # With the default schedule of r, sweep 0 is Metropolis (r = 0), sweep S-1 is the fixed r = 1
+    # (greedy proposal, pinned against brute-force argmin above) and the middle sweep of an odd
+    # S is r = 1/2.  Sweeps are run one at a time from the same start state; the draws depend
+    # only on (variable, sweep, read), so each comparison is exact.
+    r = rng(720)
+    p = I.random_huio(30, 200, [2, 3, 4], -6, 9, 5, r)
+    P = oracle.Poly(p)
+    S = 11
+    beta, _, _ = P.schedule(S)
+    z0, _ = P.anneal(oracle.METROPOLIS, beta, 64, seed=5, s_end=3)
+    for s, fixed in [(0, 0.0), (5, 0.5), (10, 1.0)]:
+        za, ea = P.anneal(oracle.OPT_METROPOLIS, beta, 64, seed=5, s_begin=s, s_end=s + 1, z_init=z0)
+        zb, eb = P.anneal(oracle.OPT_METROPOLIS, beta, 64, seed=5, s_begin=s, s_end=s + 1, z_init=z0,
+                          otm_r=fixed)
+        assert np.array_equal(za, zb) and np.array_equal(ea, eb), s
+        if s == 0:
+            zm, em = P.anneal(oracle.METROPOLIS, beta, 64, seed=5, s_begin=0, s_end=1, z_init=z0)
+            assert np.array_equal(za, zm) and np.array_equal(ea, em)
+    # a wrong schedule (r = s / S, or the reverse) would differ at an end of the schedule
+    zc, _ = P.anneal(oracle.OPT_METROPOLIS, beta, 64, seed=5, s_begin=10, s_end=11, z_init=z0,
+                     otm_r=10 / 11)
+    zd, _ = P.anneal(oracle.OPT_METROPOLIS, beta, 64, seed=5, s_begin=10, s_end=11, z_init=z0)
+    assert not np.array_equal(zc, zd)
+
+
+# ---------------------------------------------------------------------------------------------
+# Tracing: per-sweep state hashes and the explanation of one update
+# ---------------------------------------------------------------------------------------------
+
+def test_state_hash_mixer_is_splitmix64():
+    # published SplitMix64 outputs from state 0: the finaliser of state k * 0x9E3779B97F4A7C15
+    golden = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for i, w in enumerate(want, start=1):
+        assert oracle.mix64((i * golden) & 0xFFFFFFFFFFFFFFFF) == w
+    # the state hash is the sum of the mixed (index, value) words, modulo 2^64
+    z = np.array([3, -7, 0, 2_000_000_000], np.int32)
+    words = [(k << 32) | (int(v) & 0xFFFFFFFF) for k, v in enumerate(z)]
+    assert oracle.state_hash(z) == sum(oracle.mix64(w) for w in words) % 2 ** 64
+
+
+@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS,
+                                  oracle.HEAT_BATH_CLOSED])
+def test_traced_hashes_follow_the_state(rule):
+    r = rng(900 + rule)
+    p = I.tiny_random(r, 12, -6, 6, 60, 3)
+    P = oracle.Poly(p)
+    beta, _, _ = P.schedule(20)
+    z, e, h = P.anneal(rule, beta, 5, seed=13, trace=True)
+    assert h.shape == (5, 20)
+    for i in range(5):
+        assert int(h[i, -1]) == oracle.state_hash(z[i])
+    # a run resumed at sweep 8 reports the hashes of the uninterrupted run
+    z1, _ = P.anneal(rule, beta, 5, seed=13, s_end=8)
+    z2, e2, h2 = P.anneal(rule, beta, 5, seed=13, s_begin=8, z_init=z1, trace=True)
+    assert np.array_equal(h2, h[:, 8:]) and np.array_equal(z2, z)
+    # each hash is the state after that sweep
+    for s in (0, 7, 13):
+        zs, _ = P.anneal(rule, beta, 5, seed=13, s_end=s + 1)
+        assert all(int(h[i, s]) == oracle.state_hash(zs[i]) for i in range(5))
+
+
+@pytest.mark.parametrize("rule", [oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS])
+def test_explain_step_reproduces_the_run(rule):
+    # replaying sweep s one variable at a time with explain_step gives the run's state after s
+    r = rng(910 + rule)
+    p = I.tiny_random(r, 10, -5, 7, 50, 3)
+    P = oracle.Poly(p)
+    beta, _, _ = P.schedule(12)
+    s = 6
+    zb, eb = P.anneal(rule, beta, 3, seed=17, s_end=s)
+    za, ea = P.anneal(rule, beta, 3, seed=17, s_end=s + 1)
+    for i in range(3):
+        z = zb[i].copy()
+        E = int(eb[i])
+        for k in range(p.n_vars):
+            info = P.explain_step(rule, z, k, s, i, beta[s], s / 11, seed=17)
+            if info["accepted"]:
+                assert info["dE"] == brute.energy_raw(p, np.where(np.arange(p.n_vars) == k, info["v"], z)) - \
+                    brute.energy_raw(p, z)
+                z[k] = info["v"]
+                E += info["dE"]
+            if rule == oracle.HEAT_BATH and p.lower[k] < p.upper[k]:
+                assert info["c_prev"] <= info["threshold"] < info["c_at"] or info["v"] == p.upper[k]
+                assert 0.0 <= info["margin"] <= 1.0
+        assert np.array_equal(z, za[i]) and E == int(ea[i])
