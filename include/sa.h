@@ -108,6 +108,22 @@ typedef struct {
     int32_t otm_enum_max;       /* optimal transition: ranges of at most this many values take the
                                    argmin by enumeration, wider ones from the stationary points of
                                    the degree-<=4 energy difference (same result); 0: 2048 */
+    uint64_t *trace_hashes;     /* NULL: no tracing (default).  Otherwise n_reads x (sweep_end -
+                                   sweep_begin) words, row-major (read, sweep), host or device memory
+                                   as device_buffers says: the hash of each read's state after each
+                                   sweep of the run, sum_k mix(k * 2^32 + (uint32_t)z_k) modulo 2^64
+                                   with mix the 64-bit finaliser of SplitMix64.  Two runs of a chain
+                                   part at the first sweep whose hashes differ.  Plain launches only
+                                   (batches and the server do not trace). */
+    int32_t lanes_per_update;   /* heat bath: lanes that carry one update.  0: automatic.  64: one
+                                   wavefront per update (the candidate values split over its lanes,
+                                   the waves of a replica over schedule windows, as waves_per_replica
+                                   says).  4: one quad of lanes per update, the 16 quads of each of a
+                                   workgroup's 8 waves over the dependency levels of the sweep
+                                   (sparse problems, exponents <= 2, ranges of at most 128 values,
+                                   waves_per_replica 0; SA_EINVAL otherwise).  Both follow the
+                                   sequential sweep; they differ only in the order in which heat-bath
+                                   weights are added (a quad adds them in value order). */
 } sa_opts;
 
 void sa_opts_default(sa_opts *opts);
@@ -154,6 +170,8 @@ typedef struct {
     int32_t kernel_variant;     /* internal id of the instantiated kernel */
     int32_t waves_per_replica;  /* G: wavefronts cooperating on one replica */
     int32_t n_windows;          /* windows per sweep in the schedule (N for G = 1 without fixed vars) */
+    int32_t lanes_per_update;   /* 64, or 4 for the quad kernel */
+    int32_t n_levels;           /* quad kernel: dependency levels per sweep (0 otherwise) */
 } sa_launch_info;
 int32_t sa_plan_last_launch(const sa_plan *plan, sa_launch_info *info);
 

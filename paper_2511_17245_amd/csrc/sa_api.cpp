@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -26,6 +27,8 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(SA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+void clear_error() { g_last_error.clear(); }
+
 }  // namespace sa
 
 using sa::align256;
@@ -35,63 +38,91 @@ using sa::hip_fail;
 namespace {
 
 int upload_packed(const sa::Packed &pk, sa_plan *plan) {
-    struct Part {
-        const void *src;
-        size_t bytes;
-        size_t extra;   // zero bytes reserved after the copied ones
-        size_t off;
+    const sa::PackedLayout L = sa::packed_layout(pk);
+    hipError_t e = hipMalloc(&plan->arena.base, L.total);
+    if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
+    plan->arena.bytes = L.total;
+    std::vector<char> staging(L.total, 0);
+    sa::stage_packed(pk, L, staging.data());
+    e = hipMemcpy(plan->arena.base, staging.data(), L.total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan)");
+    sa::bind_packed(pk, L, (char *)plan->arena.base, plan->dp);
+    return SA_OK;
+}
+
+}  // namespace
+
+namespace sa {
+
+namespace {
+// the parts of a packed instance in their device order
+std::vector<std::pair<const void *, size_t>> packed_parts(const Packed &pk) {
+    return {
+        {pk.var.data(), pk.var.size() * sizeof(VarRec)},
+        {pk.emask.data(), pk.emask.size() * sizeof(uint32_t)},
+        {pk.inc.data(), pk.inc.size() * sizeof(IncRec)},
+        {pk.inc_coef.data(), pk.inc_coef.size() * sizeof(int64_t)},
+        {pk.overflow.data(), pk.overflow.size() * sizeof(int32_t)},
+        {pk.t_off.data(), pk.t_off.size() * sizeof(int32_t)},
+        {pk.t_var.data(), pk.t_var.size() * sizeof(int32_t)},
+        {pk.t_coef.data(), pk.t_coef.size() * sizeof(int64_t)},
+        {pk.jbytes == 1 ? (const void *)pk.jd8.data() : (const void *)pk.jd32.data(),
+         pk.jbytes == 1 ? pk.jd8.size() : pk.jd32.size() * sizeof(int32_t)},
+        {pk.h.data(), pk.h.size() * sizeof(int64_t)},
+        {pk.d.data(), pk.d.size() * sizeof(int64_t)},
     };
+}
+}  // namespace
+
+PackedLayout packed_layout(const Packed &pk) {
     // the incidence records and their coefficients are followed by one zero record, which lanes
     // past the end of a row read
-    std::vector<Part> parts = {
-        {pk.var.data(), pk.var.size() * sizeof(sa::VarRec), 0, 0},
-        {pk.emask.data(), pk.emask.size() * sizeof(uint32_t), 0, 0},
-        {pk.inc.data(), pk.inc.size() * sizeof(sa::IncRec), sizeof(sa::IncRec), 0},
-        {pk.inc_coef.data(), pk.inc_coef.size() * sizeof(int64_t), sizeof(int64_t), 0},
-        {pk.overflow.data(), pk.overflow.size() * sizeof(int32_t), 0, 0},
-        {pk.t_off.data(), pk.t_off.size() * sizeof(int32_t), 0, 0},
-        {pk.t_var.data(), pk.t_var.size() * sizeof(int32_t), 0, 0},
-        {pk.t_coef.data(), pk.t_coef.size() * sizeof(int64_t), 0, 0},
-        {pk.jbytes == 1 ? (const void *)pk.jd8.data() : (const void *)pk.jd32.data(),
-         pk.jbytes == 1 ? pk.jd8.size() : pk.jd32.size() * sizeof(int32_t), 0, 0},
-        {pk.h.data(), pk.h.size() * sizeof(int64_t), 0, 0},
-        {pk.d.data(), pk.d.size() * sizeof(int64_t), 0, 0},
-    };
+    const auto parts = packed_parts(pk);
+    const size_t extra[PackedLayout::kParts] = {0, 0, sizeof(IncRec), sizeof(int64_t), 0, 0, 0, 0, 0, 0, 0};
+    PackedLayout L;
     size_t total = 0;
-    for (auto &p : parts) {
-        p.off = total;
-        total += align256(p.bytes + p.extra > 0 ? p.bytes + p.extra : 1);
+    for (int i = 0; i < PackedLayout::kParts; ++i) {
+        L.off[i] = total;
+        const size_t b = parts[(size_t)i].second + extra[i];
+        total += align256(b > 0 ? b : 1);
     }
-    hipError_t e = hipMalloc(&plan->arena.base, total);
-    if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
-    plan->arena.bytes = total;
-    std::vector<char> staging(total, 0);
-    for (auto &p : parts)
-        if (p.bytes) std::memcpy(staging.data() + p.off, p.src, p.bytes);
-    e = hipMemcpy(plan->arena.base, staging.data(), total, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan)");
-    char *b = (char *)plan->arena.base;
-    sa::DevProblem &d = plan->dp;
+    L.total = total;
+    return L;
+}
+
+void stage_packed(const Packed &pk, const PackedLayout &L, char *image) {
+    const auto parts = packed_parts(pk);
+    for (int i = 0; i < PackedLayout::kParts; ++i) {
+        const size_t end = i + 1 < PackedLayout::kParts ? L.off[i + 1] : L.total;
+        std::memset(image + L.off[i], 0, end - L.off[i]);
+        if (parts[(size_t)i].second) std::memcpy(image + L.off[i], parts[(size_t)i].first, parts[(size_t)i].second);
+    }
+}
+
+void bind_packed(const Packed &pk, const PackedLayout &L, char *b, DevProblem &d) {
     d.n = pk.n;
     d.n_terms = pk.n_terms;
-    d.var = (const sa::VarRec *)(b + parts[0].off);
-    d.emask = (const uint32_t *)(b + parts[1].off);
-    d.inc = (const sa::IncRec *)(b + parts[2].off);
-    d.inc_coef = (const int64_t *)(b + parts[3].off);
-    d.overflow = (const int32_t *)(b + parts[4].off);
-    d.t_off = (const int32_t *)(b + parts[5].off);
-    d.t_var = (const int32_t *)(b + parts[6].off);
-    d.t_coef = (const int64_t *)(b + parts[7].off);
+    d.var = (const VarRec *)(b + L.off[0]);
+    d.emask = (const uint32_t *)(b + L.off[1]);
+    d.inc = (const IncRec *)(b + L.off[2]);
+    d.inc_coef = (const int64_t *)(b + L.off[3]);
+    d.overflow = (const int32_t *)(b + L.off[4]);
+    d.t_off = (const int32_t *)(b + L.off[5]);
+    d.t_var = (const int32_t *)(b + L.off[6]);
+    d.t_coef = (const int64_t *)(b + L.off[7]);
     d.max_other = pk.max_other;
     d.inc_pad = (int32_t)pk.inc.size();
     d.dense = pk.dense ? 1 : 0;
     d.jbytes = pk.jbytes;
     d.row_stride = pk.row_stride;
-    d.jd = (const void *)(b + parts[8].off);
-    d.h = (const int64_t *)(b + parts[9].off);
-    d.d = (const int64_t *)(b + parts[10].off);
-    return SA_OK;
+    d.jd = (const void *)(b + L.off[8]);
+    d.h = (const int64_t *)(b + L.off[9]);
+    d.d = (const int64_t *)(b + L.off[10]);
 }
+
+}  // namespace sa
+
+namespace sa {
 
 int check_rule_support(int rule, int32_t max_exp) {
     if (rule < SA_METROPOLIS || rule > SA_HEAT_BATH_CLOSED) return fail(SA_EINVAL, "unknown rule");
@@ -104,7 +135,29 @@ int check_rule_support(int rule, int32_t max_exp) {
     return SA_OK;
 }
 
-}  // namespace
+// Waves per replica.  The sweep is latency-bound (one dependent chain per replica), so the widest
+// window G in {16, 8, 4, 2} is taken whose waves stay busy (mean window size >= 0.6 G), whose
+// shared state fits in LDS and whose n_reads x G waves are all resident at once; otherwise G = 1.
+// The annealing variants use 84 to 128 VGPRs, which leaves room for 4 waves per SIMD: a wider G
+// would run the replicas in two rounds (measured slower, e.g. 8 against 4 waves per replica for
+// 1024 replicas of the N = 2000 HUIO problem: 573 against 508 ms).
+int pick_waves_per_replica(int32_t n, int32_t n_reads, int device,
+                           const std::function<bool(int, int32_t &, int32_t &)> &windows) {
+    int cus = 256, max_lds = 65536;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    const int64_t max_waves = (int64_t)cus * 4 * 4;
+    for (int G = 16; G > 1; G /= 2) {
+        if ((int64_t)n_reads * G > max_waves) continue;
+        if (shared_state_bytes(n, G) > max_lds) continue;
+        int32_t n_win = 0, n_active = 0;
+        if (!windows(G, n_win, n_active) || n_win == 0) continue;
+        if ((double)n_active / (double)n_win >= 0.6 * G) return G;
+    }
+    return 1;
+}
+
+}  // namespace sa
 
 namespace sa {
 
@@ -213,6 +266,65 @@ int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out) {
     return SA_OK;
 }
 
+int get_levels(sa_plan *plan, sa_plan::Levels **out) {
+    std::lock_guard<std::mutex> lk(plan->sched_mu);
+    sa_plan::Levels &lv = plan->levels;
+    if (lv.n_levels < 0) {
+        std::vector<int32_t> start;
+        std::vector<SchedRec> slots;
+        const int32_t nl = build_levels(plan->packed, start, slots);
+        const size_t sb = align256(start.size() * sizeof(int32_t));
+        const size_t bytes = sb + std::max<size_t>(slots.size(), 1) * sizeof(SchedRec);
+        hipError_t e = hipMalloc(&lv.dev, bytes);
+        if (e != hipSuccess) {
+            lv.dev = nullptr;
+            return fail(SA_ENOMEM, std::string("hipMalloc(levels): ") + hipGetErrorString(e));
+        }
+        std::vector<char> img(bytes, 0);
+        std::memcpy(img.data(), start.data(), start.size() * sizeof(int32_t));
+        if (!slots.empty()) std::memcpy(img.data() + sb, slots.data(), slots.size() * sizeof(SchedRec));
+        e = hipMemcpy(lv.dev, img.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(levels)");
+        lv.start = (const int32_t *)lv.dev;
+        lv.slots = (const SchedRec *)((char *)lv.dev + sb);
+        lv.n_slots = (int32_t)slots.size();
+        lv.uniform_width = uniform_width(slots);
+        lv.n_levels = nl;
+    }
+    *out = &lv;
+    return SA_OK;
+}
+
+int32_t uniform_width(const std::vector<SchedRec> &slots) {
+    if (slots.empty()) return 0;
+    for (const auto &sl : slots)
+        if (sl.width != slots[0].width) return 0;
+    return slots[0].width;
+}
+
+bool quad_eligible(int rule, const Packed &pk, int device) {
+    if (rule != SA_HEAT_BATH && rule != SA_HEAT_BATH_CLOSED) return false;
+    if (pk.dense || pk.max_exp > 2 || pk.max_width > 4 * kQuadMaxR) return false;
+    int max_lds = 65536;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    return shared_state_bytes(pk.n, kQuadWaves) <= max_lds;
+}
+
+int choose_lanes(int requested, int waves_per_replica, bool eligible, int32_t n_levels, int32_t n_slots) {
+    if (requested != 0 && requested != 4 && requested != 64)
+        return fail(SA_EINVAL, "lanes_per_update must be 0, 4 or 64"), -1;
+    if (requested == 64) return 64;
+    if (requested == 4) {
+        if (!eligible || waves_per_replica != 0)
+            return fail(SA_EINVAL, "lanes_per_update = 4 needs the heat bath on a sparse problem with exponents "
+                                   "<= 2, ranges of at most 128 values, its state in LDS and waves_per_replica = 0"),
+                   -1;
+        return 4;
+    }
+    if (!eligible || waves_per_replica != 0 || n_levels <= 0) return 64;
+    return (int64_t)n_slots >= 64 * (int64_t)n_levels ? 4 : 64;
+}
+
 int reg_chunk_class(int32_t max_width) {
     const int64_t chunk = ((int64_t)max_width + 63) / 64;
     return chunk <= 1 ? 1 : chunk <= 2 ? 2 : chunk <= 8 ? 8 : chunk <= kHeatBathRegChunk ? 32 : 0;
@@ -226,25 +338,14 @@ using sa::get_schedule;
 using sa::stage_beta;
 using sa::resolve_schedule;
 
-// Waves per replica.  The sweep is latency-bound (one dependent chain per replica), so the widest
-// window G in {16, 8, 4, 2} is taken whose waves stay busy (mean window size >= 0.6 G), whose
-// shared state fits in LDS and whose n_reads x G waves are all resident at once; otherwise G = 1.
-// The annealing variants use 84 to 128 VGPRs, which leaves room for 4 waves per SIMD: a wider G
-// would run the replicas in two rounds (measured slower, e.g. 8 against 4 waves per replica for
-// 1024 replicas of the N = 2000 HUIO problem: 573 against 508 ms).
 int auto_waves_per_replica(sa_plan *plan, int32_t n_reads, int device) {
-    int cus = 256, max_lds = 65536;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    const int64_t max_waves = (int64_t)cus * 4 * 4;
-    for (int G = 16; G > 1; G /= 2) {
-        if ((int64_t)n_reads * G > max_waves) continue;
-        if (sa::shared_state_bytes(plan->dp.n, G) > max_lds) continue;
+    return sa::pick_waves_per_replica(plan->dp.n, n_reads, device, [&](int G, int32_t &n_win, int32_t &n_active) {
         sa_plan::Sched *sc = nullptr;
-        if (get_schedule(plan, G, &sc) != SA_OK || sc->n_win == 0) continue;
-        if ((double)sc->n_active / (double)sc->n_win >= 0.6 * G) return G;
-    }
-    return 1;
+        if (get_schedule(plan, G, &sc) != SA_OK) return false;
+        n_win = sc->n_win;
+        n_active = sc->n_active;
+        return true;
+    });
 }
 
 int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t seed,
@@ -281,24 +382,39 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
 
     const size_t zbytes = (size_t)n_reads * (size_t)n * sizeof(int32_t);
     const size_t ebytes = (size_t)n_reads * sizeof(int64_t);
+    const int32_t n_traced = s1 - s0;
+    const size_t tbytes = opts.trace_hashes ? (size_t)n_reads * (size_t)n_traced * sizeof(uint64_t) : 0;
     int32_t *z_dev = out_states;
     int64_t *e_dev = out_energies;
+    uint64_t *t_dev = opts.trace_hashes;
     const int32_t *zi_dev = opts.init_states;
     void *tmp = nullptr;
     if (!opts.device_buffers) {
-        size_t need = align256(zbytes) + align256(ebytes) + (opts.init_states ? align256(zbytes) : 0);
+        size_t need = align256(zbytes) + align256(ebytes) + (opts.init_states ? align256(zbytes) : 0) +
+                      align256(tbytes);
         e = hipMalloc(&tmp, need);
         if (e != hipSuccess) return fail(SA_ENOMEM, std::string("hipMalloc(run): ") + hipGetErrorString(e));
         z_dev = (int32_t *)tmp;
         e_dev = (int64_t *)((char *)tmp + align256(zbytes));
+        size_t off = align256(zbytes) + align256(ebytes);
         if (opts.init_states) {
-            int32_t *zi = (int32_t *)((char *)tmp + align256(zbytes) + align256(ebytes));
+            int32_t *zi = (int32_t *)((char *)tmp + off);
+            off += align256(zbytes);
             e = hipMemcpyAsync(zi, opts.init_states, zbytes, hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) {
                 (void)hipFree(tmp);
                 return hip_fail(e, "hipMemcpyAsync(init)");
             }
             zi_dev = zi;
+        }
+        if (opts.trace_hashes) t_dev = (uint64_t *)((char *)tmp + off);
+    }
+    if (t_dev) {
+        std::string zerr;
+        rc = sa::launch_zero_u64(t_dev, (int64_t)n_reads * n_traced, stream, zerr);
+        if (rc != SA_OK) {
+            if (tmp) (void)hipFree(tmp);
+            return fail(rc, zerr);
         }
     }
     sa::AnnealArgs a{};
@@ -320,41 +436,100 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
     a.z_init = zi_dev;
     a.z_out = z_dev;
     a.e_out = e_dev;
+    a.trace = t_dev;
     int G = opts.waves_per_replica;
     if (G != 0 && G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
         if (tmp) (void)hipFree(tmp);
         return fail(SA_EINVAL, "waves_per_replica must be 0, 1, 2, 4, 8 or 16");
     }
-    if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
-    sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
-                                            plan->info.max_exponent, plan->device, G, plan->narrow_ok,
-                                            a.otm_enum_max, plan->packed.dense);
-    sa_plan::Sched *sc = nullptr;
-    rc = get_schedule(plan, lc.win_waves, &sc);
-    if (rc != SA_OK) {
-        if (tmp) (void)hipFree(tmp);
-        return rc;
+    const bool eligible = sa::quad_eligible(plan->rule, plan->packed, plan->device);
+    sa_plan::Levels *lv = nullptr;
+    if (eligible && G == 0 && opts.lanes_per_update != 64) {
+        rc = sa::get_levels(plan, &lv);
+        if (rc != SA_OK) {
+            if (tmp) (void)hipFree(tmp);
+            return rc;
+        }
     }
-    a.sched = sc->dev;
-    a.n_win = sc->n_win;
-    a.win_waves = lc.win_waves;
-    a.waves_per_group = lc.waves_per_group;
-    std::string err;
-    rc = sa::launch_anneal(plan->rule, a, lc, stream, err);
-    if (rc != SA_OK) {
+    const int lanes = sa::choose_lanes(opts.lanes_per_update, G, eligible, lv ? lv->n_levels : 0,
+                                       lv ? lv->n_slots : 0);
+    if (lanes < 0) {
         if (tmp) (void)hipFree(tmp);
-        return fail(rc, err);
+        return SA_EINVAL;
     }
-    plan->last.waves_per_group = lc.waves_per_group;
-    plan->last.groups = lc.groups;
-    plan->last.lds_bytes = lc.lds_bytes;
-    plan->last.state_in_lds = lc.state_in_lds ? 1 : 0;
-    plan->last.kernel_variant = lc.variant;
-    plan->last.waves_per_replica = lc.win_waves;
-    plan->last.n_windows = sc->n_win;
+    if (lanes == 4) {
+        sa::QuadArgs q{};
+        q.P = plan->dp;
+        q.beta = plan->beta_dev;
+        q.n_sweeps = S;
+        q.s_begin = s0;
+        q.s_end = s1;
+        q.n_reads = n_reads;
+        q.key0 = a.key0;
+        q.key1 = a.key1;
+        q.instance_id = a.instance_id;
+        q.level_start = lv->start;
+        q.slots = lv->slots;
+        q.n_levels = lv->n_levels;
+        q.uniform_width = lv->uniform_width;
+        q.z_init = zi_dev;
+        q.z_out = z_dev;
+        q.e_out = e_dev;
+        q.trace = t_dev;
+        std::string err;
+        rc = sa::launch_quad(plan->rule, q, plan->info.max_width, plan->info.max_exponent,
+                             plan->narrow_ok, stream, err);
+        if (rc == SA_OK && t_dev) rc = sa::launch_trace_prefix(t_dev, n_reads, n_traced, stream, err);
+        if (rc != SA_OK) {
+            if (tmp) (void)hipFree(tmp);
+            return fail(rc, err);
+        }
+        plan->last = sa_launch_info{};
+        plan->last.waves_per_group = sa::kQuadWaves;
+        plan->last.groups = n_reads;
+        plan->last.lds_bytes = (int32_t)sa::shared_state_bytes(n, sa::kQuadWaves);
+        plan->last.state_in_lds = 1;
+        plan->last.kernel_variant = 2000000 + plan->rule * 100000;
+        plan->last.waves_per_replica = sa::kQuadWaves;
+        plan->last.lanes_per_update = 4;
+        plan->last.n_levels = lv->n_levels;
+    } else {
+        if (G == 0) G = auto_waves_per_replica(plan, n_reads, plan->device);
+        sa::LaunchChoice lc = sa::choose_launch(plan->rule, n, n_reads, plan->info.max_width,
+                                                plan->info.max_exponent, plan->device, G, plan->narrow_ok,
+                                                a.otm_enum_max, plan->packed.dense);
+        sa_plan::Sched *sc = nullptr;
+        rc = get_schedule(plan, lc.win_waves, &sc);
+        if (rc != SA_OK) {
+            if (tmp) (void)hipFree(tmp);
+            return rc;
+        }
+        a.sched = sc->dev;
+        a.n_win = sc->n_win;
+        a.win_waves = lc.win_waves;
+        a.waves_per_group = lc.waves_per_group;
+        std::string err;
+        rc = sa::launch_anneal(plan->rule, a, lc, stream, err);
+        if (rc == SA_OK && t_dev) rc = sa::launch_trace_prefix(t_dev, n_reads, n_traced, stream, err);
+        if (rc != SA_OK) {
+            if (tmp) (void)hipFree(tmp);
+            return fail(rc, err);
+        }
+        plan->last.waves_per_group = lc.waves_per_group;
+        plan->last.groups = lc.groups;
+        plan->last.lds_bytes = lc.lds_bytes;
+        plan->last.state_in_lds = lc.state_in_lds ? 1 : 0;
+        plan->last.kernel_variant = lc.variant;
+        plan->last.waves_per_replica = lc.win_waves;
+        plan->last.n_windows = sc->n_win;
+        plan->last.lanes_per_update = 64;
+        plan->last.n_levels = 0;
+    }
     if (!opts.device_buffers) {
         e = hipMemcpyAsync(out_states, z_dev, zbytes, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(out_energies, e_dev, ebytes, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && tbytes)
+            e = hipMemcpyAsync(opts.trace_hashes, t_dev, tbytes, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         (void)hipFree(tmp);
         if (e != hipSuccess) return hip_fail(e, "annealing run");

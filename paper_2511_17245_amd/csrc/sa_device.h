@@ -174,6 +174,18 @@ __device__ __forceinline__ Acc upow(Acc x, int e) {
     return r;
 }
 
+// State hash for tracing: the hash of z is sum_k mix(k 2^32 + (uint32)z_k) modulo 2^64, with mix the
+// 64-bit finaliser of SplitMix64 (Stafford's variant 13).  Being a sum, it is kept up to date from
+// the accepted moves alone, whichever wave makes them.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ uint64_t hash_word(int32_t k, int64_t v) {
+    return mix64(((uint64_t)(uint32_t)k << 32) | (uint64_t)(uint32_t)(int32_t)v);
+}
+
 // J_t times the product of the term's other factors, for one incidence record of the row being
 // visited.  Sets e to the exponent of the visited variable in the term.  A zero record (meta = 0,
 // coef = 0) contributes nothing, so lanes beyond the row hold one.
@@ -838,6 +850,7 @@ struct ReplicaCtx {
     int32_t n_win;
     bool shared;            // the replica's waves cooperate (barrier after each window)
     bool active;            // false: an idle team that only keeps the workgroup's barriers
+    uint64_t *trace;        // this read's per-sweep hash words (s_end - s_begin), or nullptr
 };
 
 // Initial state (given, or uniform on each box, Sec. 3.1) written by threads tid, tid+nthr, ...
@@ -897,6 +910,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
     const int32_t n_win = R.n_win;
     const SchedRec *mine = R.sched;
     int64_t E = 0;
+    uint64_t H = 0;   // change of the state hash in this sweep by this wave's moves (tracing)
     ScanCarry cy;
     if (!R.active) {
         if (R.shared)
@@ -1008,6 +1022,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     if (accept && v != zk) {
                         z[k] = (ZT)v;  // every lane stores the same value
                         E += d;
+                        if (R.trace) H += hash_word(k, v) - hash_word(k, zk);
                         if (!R.shared) state_write_fence<kStateInLds>();
                     }
                 }
@@ -1030,6 +1045,10 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                     visit(j, crec, ccoef, cd, crow, cdeg, [] {});
                 }
             }
+        }
+        if (R.trace) {
+            if (lane == 0) atomicAdd((unsigned long long *)&R.trace[s - R.s_begin], (unsigned long long)H);
+            H = 0;
         }
     }
     return E;
@@ -1060,6 +1079,14 @@ __global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
     if (shared) window_barrier();
     else state_write_fence<kStateInLds>();
     int64_t E = energy_part(P, z, tid, nthr);
+    uint64_t *trace = A.trace ? A.trace + (size_t)read * (size_t)(A.s_end - A.s_begin) : nullptr;
+    if (trace && A.s_end > A.s_begin) {
+        // the initial state's hash goes into the first sweep's word
+        uint64_t h0 = 0;
+        for (int32_t k = tid; k < n; k += nthr) h0 += hash_word(k, z[k]);
+        h0 = wave_sum_u64(h0);
+        if (lane == 0) atomicAdd((unsigned long long *)&trace[0], (unsigned long long)h0);
+    }
 
     ReplicaCtx R;
     R.P = P;
@@ -1077,6 +1104,7 @@ __global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
     R.n_win = A.n_win;
     R.shared = shared;
     R.active = true;
+    R.trace = trace;
     E += sweep_replica<kRule, kStateInLds, kRegChunk, kMaxE, Acc, int32_t>(R, z, lane);
 
     if (shared) {
@@ -1151,6 +1179,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B)
         R.n_win = D.n_win;
         R.shared = G > 1;
         R.active = active;
+        R.trace = nullptr;
         if (D.rule == SA_METROPOLIS) {
             E += sweep_replica<SA_METROPOLIS, true, 0, 1, Acc, ZT>(R, z, lane);
         } else if (D.rule == SA_HEAT_BATH) {

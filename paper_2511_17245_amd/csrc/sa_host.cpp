@@ -463,3 +463,50 @@ int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out) {
 }
 
 }  // namespace sa
+
+namespace sa {
+
+int32_t build_levels(const Packed &p, std::vector<int32_t> &level_start, std::vector<SchedRec> &slots) {
+    const int32_t n = p.n;
+    std::vector<int32_t> level(n, -1);
+    int32_t n_levels = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const VarRec &vr = p.var[k];
+        if (vr.width == 1) continue;   // a fixed variable never changes: it orders nothing
+        int32_t lv = 0;
+        auto see = [&](int32_t j) {
+            if (j < k && level[j] >= lv) lv = level[j] + 1;
+        };
+        if (p.dense) {
+            // every pair is coupled: each variable waits for all earlier ones
+            for (int32_t j = 0; j < k; ++j) see(j);
+        } else {
+            for (int32_t q = vr.row; q < vr.row + vr.deg; ++q) {
+                const IncRec &r = p.inc[q];
+                const uint32_t no = r.meta >> 8;
+                if (no <= 3) {
+                    for (uint32_t f = 0; f < no; ++f) see(r.o[f]);
+                } else {
+                    for (uint32_t f = 0; f < no; ++f) see(p.overflow[(size_t)r.o[0] + f]);
+                }
+            }
+        }
+        level[k] = lv;
+        n_levels = std::max(n_levels, lv + 1);
+    }
+    // counting sort by level; index order inside a level
+    level_start.assign((size_t)n_levels + 1, 0);
+    for (int32_t k = 0; k < n; ++k)
+        if (level[k] >= 0) level_start[(size_t)level[k] + 1]++;
+    for (int32_t l = 0; l < n_levels; ++l) level_start[(size_t)l + 1] += level_start[(size_t)l];
+    slots.assign((size_t)level_start[(size_t)n_levels], SchedRec{-1, 0, 1, 0, 0, 0u, {0, 0}});
+    std::vector<int32_t> fill(level_start.begin(), level_start.end() - 1);
+    for (int32_t k = 0; k < n; ++k) {
+        if (level[k] < 0) continue;
+        const VarRec &vr = p.var[k];
+        slots[(size_t)fill[(size_t)level[k]]++] = SchedRec{k, vr.lo, vr.width, vr.row, vr.deg, p.emask[k], {0, 0}};
+    }
+    return n_levels;
+}
+
+}  // namespace sa

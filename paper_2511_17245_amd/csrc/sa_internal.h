@@ -101,6 +101,14 @@ struct SchedRec {
 // (slot g * n_win + w).  Returns the number of windows.
 int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out);
 
+// Dependency levels of one sweep: level l holds, in index order, the variables (not fixed) all of
+// whose lower-index neighbours lie in earlier levels.  Updating the levels one after another, the
+// variables of a level in any order or at once, reads every neighbour exactly as the sequential
+// index-order sweep does: a lower-index neighbour already updated in this sweep, a higher-index
+// one not yet.  Returns the number of levels; slots are level-major, level_start has one more
+// entry than there are levels.
+int32_t build_levels(const Packed &p, std::vector<int32_t> &level_start, std::vector<SchedRec> &slots);
+
 // Device view of a packed plan.
 struct DevProblem {
     int32_t n;
@@ -143,7 +151,38 @@ struct AnnealArgs {
     const int32_t *z_init;   // device, n_reads * n, or nullptr
     int32_t *z_out;          // device, n_reads * n (also the working state when not in LDS)
     int64_t *e_out;          // device, n_reads
+    uint64_t *trace;         // device, n_reads * (s_end - s_begin) zeroed words, or nullptr: each
+                             // wave adds its share of the state hash's change per sweep (and of the
+                             // initial state's hash into the first sweep); a prefix pass then turns
+                             // them into the hash after every sweep
 };
+
+// Kernel arguments of one launch of the quad kernel (one update per four lanes, dependency levels).
+struct QuadArgs {
+    DevProblem P;
+    const double *beta;          // S inverse temperatures (device)
+    int32_t n_sweeps;
+    int32_t s_begin, s_end;
+    int32_t n_reads;
+    uint32_t key0, key1;
+    uint32_t instance_id;
+    const int32_t *level_start;  // n_levels + 1 offsets into slots (device)
+    const SchedRec *slots;       // level-major variables (device)
+    int32_t n_levels;
+    int32_t uniform_width;       // the common width W of every slot, or 0 when widths differ
+    const int32_t *z_init;
+    int32_t *z_out;
+    int64_t *e_out;
+    uint64_t *trace;             // as AnnealArgs::trace
+};
+// Waves of the quad kernel's workgroup (one replica); values per lane it keeps in registers.
+constexpr int kQuadWaves = 8;
+constexpr int kQuadMaxR = 32;
+// Launches the quad kernel for rule (SA_HEAT_BATH or SA_HEAT_BATH_CLOSED), a problem whose widest
+// range is max_width <= 4 * kQuadMaxR and whose exponents are <= max_exp <= 2 (defined in
+// sa_kernels_quad.hip).
+int launch_quad(int rule, const QuadArgs &a, int32_t max_width, int32_t max_exp, bool narrow, void *stream,
+                std::string &err);
 
 struct LaunchChoice {
     int win_waves = 1;         // waves per replica (window width)
@@ -156,6 +195,19 @@ struct LaunchChoice {
     bool narrow = false;       // energy differences in 32-bit arithmetic
     int variant = 0;
 };
+
+// Byte layout of a packed instance in one device area, each part 256-byte aligned (the records
+// and their coefficients are followed by one zero record).
+struct PackedLayout {
+    static constexpr int kParts = 11;
+    size_t off[kParts];
+    size_t total;
+};
+PackedLayout packed_layout(const Packed &pk);
+// Writes the packed instance into a host image of L.total bytes (padding zeroed).
+void stage_packed(const Packed &pk, const PackedLayout &L, char *image);
+// Points d at the parts of an image copied to device address base.
+void bind_packed(const Packed &pk, const PackedLayout &L, char *base, DevProblem &d);
 
 // Launches one annealing pass (defined in sa_kernels.hip).  Returns an SA_* status.
 int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *stream,
@@ -208,6 +260,12 @@ struct BatchLaunch {
 };
 // Queues the counter reset and the persistent kernel (both plain kernel launches).
 int launch_batch(const BatchArgs &b, const BatchLaunch &bl, void *stream, std::string &err);
+
+// Zeroes n words of device memory with a kernel (no memset node, so the work may be captured).
+int launch_zero_u64(uint64_t *p, int64_t n, void *stream, std::string &err);
+// Turns per-sweep hash changes into the hash after each sweep: row r of `trace` (n_reads rows of
+// n_cols) becomes its own inclusive prefix sum.
+int launch_trace_prefix(uint64_t *trace, int32_t n_reads, int32_t n_cols, void *stream, std::string &err);
 
 // Energies of n_states device-resident states (one wavefront per state).
 int launch_energy(const DevProblem &P, const int32_t *states, int32_t n_states, int64_t *out,

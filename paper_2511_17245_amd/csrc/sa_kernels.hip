@@ -1,6 +1,8 @@
 // sa_kernels.hip -- launch geometry and dispatch of the plain annealing kernels, and the energy
 // kernel.  The annealing kernels themselves (sa_device.h) are compiled per rule in
 // sa_kernels_<rule>.hip; the batched kernel in sa_kernels_batch.hip.
+#include <algorithm>
+
 #include "sa_device.h"
 #include "sa_kernel_table.h"
 
@@ -15,6 +17,23 @@ __global__ void __launch_bounds__(256) energy_kernel(DevProblem P, const int32_t
     if (idx >= n_states) return;
     const int64_t E = energy_part(P, states + (size_t)idx * P.n, lane, kWave);
     if (lane == 0) out[idx] = E;
+}
+
+__global__ void __launch_bounds__(256) zero_u64_kernel(uint64_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// One thread per read: row r becomes its inclusive prefix sum (modulo 2^64).
+__global__ void __launch_bounds__(256) trace_prefix_kernel(uint64_t *trace, int32_t n_reads, int32_t n_cols) {
+    const int32_t r = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= n_reads) return;
+    uint64_t *row = trace + (size_t)r * (size_t)n_cols;
+    uint64_t acc = 0;
+    for (int32_t c = 0; c < n_cols; ++c) {
+        acc += row[c];
+        row[c] = acc;
+    }
 }
 
 using KernelFn = AnnealKernelFn;
@@ -117,6 +136,30 @@ int launch_anneal(int rule, const AnnealArgs &a, const LaunchChoice &lc, void *s
     }
     hipLaunchKernelGGL(fn, dim3((unsigned)lc.groups), dim3((unsigned)(lc.waves_per_group * kWave)),
                        (size_t)lc.lds_bytes, (hipStream_t)stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return SA_EDEVICE;
+    }
+    return SA_OK;
+}
+
+int launch_zero_u64(uint64_t *p, int64_t n, void *stream, std::string &err) {
+    if (n <= 0) return SA_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return SA_EDEVICE;
+    }
+    return SA_OK;
+}
+
+int launch_trace_prefix(uint64_t *trace, int32_t n_reads, int32_t n_cols, void *stream, std::string &err) {
+    if (n_reads <= 0 || n_cols <= 0) return SA_OK;
+    hipLaunchKernelGGL(trace_prefix_kernel, dim3((unsigned)((n_reads + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, trace, n_reads, n_cols);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         err = std::string("kernel launch: ") + hipGetErrorString(e);

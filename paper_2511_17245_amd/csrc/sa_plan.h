@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -51,11 +52,22 @@ struct sa_plan {
         int32_t n_active = 0;  // variables that are not fixed
     };
     Sched sched[17];  // index G = 1, 2, 4, 8, 16
-    std::mutex sched_mu;  // guards the lazy building of sched (a server's preparers share plans)
+    // dependency levels of the sweep (the quad kernel), built on first use
+    struct Levels {
+        void *dev = nullptr;          // level_start (n_levels + 1 int32) then the slots
+        const int32_t *start = nullptr;
+        const sa::SchedRec *slots = nullptr;
+        int32_t n_levels = -1;        // -1: not built
+        int32_t n_slots = 0;
+        int32_t uniform_width = 0;    // common width of every slot, 0 when they differ
+    };
+    Levels levels;
+    std::mutex sched_mu;  // guards the lazy building of sched and levels (a server's preparers share plans)
     ~sa_plan() {
         if (beta_dev) (void)hipFree(beta_dev);
         for (auto &sc : sched)
             if (sc.dev) (void)hipFree(sc.dev);
+        if (levels.dev) (void)hipFree(levels.dev);
     }
 };
 
@@ -65,6 +77,8 @@ namespace sa {
 // Records msg as this thread's last error and returns code.
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
+// Clears this thread's last error (at the start of an entry point).
+void clear_error();
 // Canonicalise, check, pack and upload; *out owns the result.
 int build_plan(const sa_instance *inst, const sa_bounds *bounds, int32_t rule, sa_plan **out);
 // Inverse temperatures of a schedule (explicit or automatic) for the plan's instance.
@@ -75,5 +89,22 @@ int get_schedule(sa_plan *plan, int G, sa_plan::Sched **out);
 int stage_beta(sa_plan *plan, const std::vector<double> &beta, hipStream_t stream);
 // Heat-bath register chunk class of a plan's widest range (1, 2, 8, 32, or 0 = recompute).
 int reg_chunk_class(int32_t max_width);
+// The plan's dependency levels (built and uploaded on first use).
+int get_levels(sa_plan *plan, sa_plan::Levels **out);
+// The common width of the level slots, or 0 when widths differ.
+int32_t uniform_width(const std::vector<SchedRec> &slots);
+// Whether the quad kernel can run `rule` on this packed problem with n replicas' state in LDS.
+bool quad_eligible(int rule, const Packed &pk, int device);
+// Lanes per update (64 or 4) for a run: `requested` (0 = automatic) checked against eligibility;
+// the automatic choice takes the quad kernel when its levels hold >= 64 variables on average.
+// Returns -1 (with the error recorded) for a request the problem cannot take.
+int choose_lanes(int requested, int waves_per_replica, bool eligible, int32_t n_levels, int32_t n_slots);
+// SA_EUNSUPPORTED / SA_EINVAL (with the message recorded) when the GPU kernels cannot run `rule`
+// on a problem whose largest exponent is max_exp.
+int check_rule_support(int rule, int32_t max_exp);
+// Automatic waves per replica; windows(G, n_win, n_active) reports the window count of a G-wide
+// schedule and the number of variables that are not fixed (false: no such schedule).
+int pick_waves_per_replica(int32_t n, int32_t n_reads, int device,
+                           const std::function<bool(int, int32_t &, int32_t &)> &windows);
 
 }  // namespace sa

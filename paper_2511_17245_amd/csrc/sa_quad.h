@@ -1,0 +1,293 @@
+// sa_quad.h -- the heat-bath sweep with one update per four lanes (a "quad"), for sparse problems.
+//
+// Mapping: a workgroup of kWaves wavefronts anneals one replica, its state z in LDS.  The sweep
+// visits the dependency levels of the variables one after another (build_levels: a level holds
+// variables none of which shares a term with another, and all of whose lower-index neighbours lie
+// in earlier levels), with a workgroup barrier between levels; inside a level the 16 kWaves quads
+// of the workgroup take its variables in turn, each quad updating one variable on its own.  This
+// reads every neighbour as the sequential index-order sweep (Sec. 3.1) does, so the result is the
+// sequential sweep's.
+//
+// One update (Sec. 3.2, 3.3.2): the quad's four lanes split the variable's incidence records and
+// sum the coefficient a_k^(1) (and a_k^(2)) across the quad; lane q holds the values
+// l + q c .. l + q c + c - 1 (c = ceil(W / 4)) and their weights w_v = exp(-beta (dE_v - dE_min))
+// in registers (c = kR, the launch's class for its widest range; values past a variable's own
+// range weigh zero); the cumulative weights C_v are formed in value order, one value at a time --
+// lane 0 adds its c weights, hands the running sum to lane 1, and so on -- so they are the exact
+// sums of the plain sequential definition; the drawn value is the first v with C_v > U * C_u,
+// i.e. the number of C_v <= U * C_u (C never decreases), summed over the quad.
+#pragma once
+
+#include "sa_device.h"
+
+namespace sa {
+namespace {
+
+// DPP quad_perm controls: lane i of each quad reads lane perm[i] of that quad.
+constexpr int kQuadXor1 = 0xB1;   // [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;   // [2, 3, 0, 1]
+
+template <int kCtrl>
+__device__ __forceinline__ uint32_t qperm32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kCtrl, 0xf, 0xf, false);
+}
+template <int kCtrl>
+__device__ __forceinline__ uint64_t qperm64(uint64_t x) {
+    return ((uint64_t)qperm32<kCtrl>((uint32_t)(x >> 32)) << 32) | qperm32<kCtrl>((uint32_t)x);
+}
+// every lane of a quad takes lane kQ's value
+template <int kQ>
+__device__ __forceinline__ double quad_bcast(double x) {
+    return __longlong_as_double((long long)qperm64<kQ * 0x55>((uint64_t)__double_as_longlong(x)));
+}
+
+template <typename Acc>
+__device__ __forceinline__ Acc quad_sum(Acc x) {
+    if (sizeof(Acc) == 4) {
+        uint32_t y = (uint32_t)x;
+        y += qperm32<kQuadXor1>(y);
+        y += qperm32<kQuadXor2>(y);
+        return (Acc)y;
+    }
+    uint64_t y = (uint64_t)x;
+    y += qperm64<kQuadXor1>(y);
+    y += qperm64<kQuadXor2>(y);
+    return (Acc)y;
+}
+
+__device__ __forceinline__ int64_t quad_min_i64(int64_t x) {
+    int64_t y = (int64_t)qperm64<kQuadXor1>((uint64_t)x);
+    x = y < x ? y : x;
+    y = (int64_t)qperm64<kQuadXor2>((uint64_t)x);
+    return y < x ? y : x;
+}
+
+// One step of the value-order walk: lane kQ of each quad turns its weights into cumulative
+// weights, starting from `carry` (the sum of the quad's earlier lanes' weights); every lane then
+// takes lane kQ's new running sum as the carry.
+template <int kQ, int kR>
+__device__ __forceinline__ void walk_step(double (&w)[kR], int ql, double &carry) {
+    if (ql == kQ) {
+        double run = carry;
+#pragma unroll
+        for (int i = 0; i < kR; ++i) {
+            run += w[i];
+            w[i] = run;
+        }
+        carry = run;
+    }
+    carry = quad_bcast<kQ>(carry);
+}
+
+// Heat-bath draw (Sec. 3.3.2) of one quad: returns the new value.  C: the quad's coefficients.
+// kR: values per lane (4 kR >= W).  jinf[i]: the lane's value index q kR + i as a double when
+// it lies inside this variable's range, +inf past it.
+template <int kR, int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W, int64_t zk,
+                                                  double beta, double U, int ql, bool linear_in,
+                                                  const double (&jinf)[kR]) {
+    const uint32_t W32 = (uint32_t)W;
+    const uint32_t j0 = (uint32_t)ql * (uint32_t)kR;
+    const bool linear = kMaxE == 1 || linear_in;
+    double w[kR];
+    if (linear) {
+        // dE(v) = a1 (v - z_k): its minimum is at an end of the range, and dE_v - dE_min is |a1|
+        // times the distance of v from that end (an exact integer, converted to double with one
+        // rounding as the integer difference would be)
+        const bool from_top = to_i64<Acc>(C.a[1]) < 0;
+        const Acc slope = from_top ? (Acc)0 - C.a[1] : C.a[1];
+        const double slope_d = sizeof(Acc) == 4 ? (double)(uint32_t)slope : (double)(int64_t)slope;
+        if (!(beta * slope_d > 0.0)) {
+            // every weight is exp(-0) = 1: C_v = v - l + 1 exactly, and the draw is the count of
+            // those <= U W
+            const double thr = U * (double)W32;
+            const uint32_t below = (uint32_t)thr;   // floor: thr >= 0
+            return lo + (int64_t)(below < W32 ? below : W32 - 1u);
+        }
+        // |a1| times the distance: one rounding of the exact product, as the oracle's conversion of
+        // the integer difference (slope * (W - 1) is exact in double: W <= 128)
+        const double s_slope = from_top ? -slope_d : slope_d;
+        const double o_slope = from_top ? slope_d * (double)(W32 - 1u) : 0.0;
+#pragma unroll
+        for (int i = 0; i < kR; ++i) {
+            // a value past the range has index +inf, so x = +inf and the argument -(beta x) = -inf
+            // (beta x > 0 here), which the exponential clamps to a weight of exactly 0
+            const double x = __builtin_fabs(fma(jinf[i], s_slope, o_slope));
+            w[i] = exp_nonpos(-(beta * x));
+        }
+    } else {
+        int64_t dmin = INT64_MAX;
+#pragma unroll
+        for (int i = 0; i < kR; ++i) {
+            const uint32_t j = j0 + (uint32_t)i;
+            const int64_t d = poly_delta(C, zk, lo + (int64_t)(j < W32 ? j : W32 - 1u));
+            dmin = d < dmin ? d : dmin;
+        }
+        dmin = quad_min_i64(dmin);
+#pragma unroll
+        for (int i = 0; i < kR; ++i) {
+            // evaluated at a clamped index past the range, so that the exponentials of a lane are
+            // independent instructions; such values weigh zero
+            const uint32_t j = j0 + (uint32_t)i;
+            const uint32_t jc = j < W32 ? j : W32 - 1u;
+            const int64_t d = poly_delta(C, zk, lo + (int64_t)jc);
+            const double x = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)d - (uint32_t)dmin) : (double)(d - dmin);
+            const double wv = exp_nonpos(-(beta * x));
+            w[i] = j < W32 ? wv : 0.0;
+        }
+    }
+    double carry = 0.0;
+    walk_step<0, kR>(w, ql, carry);
+    walk_step<1, kR>(w, ql, carry);
+    walk_step<2, kR>(w, ql, carry);
+    walk_step<3, kR>(w, ql, carry);
+    const double thr = U * carry;   // carry: the sum of all W weights, C at the last value
+    uint32_t below = 0;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) below += w[i] <= thr ? 1u : 0u;
+    below = quad_sum<uint32_t>(below);
+    return lo + (int64_t)(below < W32 ? below : W32 - 1u);
+}
+
+// The quad's coefficients a_k^(m) of variable k (row `row`, `deg` incidence records): lane q takes
+// records q, q + 4, ...; lanes past the row read the zero record.
+template <int kMaxE, typename Acc>
+__device__ __forceinline__ void quad_coeffs(const DevProblem &P, const int32_t *z, int32_t row, int32_t deg,
+                                            uint32_t emask, int ql, Coeffs<kMaxE, Acc> &C) {
+    Acc part[kMaxE + 1];
+#pragma unroll
+    for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
+    for (int32_t c0 = 0; c0 < deg; c0 += 4) {
+        const int32_t idx = c0 + ql < deg ? row + c0 + ql : P.inc_pad;
+        const IncRec r = P.inc[idx];
+        const uint64_t coef = (uint64_t)P.inc_coef[idx];
+        int e;
+        const Acc prod = record_product<Acc, int32_t>(P, z, r, coef, e);
+#pragma unroll
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
+    }
+    C.a[0] = 0;
+#pragma unroll
+    for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? quad_sum<Acc>(part[m]) : (Acc)0;
+}
+
+// kRule: SA_HEAT_BATH, or SA_HEAT_BATH_CLOSED (the O(1) draw of Sec. 3.3.2 for variables whose
+// energy difference is linear, the enumeration for the others).  kR: values per lane (W <= 4 kR).
+template <int kRule, int kR, int kMaxE, typename Acc, int kWaves>
+__global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
+    extern __shared__ int32_t lds_state[];
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)(threadIdx.x / kWave);
+    const int ql = lane & 3;
+    constexpr int kQuads = kWaves * 16;
+    const int qid = wave * 16 + (lane >> 2);
+    const int read = (int)blockIdx.x;
+    if (read >= A.n_reads) return;   // uniform over the workgroup
+    const DevProblem &P = A.P;
+    const int32_t n = P.n;
+    int32_t *z = lds_state;
+    const int tid = (int)threadIdx.x, nthr = kWaves * kWave;
+
+    init_state(P, z, A.z_init ? A.z_init + (size_t)read * n : nullptr, (uint32_t)read, A.instance_id, A.key0,
+               A.key1, tid, nthr);
+    window_barrier();
+    int64_t E = energy_part(P, z, tid, nthr);   // this wave's share of E(z0)
+    uint64_t *trace = A.trace ? A.trace + (size_t)read * (size_t)(A.s_end - A.s_begin) : nullptr;
+    if (trace && A.s_end > A.s_begin) {
+        uint64_t h0 = 0;
+        for (int32_t k = tid; k < n; k += nthr) h0 += hash_word(k, z[k]);
+        h0 = wave_sum_u64(h0);
+        if (lane == 0) atomicAdd((unsigned long long *)&trace[0], (unsigned long long)h0);
+    }
+
+    // this lane's value indexes q kR + i as doubles, +inf past the range: set once when every
+    // variable has the same width, else per update
+    const uint32_t Wu = (uint32_t)A.uniform_width;
+    double jinf[kR];
+    auto set_jinf = [&](uint32_t W32) {
+#pragma unroll
+        for (int i = 0; i < kR; ++i) {
+            const uint32_t j = (uint32_t)(ql * kR + i);
+            jinf[i] = j < W32 ? (double)j : __builtin_huge_val();
+        }
+    };
+    if (Wu) set_jinf(Wu);
+    int64_t dE = 0;    // this quad's applied energy changes (the same in its four lanes)
+    uint64_t H = 0;    // this quad's change of the state hash in the current sweep (tracing)
+    for (int32_t s = A.s_begin; s < A.s_end; ++s) {
+        const double beta = A.beta[s];
+        for (int32_t l = 0; l < A.n_levels; ++l) {
+            const int32_t b0 = A.level_start[l], b1 = A.level_start[l + 1];
+            // batches of four rounds: lane q of a quad fetches the slot of the batch's round q and
+            // draws its random words; in round q the quad reads them from lane q
+            for (int32_t batch = b0; batch < b1; batch += 4 * kQuads) {
+                const int32_t my_idx = batch + ql * kQuads + qid;
+                SchedRec ms;
+                if (my_idx < b1) {
+                    ms = A.slots[my_idx];
+                } else {
+                    ms.k = 0;
+                    ms.lo = 0;
+                    ms.width = 1;
+                    ms.row = 0;
+                    ms.deg = 0;
+                    ms.emask = 0;
+                }
+                uint32_t y0 = (uint32_t)ms.k, y1 = (uint32_t)s, y2 = (uint32_t)read, y3 = A.instance_id;
+                philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t idx = batch + q * kQuads + qid;
+                    if (batch + q * kQuads >= b1) break;   // uniform: the level has no round q here
+                    const int src = ((lane & ~3) | q) << 2;
+                    auto from_q = [&](uint32_t v) { return (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)v); };
+                    const int32_t k = (int32_t)from_q((uint32_t)ms.k);
+                    const int64_t lo = (int32_t)from_q((uint32_t)ms.lo);
+                    const int64_t W = (int32_t)from_q((uint32_t)ms.width);
+                    const int32_t row = (int32_t)from_q((uint32_t)ms.row);
+                    const int32_t deg = (int32_t)from_q((uint32_t)ms.deg);
+                    const uint32_t emask = from_q(ms.emask);
+                    const uint32_t x1 = from_q(y1), x2 = from_q(y2), x3 = from_q(y3);
+                    if (idx < b1) {
+                        const double U = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
+                        const int64_t zk = z[k];
+                        Coeffs<kMaxE, Acc> C;
+                        quad_coeffs<kMaxE, Acc>(P, z, row, deg, emask, ql, C);
+                        const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
+                        int64_t v;
+                        if (kRule == SA_HEAT_BATH_CLOSED && linear) {
+                            v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, x1);
+                        } else {
+                            if (!Wu) set_jinf((uint32_t)W);
+                            v = quad_heat_bath<kR, kMaxE, Acc>(C, lo, W, zk, beta, U, ql, linear, jinf);
+                        }
+                        if (v != zk) {
+                            z[k] = (int32_t)v;   // the quad's four lanes store the same value
+                            dE += poly_delta(C, zk, v);
+                            if (trace) H += hash_word(k, v) - hash_word(k, zk);
+                        }
+                    }
+                }
+            }
+            window_barrier();
+        }
+        if (trace) {
+            const uint64_t hw = wave_sum_u64(ql == 0 ? H : 0ull);
+            if (lane == 0) atomicAdd((unsigned long long *)&trace[s - A.s_begin], (unsigned long long)hw);
+            H = 0;
+        }
+    }
+    E += (int64_t)wave_sum_u64(ql == 0 ? (uint64_t)dE : 0ull);
+    int64_t *parts = (int64_t *)(lds_state + (((size_t)n + 1) & ~(size_t)1));
+    if (lane == 0) parts[wave] = E;
+    window_barrier();
+    if (wave == 0 && lane == 0) {
+        int64_t tot = 0;
+        for (int q = 0; q < kWaves; ++q) tot += parts[q];
+        A.e_out[read] = tot;
+    }
+    int32_t *zo = A.z_out + (size_t)read * n;
+    for (int32_t k = tid; k < n; k += nthr) zo[k] = z[k];
+}
+
+}  // namespace
+}  // namespace sa

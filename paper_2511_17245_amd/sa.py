@@ -43,7 +43,8 @@ class sa_schedule(C.Structure):
 class sa_opts(C.Structure):
     _fields_ = [("instance_id", C.c_uint32), ("hip_stream", C.c_void_p), ("device_buffers", C.c_int32),
                 ("sweep_begin", C.c_int32), ("sweep_end", C.c_int32), ("init_states", C.c_void_p),
-                ("otm_r", C.c_double), ("waves_per_replica", C.c_int32), ("otm_enum_max", C.c_int32)]
+                ("otm_r", C.c_double), ("waves_per_replica", C.c_int32), ("otm_enum_max", C.c_int32),
+                ("trace_hashes", C.c_void_p), ("lanes_per_update", C.c_int32)]
 
 
 class sa_plan_info(C.Structure):
@@ -56,7 +57,8 @@ class sa_plan_info(C.Structure):
 class sa_launch_info(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("groups", C.c_int32), ("lds_bytes", C.c_int32),
                 ("state_in_lds", C.c_int32), ("kernel_variant", C.c_int32),
-                ("waves_per_replica", C.c_int32), ("n_windows", C.c_int32)]
+                ("waves_per_replica", C.c_int32), ("n_windows", C.c_int32),
+                ("lanes_per_update", C.c_int32), ("n_levels", C.c_int32)]
 
 
 class sa_problem(C.Structure):
@@ -195,7 +197,8 @@ def _schedule(n_sweeps: int, beta):
 
 
 def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, sweep_end=0,
-              init_states=None, otm_r=-1.0, waves_per_replica=0, otm_enum_max=0) -> sa_opts:
+              init_states=None, otm_r=-1.0, waves_per_replica=0, otm_enum_max=0,
+              trace_hashes=None, lanes_per_update=0) -> sa_opts:
     o = sa_opts()
     lib().sa_opts_default(C.byref(o))
     o.instance_id = int(instance_id) & 0xFFFFFFFF
@@ -207,6 +210,8 @@ def make_opts(instance_id=0, stream=None, device_buffers=False, sweep_begin=0, s
     o.otm_r = float(otm_r)
     o.waves_per_replica = int(waves_per_replica)
     o.otm_enum_max = int(otm_enum_max)
+    o.trace_hashes = _p(trace_hashes)
+    o.lanes_per_update = int(lanes_per_update)
     return o
 
 
@@ -273,33 +278,43 @@ class Plan:
 
     def run_device(self, n_sweeps, n_reads, seed, z_out, e_out, beta=None, stream=None,
                    instance_id=0, sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0,
-                   waves_per_replica=0, otm_enum_max=0):
-        """Queue a run writing into device tensors z_out (int32 [n_reads, N]) and e_out (int64)."""
+                   waves_per_replica=0, otm_enum_max=0, trace=None, lanes_per_update=0):
+        """Queue a run writing into device tensors z_out (int32 [n_reads, N]) and e_out (int64);
+        trace, when given, is a device tensor of n_reads * (sweep_end - sweep_begin) 64-bit words
+        that receives the state hash after every sweep."""
         assert z_out.is_cuda and e_out.is_cuda
         assert z_out.dtype.itemsize == 4 and e_out.dtype.itemsize == 8
         assert z_out.numel() == n_reads * self.n and e_out.numel() == n_reads
         assert z_out.is_contiguous() and e_out.is_contiguous()
         if init_states is not None:
             assert init_states.is_cuda and init_states.numel() == n_reads * self.n
+        if trace is not None:
+            s1 = sweep_end if sweep_end > 0 else n_sweeps
+            assert trace.is_cuda and trace.dtype.itemsize == 8 and trace.is_contiguous()
+            assert trace.numel() == n_reads * (s1 - sweep_begin)
         sched, keep = _schedule(n_sweeps, beta)
         opts = make_opts(instance_id, stream, True, sweep_begin, sweep_end, init_states, otm_r,
-                         waves_per_replica, otm_enum_max)
+                         waves_per_replica, otm_enum_max, trace, lanes_per_update)
         rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                _p(z_out), _p(e_out), C.byref(opts))
         _check(rc, "sa_plan_run")
 
     def run(self, n_sweeps, n_reads, seed, beta=None, instance_id=0, sweep_begin=0, sweep_end=0,
-            init_states=None, otm_r=-1.0, waves_per_replica=0):
-        """Run with host buffers; returns (states, energies)."""
+            init_states=None, otm_r=-1.0, waves_per_replica=0, trace=False, lanes_per_update=0):
+        """Run with host buffers; returns (states, energies), and with trace=True also the state
+        hash after every sweep (uint64 [n_reads, sweep_end - sweep_begin])."""
         sched, keep = _schedule(n_sweeps, beta)
         z = np.zeros((n_reads, self.n), np.int32)
         e = np.zeros(n_reads, np.int64)
         zi = None if init_states is None else np.ascontiguousarray(init_states, np.int32)
-        opts = make_opts(instance_id, None, False, sweep_begin, sweep_end, zi, otm_r, waves_per_replica)
+        s1 = sweep_end if sweep_end > 0 else n_sweeps
+        h = np.zeros((n_reads, s1 - sweep_begin), np.uint64) if trace else None
+        opts = make_opts(instance_id, None, False, sweep_begin, sweep_end, zi, otm_r, waves_per_replica,
+                         trace_hashes=h if trace and h.size else None, lanes_per_update=lanes_per_update)
         rc = lib().sa_plan_run(self.h, C.byref(sched), int(n_reads), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                _p(z), _p(e), C.byref(opts))
         _check(rc, "sa_plan_run")
-        return z, e
+        return (z, e, h) if trace else (z, e)
 
 
 class Batch:

@@ -1,11 +1,14 @@
 """GPU: the batched form (one persistent launch over many problems) gives, problem by problem,
-exactly the per-instance results, which match the oracle."""
+exactly the results of plain per-instance launches of the same kernels (one wavefront per update),
+and those match the oracle at the parity bar (tests/parity.py)."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2511_17245_amd import inputs as I
 from paper_2511_17245_amd import sa
+from tests import parity
+from tests.test_gpu_parity import explainer
 
 pytestmark = pytest.mark.gpu
 
@@ -34,12 +37,14 @@ def mixed_items(n=18, sweeps=30, reads=6):
 
 
 def per_instance(w):
+    """A plain launch of the problem alone, one wavefront per update (the batch's update code)."""
     import torch
     plan = sa.Plan(w.problem, w.rule)
     z = torch.empty((w.n_reads, w.problem.n_vars), dtype=torch.int32, device="cuda")
     e = torch.empty(w.n_reads, dtype=torch.int64, device="cuda")
     plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=w.beta,
-                    stream=torch.cuda.current_stream().cuda_stream, instance_id=w.instance_id)
+                    stream=torch.cuda.current_stream().cuda_stream, instance_id=w.instance_id,
+                    waves_per_replica=1)
     torch.cuda.synchronize()
     plan.close()
     return z.cpu().numpy(), e.cpu().numpy()
@@ -49,6 +54,16 @@ def oracle_run(w):
     P = oracle.Poly(w.problem)
     beta = w.beta if w.beta is not None else P.schedule(w.n_sweeps)[0]
     return P.anneal(w.rule, beta, w.n_reads, w.seed, w.instance_id)
+
+
+def vs_oracle(label, w, z, e):
+    """Results of problem w against the oracle at the parity bar; a parted read is traced through
+    plain launches of the same update code."""
+    P = oracle.Poly(w.problem)
+    beta = w.beta if w.beta is not None else P.schedule(w.n_sweeps)[0]
+    zo, eo = P.anneal(w.rule, beta, w.n_reads, w.seed, w.instance_id)
+    parity.check(label, w.n_reads, lambda i: e[i] == eo[i] and np.array_equal(z[i], zo[i]),
+                 explainer(w.problem, P, w.rule, beta, w.seed, w.instance_id, G=1))
 
 
 @pytest.mark.parametrize("mode", ["plain", "graph", "autotune"])
@@ -65,9 +80,58 @@ def test_batch_equals_per_instance_and_oracle(mode):
         zp, ep = per_instance(w)
         assert np.array_equal(got[i][0], zp) and np.array_equal(got[i][1], ep), f"problem {i} vs plain"
         if i % 3 == 0 or w.rule == sa.HEAT_BATH_CLOSED:
-            zo, eo = oracle_run(w)
-            assert np.array_equal(got[i][0], zo) and np.array_equal(got[i][1], eo), f"problem {i} vs oracle"
+            vs_oracle(f"{mode} problem {i}", w, got[i][0], got[i][1])
     b.close()
+
+
+def test_batch_wide_heat_bath_ranges():
+    # heat-bath problems wider than 512 values take the batch kernel's recompute path (weights
+    # evaluated again in the selection); 2048 < W takes it in plain launches too.  Sparse and dense
+    # QUIO (the served dense requests have W = 2001), linear and squared variables.
+    r = np.random.Generator(np.random.PCG64(21))
+    items = [
+        I.Workload(I.erdos_renyi_quio(300, 6.0, -400, 400, 10, 10, r), sa.HEAT_BATH, 8, 4, 11, 1),   # W 801
+        I.Workload(I.dense_quio(256, -1000, 1000, 10, 10, r), sa.HEAT_BATH, 3, 4, 12, 2),        # W 2001, dense
+        I.Workload(I.random_huio(120, 500, [1, 2, 3], -1500, 1500, 2, r), sa.HEAT_BATH, 4, 3, 13, 3),  # W 3001
+        I.Workload(I.erdos_renyi_quio(200, 4.0, -1200, 1300, 5, 5, r), sa.HEAT_BATH_CLOSED, 6, 4, 14, 4),
+        I.Workload(I.dense_quio(96, -700, 700, 8, 8, r), sa.HEAT_BATH_CLOSED, 4, 4, 15, 5),       # squares: enum
+        I.Workload(I.cfg3_huio(n=200, m=2000).problem, sa.OPT_METROPOLIS, 10, 4, 16, 6),
+    ]
+    for mode in ("plain", "graph"):
+        say("wide batch", mode)
+        b = sa.Batch(items, use_graph=(mode == "graph"))
+        b.run()
+        got = b.results()
+        b.close()
+        for i, w in enumerate(items):
+            zp, ep = per_instance(w)
+            assert np.array_equal(got[i][0], zp) and np.array_equal(got[i][1], ep), f"{mode} problem {i} vs plain"
+            if mode == "plain":
+                vs_oracle(f"wide problem {i}", w, got[i][0], got[i][1])
+
+
+def test_cfg4_full_batch_sampled_problems_all_reads():
+    # the 512-problem batch in the benchmark's configuration (autotuned geometry, graph replay);
+    # every read of a seeded sample of 40 problems against the oracle's stored results
+    from tests.golden import make_full_size as M
+    items, ids = M.cfg4_sample()
+    gold = M.read("cfg4")
+    say("cfg4 full batch", len(items), "problems")
+    b = sa.Batch(items, autotune=True, use_graph=True)
+    say("info", b.info())
+    b.run()
+    got = b.results()
+    b.close()
+    for i in ids:
+        w = items[i]
+        hdr, eo, ho = gold[f"cfg4-item{i}"]
+        z, e = got[i]
+        P = oracle.Poly(w.problem)
+        assert all(int(e[j]) == P.energy(z[j]) for j in range(w.n_reads))
+        hg = parity.state_hashes(z)
+        beta = M.schedule(P, w)
+        parity.check(f"cfg4 item {i}", w.n_reads, lambda j: e[j] == eo[j] and hg[j] == ho[j],
+                     explainer(w.problem, P, w.rule, beta, w.seed, w.instance_id, G=1))
 
 
 def test_graph_replays_are_identical_with_eager_work_between():

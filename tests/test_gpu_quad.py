@@ -1,0 +1,129 @@
+"""GPU: the quad kernel (one update per four lanes over the sweep's dependency levels) against the
+oracle.  Its heat-bath cumulative weights are added in value order, the oracle's order, so reads
+part only where an exponential's last bit decides a draw; the bar is tests/parity.py's."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_17245_amd import inputs as I
+from paper_2511_17245_amd import sa
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+HB = [sa.HEAT_BATH, sa.HEAT_BATH_CLOSED]
+
+
+def say(*a):
+    print("[gpu-quad]", *a, flush=True)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def quad_run(prob, rule, beta, n_reads, seed, instance_id=0, init=None, s0=0, s1=0, trace=False, lanes=4):
+    import torch
+    plan = sa.Plan(prob, rule)
+    z = torch.empty((n_reads, prob.n_vars), dtype=torch.int32, device="cuda")
+    e = torch.empty(n_reads, dtype=torch.int64, device="cuda")
+    zi = None if init is None else torch.as_tensor(np.ascontiguousarray(init, np.int32), device="cuda")
+    n_traced = (s1 if s1 > 0 else len(beta)) - s0
+    h = torch.empty(n_reads * n_traced, dtype=torch.int64, device="cuda") if trace else None
+    plan.run_device(len(beta), n_reads, seed, z, e, beta=beta, stream=torch.cuda.current_stream().cuda_stream,
+                    instance_id=instance_id, init_states=zi, sweep_begin=s0, sweep_end=s1, trace=h,
+                    lanes_per_update=lanes)
+    torch.cuda.synchronize()
+    launch = plan.last_launch()
+    plan.close()
+    assert launch["lanes_per_update"] == lanes
+    out = (z.cpu().numpy(), e.cpu().numpy(), launch)
+    if trace:
+        out += (h.cpu().numpy().view(np.uint64).reshape(n_reads, n_traced),)
+    return out
+
+
+def vs_oracle(label, prob, rule, beta, n_reads, seed, instance_id=0):
+    P = oracle.Poly(prob)
+    zg, eg, launch = quad_run(prob, rule, beta, n_reads, seed, instance_id)
+    zo, eo = P.anneal(rule, beta, n_reads, seed, instance_id)
+    assert all(int(eg[i]) == P.energy(zg[i]) for i in range(n_reads))
+
+    def explain(i):
+        _, _, _, h = quad_run(prob, rule, beta, i + 1, seed, instance_id, trace=True)
+
+        def after(s, z):
+            zz, _, _ = quad_run(prob, rule, beta, i + 1, seed, instance_id, init=np.tile(z, (i + 1, 1)),
+                                s0=s, s1=s + 1)
+            return zz[i]
+        return parity.localise(P, rule, beta, seed, instance_id, i, h[i], after)
+    parity.check(f"{label} {launch}", n_reads, lambda i: eg[i] == eo[i] and np.array_equal(zg[i], zo[i]),
+                 explain)
+
+
+def cases():
+    r = rng(4040)
+    yield "er_w101_n3000", I.cfg2_sparse_quio(n=3000).problem, 30, 48
+    yield "er_w2", I.erdos_renyi_quio(500, 6.0, 0, 1, 5, 5, r), 25, 32
+    yield "er_w7_n900", I.erdos_renyi_quio(900, 8.0, -3, 3, 10, 10, r), 25, 32
+    yield "er_w33", I.erdos_renyi_quio(700, 5.0, -16, 16, 10, 10, r), 25, 32
+    yield "er_w64", I.erdos_renyi_quio(700, 5.0, -32, 31, 10, 10, r), 25, 32
+    yield "er_w128", I.erdos_renyi_quio(600, 4.0, -64, 63, 7, 7, r), 20, 24
+    squares = I.random_huio(800, 2400, [1, 2], -20, 20, 6, r)      # z_i^2 terms: enumeration
+    yield "squares_w41", squares, 25, 32
+    fixed = I.erdos_renyi_quio(400, 6.0, -8, 9, 8, 8, r)
+    fixed.lower[::5] = 3
+    fixed.upper[::5] = 3
+    yield "fixed_vars_w18", fixed, 20, 16
+    yield "wide_coefs_64bit", I.random_huio(300, 900, [1, 2], -60, 60, 20000, r), 15, 16
+    yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
+    yield "uneven_widths", I.Problem(300, *[getattr(I.erdos_renyi_quio(300, 5.0, -4, 4, 6, 6, r), f)
+                                            for f in ("term_ptr", "factor_var", "coef")],
+                                     np.arange(300, dtype=np.int32) % 7 - 12, np.arange(300, dtype=np.int32) % 11)
+
+
+@pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
+def test_quad_kernel_against_the_oracle(case):
+    name, prob, sweeps, reads = case if len(case) == 4 else (*case, 20, 16)
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(sweeps)
+    for rule in HB:
+        say(name, sa.RULE_NAMES[rule], f"N={prob.n_vars} S={sweeps} R={reads}")
+        vs_oracle(f"{name}/{sa.RULE_NAMES[rule]}", prob, rule, beta, reads, 600 + rule, instance_id=5)
+
+
+def test_quad_trace_resume_and_determinism():
+    prob = I.cfg2_sparse_quio(n=2000).problem
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(20)
+    for rule in HB:
+        z, e, _, h = quad_run(prob, rule, beta, 16, 9, trace=True)
+        _, _, ho = P.anneal(rule, beta, 16, 9, trace=True)
+        assert np.array_equal(h, ho)
+        z1, _, _ = quad_run(prob, rule, beta, 16, 9, s1=7)
+        z2, e2, _ = quad_run(prob, rule, beta, 16, 9, init=z1, s0=7)
+        assert np.array_equal(z2, z) and np.array_equal(e2, e)
+        z3, e3, _ = quad_run(prob, rule, beta, 16, 9)
+        assert np.array_equal(z3, z) and np.array_equal(e3, e)
+
+
+def test_quad_is_chosen_automatically_for_the_sparse_workload_and_rejected_elsewhere():
+    prob = I.cfg2_sparse_quio(n=10_000, n_sweeps=2).problem
+    beta = sa.auto_schedule(prob, 2)
+    _, _, launch = quad_run(prob, sa.HEAT_BATH, beta, 4, 1, lanes=4)
+    import torch
+    plan = sa.Plan(prob, sa.HEAT_BATH)
+    z = torch.empty((4, prob.n_vars), dtype=torch.int32, device="cuda")
+    e = torch.empty(4, dtype=torch.int64, device="cuda")
+    plan.run_device(2, 4, 1, z, e, beta=beta, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert plan.last_launch()["lanes_per_update"] == 4
+    plan.close()
+    r = rng(1)
+    for prob, rule in [(I.dense_quio(80, -5, 5, 5, 5, r), sa.HEAT_BATH),
+                       (I.erdos_renyi_quio(200, 4.0, -100, 100, 5, 5, r), sa.HEAT_BATH),
+                       (I.erdos_renyi_quio(200, 4.0, -5, 5, 5, 5, r), sa.METROPOLIS),
+                       (I.from_terms(3, [(1, [0, 0, 0]), (2, [1, 2]), (-1, [0, 1])], -3, 3), sa.HEAT_BATH)]:
+        with pytest.raises(sa.SAError) as ex:
+            quad_run(prob, rule, np.full(2, 0.1), 2, 1)
+        assert ex.value.code == sa.EINVAL

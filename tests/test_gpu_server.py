@@ -8,6 +8,8 @@ import pytest
 import oracle
 from paper_2511_17245_amd import inputs as I
 from paper_2511_17245_amd import sa
+from tests import parity
+from tests.test_gpu_parity import explainer
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +36,8 @@ def alone(w):
     z = torch.empty((w.n_reads, w.problem.n_vars), dtype=torch.int32, device="cuda")
     e = torch.empty(w.n_reads, dtype=torch.int64, device="cuda")
     plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=w.beta,
-                    stream=torch.cuda.current_stream().cuda_stream, instance_id=w.instance_id)
+                    stream=torch.cuda.current_stream().cuda_stream, instance_id=w.instance_id,
+                    waves_per_replica=1)
     torch.cuda.synchronize()
     plan.close()
     return z.cpu().numpy(), e.cpu().numpy()
@@ -61,10 +64,13 @@ def test_served_results_equal_alone(chunk):
     for i, w in enumerate(items):
         z, e = alone(w)
         assert np.array_equal(out[i][0], z) and np.array_equal(out[i][1], e), f"request {i}"
-    P = oracle.Poly(items[2].problem)
-    zo, eo = P.anneal(items[2].rule, P.schedule(items[2].n_sweeps)[0], items[2].n_reads, items[2].seed,
-                      items[2].instance_id)
-    assert np.array_equal(out[2][0], zo) and np.array_equal(out[2][1], eo)
+    w = items[2]
+    P = oracle.Poly(w.problem)
+    beta = w.beta if w.beta is not None else P.schedule(w.n_sweeps)[0]
+    zo, eo = P.anneal(w.rule, beta, w.n_reads, w.seed, w.instance_id)
+    parity.check("served request 2", w.n_reads,
+                 lambda i: out[2][1][i] == eo[i] and np.array_equal(out[2][0][i], zo[i]),
+                 explainer(w.problem, P, w.rule, beta, w.seed, w.instance_id, G=1))
 
 
 def test_memory_budget_admission():
@@ -136,3 +142,55 @@ def test_shared_plan_requests():
         assert np.array_equal(srv.result(t)[0], z) and np.array_equal(srv.result(t)[1], e)
     srv.close()
     plan.close()
+
+
+def test_served_wide_heat_bath_alone_and_in_mix():
+    # dense W = 2001 heat-bath requests (the serving mix's type B, smaller N) and a W > 2048 one,
+    # served with HUIO requests: each equals its plain launch alone and the oracle
+    r = np.random.Generator(np.random.PCG64(23))
+    wide = [I.Workload(I.dense_quio(192, -1000, 1000, 10, 10, r), sa.HEAT_BATH, 3, 4, 31, 3001),
+            I.Workload(I.random_huio(100, 400, [1, 2], -1400, 1400, 2, r), sa.HEAT_BATH, 3, 3, 32, 3002),
+            I.Workload(I.erdos_renyi_quio(150, 5.0, -600, 600, 6, 6, r), sa.HEAT_BATH, 5, 4, 33, 3003)]
+    items = requests(n=6, sweeps=20, reads=4) + wide
+    out, timings, stats = serve(items, chunk_sweeps=2)
+    assert all(t["status"] == sa.OK for t in timings)
+    for k, w in enumerate(wide):
+        i = len(items) - len(wide) + k
+        solo, _, _ = serve([w], chunk_sweeps=1)
+        assert np.array_equal(out[i][0], solo[0][0]) and np.array_equal(out[i][1], solo[0][1]), "mix vs alone"
+        z, e = alone(w)
+        assert np.array_equal(out[i][0], z) and np.array_equal(out[i][1], e), f"wide request {k} vs plain"
+        P = oracle.Poly(w.problem)
+        beta = P.schedule(w.n_sweeps)[0]
+        zo, eo = P.anneal(w.rule, beta, w.n_reads, w.seed, w.instance_id)
+        parity.check(f"wide request {k}", w.n_reads,
+                     lambda j: out[i][1][j] == eo[j] and np.array_equal(out[i][0][j], zo[j]),
+                     explainer(w.problem, P, w.rule, beta, w.seed, w.instance_id, G=1))
+
+
+def test_cfg5_served_mix_all_reads():
+    # 64 requests of the serving stream (HUIO and dense N = 4096, W = 2001 heat bath; sweeps cut
+    # to 100 and 2) served together with staggered arrivals; every read against the oracle's stored
+    # results
+    from tests.golden import make_full_size as M
+    ws = M.cfg5_workloads()
+    gold = M.read("cfg5")
+    srv = sa.Server(chunk_sweeps=10)
+    tickets = []
+    for k, w in enumerate(ws):
+        tickets.append(srv.submit(w))
+        if k % 8 == 7:
+            time.sleep(0.05)
+    for w, t in zip(ws, tickets):
+        assert srv.wait(t)["status"] == sa.OK
+        z, e = srv.result(t)
+        hdr, eo, ho = gold[f"cfg5-req{w.instance_id}"]
+        P = oracle.Poly(w.problem)
+        assert all(int(e[j]) == P.energy(z[j]) for j in range(w.n_reads))
+        hg = parity.state_hashes(z)
+        beta = M.schedule(P, w)
+        parity.check(f"cfg5 request {w.instance_id}", w.n_reads,
+                     lambda j: e[j] == eo[j] and hg[j] == ho[j],
+                     explainer(w.problem, P, w.rule, beta, w.seed, w.instance_id, G=1))
+    say("stats", srv.stats())
+    srv.close()
