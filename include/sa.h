@@ -134,6 +134,25 @@ int32_t sa_anneal_ex(const sa_instance *inst, const sa_bounds *bounds, const sa_
                      int32_t rule, int32_t n_reads, uint64_t seed, int32_t *out_states,
                      int64_t *out_energies, const sa_opts *opts);
 
+/* ---- the same run without device allocations -------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sa_anneal_ex with device outputs, whose staging (the
+ * packed instance, the inverse temperatures and the sweep schedule) lives in a static device area
+ * of 32 MiB per GPU, set up on the first call on each device and held until the process ends.
+ * The call allocates no device memory (no hipMalloc / hipFree).  Results are those of
+ * sa_anneal_ex with the same arguments.
+ *   opts            required, with device_buffers = 1: out_states, out_energies, init_states and
+ *                   trace_hashes are device pointers on the current device
+ *   return          SA_OK once the work is queued on opts->hip_stream (the call waits only for
+ *                   its own staging copy); SA_ENOMEM if the problem needs more than the 32 MiB
+ *                   area (the message states the bytes needed); the other codes as sa_anneal_ex.
+ * Every call on a GPU uses the same area and overwrites it: calls whose work may overlap on one
+ * GPU (different streams or threads without ordering between them) race.  Calls queued on one
+ * stream are ordered and safe. */
+int32_t sa_anneal_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_schedule *sched,
+                          int32_t rule, int32_t n_reads, uint64_t seed, int32_t *out_states,
+                          int64_t *out_energies, const sa_opts *opts);
+
 /* ---- plans: a canonical instance packed once in device memory, run many times -------------- */
 typedef struct sa_plan sa_plan;
 

@@ -115,6 +115,7 @@ def lib():
         P = C.POINTER
         L.sa_anneal.argtypes = [P(sa_instance), P(sa_bounds), P(sa_schedule), i32, i32, u64, vp, vp]
         L.sa_anneal_ex.argtypes = L.sa_anneal.argtypes + [P(sa_opts)]
+        L.sa_anneal_noalloc.argtypes = L.sa_anneal.argtypes + [P(sa_opts)]
         L.sa_opts_default.argtypes = [P(sa_opts)]
         L.sa_opts_default.restype = None
         L.sa_plan_create.argtypes = [P(sa_instance), P(sa_bounds), i32, P(vp)]
@@ -145,7 +146,7 @@ def lib():
         L.sa_last_error.argtypes = []
         L.sa_last_error.restype = C.c_char_p
         L.sa_version.argtypes = []
-        for name in ("sa_anneal", "sa_anneal_ex", "sa_plan_create", "sa_plan_run", "sa_plan_get_info",
+        for name in ("sa_anneal", "sa_anneal_ex", "sa_anneal_noalloc", "sa_plan_create", "sa_plan_run", "sa_plan_get_info",
                      "sa_plan_last_launch", "sa_auto_schedule", "sa_energy", "sa_version",
                      "sa_batch_create", "sa_batch_run", "sa_batch_wait", "sa_batch_results",
                      "sa_batch_get_info", "sa_anneal_batch", "sa_server_create", "sa_server_submit",
@@ -228,6 +229,24 @@ def anneal(problem, rule: int, n_sweeps: int, n_reads: int, seed: int, beta=None
                             int(seed) & 0xFFFFFFFFFFFFFFFF, _p(z), _p(e), C.byref(opts))
     _check(rc, "sa_anneal_ex")
     return z, e
+
+
+def anneal_device(problem, rule: int, n_sweeps: int, n_reads: int, seed: int, z_out, e_out, beta=None,
+                  stream=None, instance_id=0, sweep_begin=0, sweep_end=0, init_states=None, otm_r=-1.0,
+                  waves_per_replica=0, trace=None, no_alloc=False, lanes_per_update=0):
+    """sa_anneal_ex (or, with no_alloc=True, sa_anneal_noalloc) writing into device tensors z_out
+    (int32 [n_reads, N]) and e_out (int64 [n_reads]); returns once the work is queued."""
+    m = _Marshalled(problem)
+    assert z_out.is_cuda and e_out.is_cuda and z_out.is_contiguous() and e_out.is_contiguous()
+    assert z_out.numel() == n_reads * m.n and e_out.numel() == n_reads
+    assert z_out.dtype.itemsize == 4 and e_out.dtype.itemsize == 8
+    sched, keep = _schedule(n_sweeps, beta)
+    opts = make_opts(instance_id, stream, True, sweep_begin, sweep_end, init_states, otm_r,
+                     waves_per_replica, trace_hashes=trace, lanes_per_update=lanes_per_update)
+    fn = lib().sa_anneal_noalloc if no_alloc else lib().sa_anneal_ex
+    rc = fn(C.byref(m.inst), C.byref(m.bounds), C.byref(sched), int(rule), int(n_reads),
+            int(seed) & 0xFFFFFFFFFFFFFFFF, _p(z_out), _p(e_out), C.byref(opts))
+    _check(rc, "sa_anneal_noalloc" if no_alloc else "sa_anneal_ex")
 
 
 def auto_schedule(problem, n_sweeps: int) -> np.ndarray:
@@ -444,7 +463,7 @@ class Server:
         return {f: getattr(st, f) for f, _ in sa_server_stats._fields_}
 
 
-EXPORTED = ["sa_anneal", "sa_anneal_ex", "sa_opts_default", "sa_plan_create", "sa_plan_run",
+EXPORTED = ["sa_anneal", "sa_anneal_ex", "sa_anneal_noalloc", "sa_opts_default", "sa_plan_create", "sa_plan_run",
             "sa_plan_destroy", "sa_plan_get_info", "sa_plan_last_launch", "sa_auto_schedule",
             "sa_energy", "sa_last_error", "sa_version", "sa_batch_create", "sa_batch_run", "sa_batch_wait",
             "sa_batch_results", "sa_batch_get_info", "sa_batch_destroy", "sa_anneal_batch",
