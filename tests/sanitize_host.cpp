@@ -1,0 +1,139 @@
+// Drives the host-side preparation of the GPU library (csrc/sa_host.cpp: canonicalisation, the
+// int64 bound, the automatic temperatures, packing, window and level schedules) on fixtures that
+// reach its edges, for a build with the address and undefined-behaviour sanitizers.  Prints "ok".
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../paper_2511_17245_amd/csrc/sa_internal.h"
+
+namespace {
+
+int failures = 0;
+void expect(bool c, const char *what) {
+    if (!c) {
+        std::fprintf(stderr, "FAILED: %s\n", what);
+        ++failures;
+    }
+}
+
+struct Raw {
+    int32_t n;
+    std::vector<int64_t> ptr{0};
+    std::vector<int32_t> fac;
+    std::vector<int64_t> coef;
+    std::vector<int32_t> lo, hi;
+    void term(int64_t c, std::vector<int32_t> v) {
+        fac.insert(fac.end(), v.begin(), v.end());
+        ptr.push_back((int64_t)fac.size());
+        coef.push_back(c);
+    }
+    sa_instance inst() const { return {n, (int64_t)coef.size(), ptr.data(), fac.data(), coef.data()}; }
+    sa_bounds bounds() const { return {lo.data(), hi.data()}; }
+};
+
+int prepare(const Raw &r, sa::Packed &pk, std::string &err) {
+    sa_instance in = r.inst();
+    sa_bounds bd = r.bounds();
+    sa::Canonical c;
+    int rc = sa::canonicalize(&in, &bd, c, err);
+    if (rc != SA_OK) return rc;
+    double bound = 0;
+    rc = sa::check_int64_bound(c, err, &bound);
+    if (rc != SA_OK) return rc;
+    double ti = 0, tf = 0;
+    if (sa::auto_temperatures(c, &ti, &tf, err) == SA_OK) {
+        std::vector<double> beta(7);
+        sa::geometric_betas(ti, tf, 7, beta.data());
+        expect(beta[0] > 0 && beta[6] >= beta[0], "betas increase");
+    }
+    (void)sa::dE_fits_32(c);
+    (void)sa::coefs_fit_32(c);
+    return sa::pack(c, pk, err);
+}
+
+void schedules(const sa::Packed &pk) {
+    for (int G : {1, 2, 4, 8, 16}) {
+        std::vector<sa::SchedRec> s;
+        const int32_t nw = sa::build_schedule(pk, G, s);
+        expect((int64_t)s.size() == (int64_t)nw * G, "schedule size");
+    }
+    std::vector<int32_t> start;
+    std::vector<sa::SchedRec> slots;
+    const int32_t nl = sa::build_levels(pk, start, slots);
+    expect((int32_t)start.size() == nl + 1 && start.back() == (int32_t)slots.size(), "level offsets");
+}
+
+}  // namespace
+
+int main() {
+    std::string err;
+    // random HUIO with powers, repeated multisets, zero and cancelling coefficients, fixed variables
+    std::mt19937_64 g(7);
+    for (int rep = 0; rep < 20; ++rep) {
+        Raw r;
+        r.n = 1 + (int32_t)(g() % 60);
+        for (int32_t i = 0; i < r.n; ++i) {
+            const int32_t l = -(int32_t)(g() % 50);
+            r.lo.push_back(l);
+            r.hi.push_back(i % 7 == 3 ? l : l + (int32_t)(g() % 100));
+        }
+        const int m = (int)(g() % 200);
+        for (int t = 0; t < m; ++t) {
+            std::vector<int32_t> v(1 + g() % 5);
+            for (auto &x : v) x = (int32_t)(g() % r.n);
+            const int64_t c = (int64_t)(g() % 11) - 5;
+            r.term(c, v);
+            if (t % 9 == 0) r.term(-c, v);   // cancels the previous term
+        }
+        sa::Packed pk;
+        const int rc = prepare(r, pk, err);
+        expect(rc == SA_OK || rc == SA_ERANGE, "random problem prepares");
+        if (rc == SA_OK) schedules(pk);
+    }
+    // dense QUIO (stored as a matrix) with int8 and int32 couplings
+    for (int64_t jmax : {10LL, 100000LL}) {
+        Raw r;
+        r.n = 40;
+        r.lo.assign(40, -5);
+        r.hi.assign(40, 5);
+        for (int32_t i = 0; i < 40; ++i)
+            for (int32_t j = i; j < 40; ++j) r.term((int64_t)(g() % (2 * jmax + 1)) - jmax, {i, j});
+        sa::Packed pk;
+        expect(prepare(r, pk, err) == SA_OK && pk.dense, "dense problem packs as a matrix");
+        schedules(pk);
+    }
+    // the int64 bound at its edge: |J| z^e summed just below and at 2^62
+    {
+        Raw r;
+        r.n = 1;
+        r.lo = {-(1 << 30)};
+        r.hi = {(1 << 30) - 2};
+        r.term(1LL << 2, {0, 0});   // 4 * 2^60 = 2^62: rejected
+        sa::Packed pk;
+        expect(prepare(r, pk, err) == SA_ERANGE, "bound at 2^62 is rejected");
+        Raw q = r;
+        q.coef[0] = 3;              // 3 * 2^60 < 2^62: accepted
+        expect(prepare(q, pk, err) == SA_OK, "bound below 2^62 is accepted");
+    }
+    // malformed inputs
+    {
+        Raw r;
+        r.n = 2;
+        r.lo = {0, 0};
+        r.hi = {1, 1};
+        r.term(1, {0, 5});          // index out of range
+        sa::Packed pk;
+        expect(prepare(r, pk, err) == SA_EINVAL, "index out of range is rejected");
+        Raw q;
+        q.n = 1;
+        q.lo = {0};
+        q.hi = {2147483647};        // u - l above 2^31 - 2
+        expect(prepare(q, pk, err) == SA_EINVAL, "range too wide is rejected");
+    }
+    if (failures) return 1;
+    std::printf("ok\n");
+    return 0;
+}
