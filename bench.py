@@ -58,6 +58,12 @@ def parse():
                     help="oracle reads behind the target energy and the CPU time (0: automatic)")
     ap.add_argument("--no-closed-form", action="store_true",
                     help="cfg2: skip timing the closed-form heat-bath draw beside the enumeration")
+    ap.add_argument("--no-ttt", action="store_true",
+                    help="cfg2: skip the time-to-target grid in the default line")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="cfg2: skip the batched-versus-plain measurement in the default line")
+    ap.add_argument("--lanes-per-update", type=int, default=0,
+                    help="heat bath: 4 (quad kernel), 64 (one wavefront per update) or 0 (automatic)")
     ap.add_argument("--cpu-reads", type=int, default=16)
     ap.add_argument("--cpu-sweeps", type=int, default=0, help="0: the whole schedule")
     return ap.parse_args()
@@ -85,7 +91,8 @@ def workload(args):
 
 # the sources that define the device program and the data it reads: kernels, their argument
 # layout, the instance packing and the launch choice (geometry and waves per replica)
-KERNEL_SOURCES = ("sa_device.h", "sa_kernels.hip", "sa_kernels_heat_bath.hip", "sa_kernels_heat_bath_closed.hip",
+KERNEL_SOURCES = ("sa_device.h", "sa_quad.h", "sa_kernels_quad.hip", "sa_kernels.hip", "sa_kernels_heat_bath.hip",
+                  "sa_kernels_heat_bath_closed.hip",
                   "sa_kernels_metropolis.hip", "sa_kernels_otm.hip", "sa_kernels_batch.hip",
                   "sa_kernels_batch16.hip", "sa_kernel_table.h", "sa_internal.h", "sa_host.cpp",
                   "sa_api.cpp")
@@ -132,8 +139,28 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": mib << 20}), flush=True)
 
 
-def cpu_baseline(w, beta, n_reads, n_sweeps):
-    """The oracle (paper's coefficient-cache mode), as it stands, on a bounded sample."""
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def cpu_baseline(w, beta, n_reads, n_sweeps, one_core_sweeps=0):
+    """The oracle (paper's coefficient-cache mode), as it stands, on a bounded sample: all usable
+    host threads over n_reads reads, and one thread over one read (the first one_core_sweeps
+    sweeps of the schedule)."""
     import numpy as np
     import oracle
     P = oracle.Poly(w.problem)
@@ -145,10 +172,75 @@ def cpu_baseline(w, beta, n_reads, n_sweeps):
     P.anneal(w.rule, b, n_reads, w.seed, w.instance_id, cache_mode=1, n_threads=threads)
     dt = time.perf_counter() - t0
     upd = n_reads * n_sweeps * w.problem.n_vars
-    return {"value": upd / dt, "unit": "updates/s", "cores": min(threads, n_reads), "kind": "oracle",
-            "sample": f"{n_reads} reads x {'all' if n_sweeps == w.n_sweeps else 'first ' + str(n_sweeps) + ' of'} "
-                      f"{w.n_sweeps} sweeps of the same workload "
-                      f"({upd:.3g} updates, {dt:.1f} s, coefficient-cache mode)"}
+    out = {"value": upd / dt, "unit": "updates/s", "cores": min(threads, n_reads), "kind": "oracle",
+           "sample": f"{n_reads} reads x {'all' if n_sweeps == w.n_sweeps else 'first ' + str(n_sweeps) + ' of'} "
+                     f"{w.n_sweeps} sweeps of the same workload "
+                     f"({upd:.3g} updates, {dt:.1f} s, coefficient-cache mode, {min(threads, n_reads)} threads)"}
+    out.update(host_cpu())
+    if one_core_sweeps > 0:
+        s1 = min(one_core_sweeps, w.n_sweeps)
+        t0 = time.perf_counter()
+        P.anneal(w.rule, np.ascontiguousarray(beta[:s1]), 1, w.seed, w.instance_id, cache_mode=1, n_threads=1)
+        d1 = time.perf_counter() - t0
+        u1 = s1 * w.problem.n_vars
+        out["one_core"] = {"value": u1 / d1, "unit": "updates/s", "cores": 1,
+                           "sample": f"1 read x first {s1} of {w.n_sweeps} sweeps ({u1:.3g} updates, {d1:.1f} s)"}
+    return out
+
+
+def stored_oracle_energies(name):
+    """Final energies of every read that the oracle recorded for a full-size workload
+    (tests/golden/full_size_<name>.txt, written by the oracle alone), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"full_size_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    e = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or line.startswith("workload"):
+                continue
+            e.append(int(line.split()[1]))
+    return np.array(e, np.int64)
+
+
+def ttt_grid(plan, w, R, lanes, e_target, e_best):
+    """GPU runs of all reads at 1/8 .. 2 times the sweeps (automatic schedule of each length): the
+    time to target is the kernel time of the shortest run whose median final energy reaches
+    e_target; TTS99 to e_best is t_run ln(0.01) / ln(1 - p_hit), minimised over the grid."""
+    import numpy as np
+    import torch
+    from paper_2511_17245_amd import sa
+    prob, S = w.problem, w.n_sweeps
+    stream = torch.cuda.current_stream()
+    z = torch.empty((R, prob.n_vars), dtype=torch.int32, device="cuda")
+    e = torch.empty(R, dtype=torch.int64, device="cuda")
+    grid = []
+    for f in (0.125, 0.25, 0.5, 1.0, 2.0):
+        Sg = max(2, int(round(f * S)))
+        beta = sa.auto_schedule(prob, Sg)
+        plan.run_device(Sg, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream, instance_id=w.instance_id,
+                        lanes_per_update=lanes)
+        torch.cuda.synchronize()   # warm (also stages beta)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.run_device(Sg, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream, instance_id=w.instance_id,
+                        lanes_per_update=lanes)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        eh = e.cpu().numpy()
+        p_hit = float(np.mean(eh <= e_best))
+        tts99 = (ms / 1e3) * (math.log(0.01) / math.log(1.0 - p_hit)) if 0.0 < p_hit < 1.0 else \
+            (ms / 1e3 if p_hit >= 1.0 else None)
+        grid.append({"sweeps": Sg, "gpu_ms": ms, "median_energy": float(np.median(eh)), "min_energy": int(eh.min()),
+                     "p_hit_best": p_hit, "tts99_s": tts99})
+        print(f"[bench] ttt grid {Sg} sweeps: {ms:.1f} ms, median {np.median(eh):.0f}", file=sys.stderr, flush=True)
+    hit = next((g for g in grid if g["median_energy"] <= e_target), None)
+    tts = [g["tts99_s"] for g in grid if g["tts99_s"] is not None]
+    return {"target_median_energy": e_target, "best_energy": e_best,
+            "ttt_s": hit["gpu_ms"] / 1e3 if hit else None, "ttt_sweeps": hit["sweeps"] if hit else None,
+            "tts99_best_s": min(tts) if tts else None, "grid": grid}
 
 
 def bench_ttt(args):
@@ -372,41 +464,42 @@ def bench_suite(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args):
-    """512 problems of uneven size, width, order and rule in one persistent (graph-replayed)
-    launch, against plain per-instance launches of a seeded sample of the same problems."""
+def batched_vs_plain(steps, warmup, plain_sample, sweeps=0):
+    """512 problems of uneven size, width, order and rule in one persistent (graph-replayed,
+    autotuned) launch, against plain per-instance launches of a seeded sample of the same problems
+    (one wavefront per update: the update code the batch runs, so the outputs must be identical)."""
     import numpy as np
     import torch
     from paper_2511_17245_amd import inputs as I
     from paper_2511_17245_amd import sa
 
     items = I.cfg4_batch()
-    if args.sweeps:
+    if sweeps:
         for w in items:
-            w.n_sweeps = args.sweeps
+            w.n_sweeps = sweeps
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         t0 = time.perf_counter()
         batch = sa.Batch(items, autotune=True, use_graph=True, stream=stream.cuda_stream)
         create_s = time.perf_counter() - t0
         info = batch.info()
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             batch.run()
         batch.wait()
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record(stream)
-        for i in range(args.steps):
+        for i in range(steps):
             batch.run()
-            print(f"[bench] queued batch {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+            print(f"[bench] queued batch {i + 1}/{steps}", file=sys.stderr, flush=True)
         stop.record(stream)
         stream.synchronize()
-        ms = start.elapsed_time(stop) / args.steps
+        ms = start.elapsed_time(stop) / steps
         batched = batch.results()
         value = info["total_updates"] / (ms / 1e3)
 
         # plain launches, one problem at a time, on a seeded sample
         rng = np.random.Generator(np.random.PCG64(4242))
-        sample = np.sort(rng.choice(len(items), size=min(args.plain_sample, len(items)), replace=False))
+        sample = np.sort(rng.choice(len(items), size=min(plain_sample, len(items)), replace=False))
         plain_ms, plain_upd, same = 0.0, 0, True
         for i in sample:
             w = items[i]
@@ -415,12 +508,12 @@ def bench_batch(args):
             e = torch.empty(w.n_reads, dtype=torch.int64, device="cuda")
             beta = w.beta if w.beta is not None else sa.auto_schedule(w.problem, w.n_sweeps)
             plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
-                            instance_id=w.instance_id)   # stages beta; not timed
+                            instance_id=w.instance_id, lanes_per_update=64)   # stages beta; not timed
             stream.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
             plan.run_device(w.n_sweeps, w.n_reads, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
-                            instance_id=w.instance_id)
+                            instance_id=w.instance_id, lanes_per_update=64)
             b.record(stream)
             stream.synchronize()
             plain_ms += a.elapsed_time(b)
@@ -429,17 +522,26 @@ def bench_batch(args):
                 np.array_equal(e.cpu().numpy(), batched[i][1])
             plan.close()
         plain = plain_upd / (plain_ms / 1e3)
+        batch.close()
+    return {"value": value, "unit": "updates/s", "ms_per_step": ms, "steps": steps,
+            "workload": "512 mixed QUIO/HUIO problems, N 50-5000, widths 2-1000, 32 reads, "
+                        f"{sweeps or 1000} sweeps, one persistent graph-replayed launch",
+            "batch": info, "create_s": create_s,
+            "plain": {"value": plain, "unit": "updates/s", "sample_problems": int(len(sample)),
+                      "sample_ms": plain_ms, "identical_outputs": bool(same)},
+            "batched_over_plain": value / plain}
+
+
+def bench_batch(args):
+    r = batched_vs_plain(args.steps, args.warmup, args.plain_sample, args.sweeps)
     out = {
         "metric": "single-variable updates/sec at 1 GPU (batched form)",
-        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": r["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64+f64", "data": "synthetic",
-        "config": {"workload": "512 mixed QUIO/HUIO problems, N 50-5000, widths 2-1000, 32 reads, 1000 sweeps, "
-                               "one persistent graph-replayed launch", "batch": info,
-                   "create_s": create_s},
-        "plain": {"value": plain, "unit": "updates/s", "sample_problems": int(len(sample)),
-                  "sample_ms": plain_ms, "identical_outputs": bool(same)},
-        "batched_over_plain": value / plain,
+        "config": {"workload": r["workload"], "batch": r["batch"], "create_s": r["create_s"]},
+        "plain": r["plain"],
+        "batched_over_plain": r["batched_over_plain"],
     }
     print(json.dumps(out), flush=True)
 
@@ -578,9 +680,12 @@ def main():
     e = torch.empty(R, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    lanes = args.lanes_per_update
+
     def step():
         plan.run_device(S, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
-                        instance_id=w.instance_id, waves_per_replica=args.waves_per_replica)
+                        instance_id=w.instance_id, waves_per_replica=args.waves_per_replica,
+                        lanes_per_update=lanes)
 
     for _ in range(args.warmup):
         step()
@@ -608,11 +713,15 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic}
     else:
-        # Metropolis / OTM: instance bytes streamed per update (incidence records + coefficients)
-        rec_bytes = info["n_incidences"] * (16 + 8) / n
-        achieved = updates * rec_bytes / (ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic}
+        # Metropolis / OTM: the incidence records come from the caches (measured HBM traffic is a
+        # small fraction of them), and the counters show VALU issue as the busy resource: the
+        # bound reported is VALU issue, from the counted instructions per update (committed
+        # counter record of the same kernel sources) at this run's rate; null without a record
+        crec = counter_record(f"{args.config}:{S}:{R}")
+        vi = crec["valu_insts_per_update"] * value / 1e9 if crec and crec.get("valu_insts_per_update") else None
+        roof = {"bound": "alu", "achieved": vi, "peak": VALU_ISSUE_PEAK_G, "unit": "G wave-instructions/s",
+                "frac": vi / VALU_ISSUE_PEAK_G if vi is not None else None, "traffic": traffic,
+                "basis": "counted VALU instructions per update x update rate (issue-bound)"}
 
     out = {
         "metric": "single-variable updates/sec at 1 GPU",
@@ -649,7 +758,8 @@ def main():
 
         def cstep():
             cplan.run_device(S, R, w.seed, z, e, beta=beta, stream=stream.cuda_stream,
-                             instance_id=w.instance_id, waves_per_replica=args.waves_per_replica)
+                             instance_id=w.instance_id, waves_per_replica=args.waves_per_replica,
+                             lanes_per_update=lanes)
 
         cstep()
         torch.cuda.synchronize()
@@ -664,10 +774,28 @@ def main():
                                         "speedup_over_enumeration": ms / cms, "launch": cplan.last_launch(),
                                         "mean_final_energy": float(np.mean(ce)), "min_final_energy": int(ce.min())}
         cplan.close()
+    if args.config == "cfg2" and not args.no_ttt and S == 2000 and R == 256:
+        # time to target (the paper's energy-versus-time protocol, Sec. 4.4): the target is the
+        # median of the oracle's final energies over all reads of this workload (stored by the
+        # oracle alone, tests/golden/full_size_cfg2.txt), the best of them for TTS99
+        eo = stored_oracle_energies("cfg2")
+        if eo is not None and len(eo) == R:
+            print("[bench] time-to-target grid", file=sys.stderr, flush=True)
+            out["time_to_target"] = ttt_grid(plan, w, R, lanes, float(np.median(eo)), int(eo.min()))
+    plan.close()
+    if args.config == "cfg2" and not args.no_batch:
+        print("[bench] batched versus plain (512 problems)", file=sys.stderr, flush=True)
+        out["batched_vs_plain"] = batched_vs_plain(1, 1, 24)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, beta, min(args.cpu_reads, R),
-                                           S if args.cpu_sweeps <= 0 else min(args.cpu_sweeps, S))
+                                           S if args.cpu_sweeps <= 0 else min(args.cpu_sweeps, S),
+                                           one_core_sweeps=500 if args.config.startswith("cfg2") else 1000)
+        tt = out.get("time_to_target")
+        if tt and tt.get("ttt_sweeps"):
+            # the oracle's time for the same grid run (its own median is the target at S sweeps),
+            # at its all-core rate
+            tt["oracle_s_at_ttt_sweeps"] = R * tt["ttt_sweeps"] * n / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 
 

@@ -70,6 +70,7 @@ std::vector<std::pair<const void *, size_t>> packed_parts(const Packed &pk) {
          pk.jbytes == 1 ? pk.jd8.size() : pk.jd32.size() * sizeof(int32_t)},
         {pk.h.data(), pk.h.size() * sizeof(int64_t)},
         {pk.d.data(), pk.d.size() * sizeof(int64_t)},
+        {pk.pair.data(), pk.pair.size() * sizeof(PairRec)},
     };
 }
 }  // namespace
@@ -78,7 +79,7 @@ PackedLayout packed_layout(const Packed &pk) {
     // the incidence records and their coefficients are followed by one zero record, which lanes
     // past the end of a row read
     const auto parts = packed_parts(pk);
-    const size_t extra[PackedLayout::kParts] = {0, 0, sizeof(IncRec), sizeof(int64_t), 0, 0, 0, 0, 0, 0, 0};
+    const size_t extra[PackedLayout::kParts] = {0, 0, sizeof(IncRec), sizeof(int64_t), 0, 0, 0, 0, 0, 0, 0, 0};
     PackedLayout L;
     size_t total = 0;
     for (int i = 0; i < PackedLayout::kParts; ++i) {
@@ -118,6 +119,7 @@ void bind_packed(const Packed &pk, const PackedLayout &L, char *b, DevProblem &d
     d.jd = (const void *)(b + L.off[8]);
     d.h = (const int64_t *)(b + L.off[9]);
     d.d = (const int64_t *)(b + L.off[10]);
+    d.pair = pk.pair_row.empty() ? nullptr : (const PairRec *)(b + L.off[11]);
 }
 
 }  // namespace sa
@@ -272,7 +274,7 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
     if (lv.n_levels < 0) {
         std::vector<int32_t> start;
         std::vector<SchedRec> slots;
-        const int32_t nl = build_levels(plan->packed, start, slots);
+        const int32_t nl = build_levels(plan->packed, kQuadWaves * 16, start, slots);
         const size_t sb = align256(start.size() * sizeof(int32_t));
         const size_t bytes = sb + std::max<size_t>(slots.size(), 1) * sizeof(SchedRec);
         hipError_t e = hipMalloc(&lv.dev, bytes);
@@ -508,6 +510,7 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
         a.n_win = sc->n_win;
         a.win_waves = lc.win_waves;
         a.waves_per_group = lc.waves_per_group;
+        a.dense_cache = lc.dense_cache ? 1 : 0;
         std::string err;
         rc = sa::launch_anneal(plan->rule, a, lc, stream, err);
         if (rc == SA_OK && t_dev) rc = sa::launch_trace_prefix(t_dev, n_reads, n_traced, stream, err);

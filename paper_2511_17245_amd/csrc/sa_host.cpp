@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <set>
 
 #include "sa_internal.h"
 
@@ -417,6 +418,36 @@ int pack(const Canonical &c, Packed &p, std::string &err) {
     for (int64_t t = 0; t <= nt; ++t) p.t_off[t] = (int32_t)c.t_off[t];
     p.t_var = c.t_var;
     p.t_coef = c.t_coef;
+    // compact pair records: every incidence is z_k to the first power with at most one other
+    // factor, and every coefficient and linear sum fits int32
+    bool compact = p.max_exp <= 1 && p.max_other <= 1;
+    for (size_t q = 0; compact && q < p.inc.size(); ++q)
+        compact = p.inc_coef[q] >= INT32_MIN && p.inc_coef[q] <= INT32_MAX;
+    if (compact) {
+        p.pair_row.assign(n, 0);
+        p.pair_deg.assign(n, 0);
+        p.pair_h.assign(n, 0);
+        for (int32_t k = 0; k < n && compact; ++k) {
+            const VarRec &vr = p.var[k];
+            int64_t h = 0;
+            p.pair_row[k] = (int32_t)p.pair.size();
+            for (int32_t q = vr.row; q < vr.row + vr.deg; ++q) {
+                if ((p.inc[q].meta >> 8) == 0)
+                    h += p.inc_coef[q];
+                else
+                    p.pair.push_back(PairRec{p.inc[q].o[0], (int32_t)p.inc_coef[q]});
+            }
+            p.pair_deg[k] = (int32_t)p.pair.size() - p.pair_row[k];
+            compact = h >= INT32_MIN && h <= INT32_MAX;
+            p.pair_h[k] = (int32_t)h;
+        }
+        if (!compact) {
+            p.pair.clear();
+            p.pair_row.clear();
+            p.pair_deg.clear();
+            p.pair_h.clear();
+        }
+    }
     return SA_OK;
 }
 
@@ -466,20 +497,24 @@ int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out) {
 
 namespace sa {
 
-int32_t build_levels(const Packed &p, std::vector<int32_t> &level_start, std::vector<SchedRec> &slots) {
+int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level_start,
+                     std::vector<SchedRec> &slots) {
     const int32_t n = p.n;
-    std::vector<int32_t> level(n, -1);
-    int32_t n_levels = 0;
+    // lower-index neighbours of every variable that is not fixed (a fixed variable never changes:
+    // it orders nothing)
+    std::vector<std::vector<int32_t>> lower((size_t)n), upper((size_t)n);
     for (int32_t k = 0; k < n; ++k) {
         const VarRec &vr = p.var[k];
-        if (vr.width == 1) continue;   // a fixed variable never changes: it orders nothing
-        int32_t lv = 0;
+        if (vr.width == 1) continue;
         auto see = [&](int32_t j) {
-            if (j < k && level[j] >= lv) lv = level[j] + 1;
+            if (j != k && p.var[j].width > 1) {
+                if (j < k) lower[(size_t)k].push_back(j);
+                else upper[(size_t)k].push_back(j);
+            }
         };
         if (p.dense) {
             // every pair is coupled: each variable waits for all earlier ones
-            for (int32_t j = 0; j < k; ++j) see(j);
+            for (int32_t j = 0; j < n; ++j) see(j);
         } else {
             for (int32_t q = vr.row; q < vr.row + vr.deg; ++q) {
                 const IncRec &r = p.inc[q];
@@ -491,20 +526,69 @@ int32_t build_levels(const Packed &p, std::vector<int32_t> &level_start, std::ve
                 }
             }
         }
-        level[k] = lv;
+        auto &lo = lower[(size_t)k];
+        std::sort(lo.begin(), lo.end());
+        lo.erase(std::unique(lo.begin(), lo.end()), lo.end());
+        auto &up = upper[(size_t)k];
+        std::sort(up.begin(), up.end());
+        up.erase(std::unique(up.begin(), up.end()), up.end());
+    }
+    // earliest level (longest chain of lower-index neighbours below k) and latest level (the
+    // number of levels minus the longest chain above k)
+    std::vector<int32_t> asap((size_t)n, -1), down((size_t)n, 0);
+    int32_t n_levels = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        if (p.var[k].width == 1) continue;
+        int32_t lv = 0;
+        for (int32_t j : lower[(size_t)k]) lv = std::max(lv, asap[(size_t)j] + 1);
+        asap[(size_t)k] = lv;
         n_levels = std::max(n_levels, lv + 1);
+    }
+    for (int32_t k = n - 1; k >= 0; --k) {
+        if (p.var[k].width == 1) continue;
+        int32_t d = 0;
+        for (int32_t j : upper[(size_t)k]) d = std::max(d, down[(size_t)j] + 1);
+        down[(size_t)k] = d;
+    }
+    // level by level: every variable that must go now (its latest level) goes, and the level is
+    // filled up to a whole number of rounds of `quads` updates with the ready variables whose
+    // latest level is nearest; a variable is ready once its lower-index neighbours are placed
+    std::vector<int32_t> level((size_t)n, -1), waiting((size_t)n, 0);
+    std::set<std::pair<int32_t, int32_t>> ready;   // (latest level, index)
+    for (int32_t k = 0; k < n; ++k) {
+        if (p.var[k].width == 1) continue;
+        waiting[(size_t)k] = (int32_t)lower[(size_t)k].size();
+        if (waiting[(size_t)k] == 0) ready.insert({n_levels - 1 - down[(size_t)k], k});
+    }
+    const int32_t Q = std::max<int32_t>(quads, 1);
+    for (int32_t l = 0; l < n_levels; ++l) {
+        std::vector<int32_t> take;
+        auto it = ready.begin();
+        while (it != ready.end() && it->first == l) take.push_back((it++)->second);
+        const size_t target = (take.size() + (size_t)Q - 1) / (size_t)Q * (size_t)Q;
+        while (it != ready.end() && take.size() < target) take.push_back((it++)->second);
+        ready.erase(ready.begin(), it);
+        for (int32_t k : take) level[(size_t)k] = l;
+        for (int32_t k : take)
+            for (int32_t j : upper[(size_t)k])
+                if (--waiting[(size_t)j] == 0) ready.insert({n_levels - 1 - down[(size_t)j], j});
     }
     // counting sort by level; index order inside a level
     level_start.assign((size_t)n_levels + 1, 0);
     for (int32_t k = 0; k < n; ++k)
-        if (level[k] >= 0) level_start[(size_t)level[k] + 1]++;
+        if (level[(size_t)k] >= 0) level_start[(size_t)level[(size_t)k] + 1]++;
     for (int32_t l = 0; l < n_levels; ++l) level_start[(size_t)l + 1] += level_start[(size_t)l];
     slots.assign((size_t)level_start[(size_t)n_levels], SchedRec{-1, 0, 1, 0, 0, 0u, {0, 0}});
     std::vector<int32_t> fill(level_start.begin(), level_start.end() - 1);
     for (int32_t k = 0; k < n; ++k) {
-        if (level[k] < 0) continue;
+        if (level[(size_t)k] < 0) continue;
         const VarRec &vr = p.var[k];
-        slots[(size_t)fill[(size_t)level[k]]++] = SchedRec{k, vr.lo, vr.width, vr.row, vr.deg, p.emask[k], {0, 0}};
+        // with compact pair records the slot points at the variable's pairs and carries its
+        // linear coefficient
+        slots[(size_t)fill[(size_t)level[(size_t)k]]++] =
+            p.pair.empty() && p.pair_row.empty()
+                ? SchedRec{k, vr.lo, vr.width, vr.row, vr.deg, p.emask[k], {0, 0}}
+                : SchedRec{k, vr.lo, vr.width, p.pair_row[k], p.pair_deg[k], p.emask[k], {p.pair_h[k], 0}};
     }
     return n_levels;
 }

@@ -59,6 +59,12 @@ struct IncRec {
     int32_t o[3];
 };
 
+// Compact incidence record of a pair term J z_k z_j (index of the other factor j, coefficient J).
+struct PairRec {
+    int32_t j;
+    int32_t J;
+};
+
 // Host-side packed image of a plan (uploaded as one device allocation).
 struct Packed {
     int32_t n = 0;
@@ -83,6 +89,10 @@ struct Packed {
     std::vector<int32_t> jd32;
     std::vector<int64_t> h, d;
     int64_t n_pairs = 0;
+    // compact form of a multilinear QUIO whose coefficients fit int32 (empty otherwise): per
+    // variable its pair records (row pair_row[k], pair_deg[k] of them) and its linear coefficient
+    std::vector<PairRec> pair;
+    std::vector<int32_t> pair_row, pair_deg, pair_h;
 };
 int pack(const Canonical &c, Packed &out, std::string &err);
 int maxe_class_of(int32_t max_exp);
@@ -101,13 +111,16 @@ struct SchedRec {
 // (slot g * n_win + w).  Returns the number of windows.
 int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out);
 
-// Dependency levels of one sweep: level l holds, in index order, the variables (not fixed) all of
-// whose lower-index neighbours lie in earlier levels.  Updating the levels one after another, the
-// variables of a level in any order or at once, reads every neighbour exactly as the sequential
-// index-order sweep does: a lower-index neighbour already updated in this sweep, a higher-index
-// one not yet.  Returns the number of levels; slots are level-major, level_start has one more
-// entry than there are levels.
-int32_t build_levels(const Packed &p, std::vector<int32_t> &level_start, std::vector<SchedRec> &slots);
+// Dependency levels of one sweep: a level holds, in index order, variables (not fixed) none of
+// which shares a term with another, each placed after all of its lower-index neighbours' levels.
+// Updating the levels one after another, the variables of a level in any order or at once, reads
+// every neighbour exactly as the sequential index-order sweep does: a lower-index neighbour
+// already updated in this sweep, a higher-index one not yet.  The number of levels is the
+// longest chain of neighbours in index order; each variable goes to a level between its earliest
+// and its latest, and levels are filled up to whole rounds of `quads` updates where the slack
+// allows.  Returns the number of levels; slots are level-major, level_start has one more entry.
+int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level_start,
+                     std::vector<SchedRec> &slots);
 
 // Device view of a packed plan.
 struct DevProblem {
@@ -131,6 +144,7 @@ struct DevProblem {
     const void *jd;
     const int64_t *h;
     const int64_t *d;
+    const PairRec *pair;     // compact pair records (nullptr when the problem has none)
 };
 
 // Kernel arguments of one annealing launch.
@@ -151,6 +165,8 @@ struct AnnealArgs {
     const int32_t *z_init;   // device, n_reads * n, or nullptr
     int32_t *z_out;          // device, n_reads * n (also the working state when not in LDS)
     int64_t *e_out;          // device, n_reads
+    int32_t dense_cache;     // 1: dense form with one wave per replica and the state in LDS keeps the
+                             // coefficient cache c1 (int64 per variable) in LDS after the states
     uint64_t *trace;         // device, n_reads * (s_end - s_begin) zeroed words, or nullptr: each
                              // wave adds its share of the state hash's change per sweep (and of the
                              // initial state's hash into the first sweep); a prefix pass then turns
@@ -193,13 +209,14 @@ struct LaunchChoice {
     int reg_chunk = 0;         // heat bath: weights per lane kept in registers (0: recomputed)
     int maxe_class = 1;        // kernel's largest exponent (1, 2, 4 or 16)
     bool narrow = false;       // energy differences in 32-bit arithmetic
+    bool dense_cache = false;  // dense form: coefficient cache in LDS (one wave per replica)
     int variant = 0;
 };
 
 // Byte layout of a packed instance in one device area, each part 256-byte aligned (the records
 // and their coefficients are followed by one zero record).
 struct PackedLayout {
-    static constexpr int kParts = 11;
+    static constexpr int kParts = 12;
     size_t off[kParts];
     size_t total;
 };

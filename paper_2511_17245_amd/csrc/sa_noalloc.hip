@@ -98,7 +98,7 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     std::vector<int32_t> lv_start;
     std::vector<sa::SchedRec> lv_slots;
     int32_t n_levels = 0;
-    if (eligible && G == 0 && opts.lanes_per_update != 64) n_levels = sa::build_levels(pk, lv_start, lv_slots);
+    if (eligible && G == 0 && opts.lanes_per_update != 64) n_levels = sa::build_levels(pk, sa::kQuadWaves * 16, lv_start, lv_slots);
     const int lanes = sa::choose_lanes(opts.lanes_per_update, G, eligible, n_levels, (int32_t)lv_slots.size());
     if (lanes < 0) return SA_EINVAL;
 
@@ -163,6 +163,7 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     a.n_win = n_win;
     a.win_waves = lc.win_waves;
     a.waves_per_group = lc.waves_per_group;
+    a.dense_cache = lc.dense_cache ? 1 : 0;
     if (a.trace) {
         rc = sa::launch_zero_u64(a.trace, (int64_t)n_reads * (s1 - s0), stream, err);
         if (rc != SA_OK) return sa::fail(rc, err);

@@ -171,6 +171,26 @@ __device__ __forceinline__ void quad_coeffs(const DevProblem &P, const int32_t *
     for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? quad_sum<Acc>(part[m]) : (Acc)0;
 }
 
+// a_k^(1) of variable k from its compact pair records (multilinear QUIO): h_k + sum_j J_kj z_j.
+// Lane q takes records q, q + 4, ...; sixteen records of the row are loaded before any is used,
+// so a typical row costs one round trip to memory and one to LDS.
+template <typename Acc>
+__device__ __forceinline__ Acc quad_a1_pairs(const DevProblem &P, const int32_t *z, int32_t row, int32_t deg,
+                                             int32_t h, int ql) {
+    Acc part = ql == 0 ? (Acc)(int64_t)h : (Acc)0;
+    for (int32_t c0 = 0; c0 < deg; c0 += 16) {
+        PairRec pr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t i = c0 + 4 * u + ql;
+            pr[u] = i < deg ? P.pair[row + i] : PairRec{0, 0};   // J = 0 past the row
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) part += (Acc)(int64_t)pr[u].J * (Acc)(int64_t)z[pr[u].j];
+    }
+    return quad_sum<Acc>(part);
+}
+
 // kRule: SA_HEAT_BATH, or SA_HEAT_BATH_CLOSED (the O(1) draw of Sec. 3.3.2 for variables whose
 // energy difference is linear, the enumeration for the others).  kR: values per lane (W <= 4 kR).
 template <int kRule, int kR, int kMaxE, typename Acc, int kWaves>
@@ -232,6 +252,7 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                     ms.row = 0;
                     ms.deg = 0;
                     ms.emask = 0;
+                    ms.pad[0] = 0;
                 }
                 uint32_t y0 = (uint32_t)ms.k, y1 = (uint32_t)s, y2 = (uint32_t)read, y3 = A.instance_id;
                 philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
@@ -246,12 +267,18 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                     const int32_t row = (int32_t)from_q((uint32_t)ms.row);
                     const int32_t deg = (int32_t)from_q((uint32_t)ms.deg);
                     const uint32_t emask = from_q(ms.emask);
+                    const int32_t h = (int32_t)from_q((uint32_t)ms.pad[0]);
                     const uint32_t x1 = from_q(y1), x2 = from_q(y2), x3 = from_q(y3);
                     if (idx < b1) {
                         const double U = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
                         const int64_t zk = z[k];
                         Coeffs<kMaxE, Acc> C;
-                        quad_coeffs<kMaxE, Acc>(P, z, row, deg, emask, ql, C);
+                        if (kMaxE == 1 && P.pair) {
+                            C.a[0] = 0;
+                            C.a[1] = quad_a1_pairs<Acc>(P, z, row, deg, h, ql);
+                        } else {
+                            quad_coeffs<kMaxE, Acc>(P, z, row, deg, emask, ql, C);
+                        }
                         const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
                         int64_t v;
                         if (kRule == SA_HEAT_BATH_CLOSED && linear) {

@@ -62,8 +62,29 @@ void schedules(const sa::Packed &pk) {
     }
     std::vector<int32_t> start;
     std::vector<sa::SchedRec> slots;
-    const int32_t nl = sa::build_levels(pk, start, slots);
+    const int32_t nl = sa::build_levels(pk, 128, start, slots);
     expect((int32_t)start.size() == nl + 1 && start.back() == (int32_t)slots.size(), "level offsets");
+    // every variable comes after the levels of its lower-index neighbours (so no two variables of
+    // a level interact), and every variable that is not fixed appears exactly once
+    std::vector<int32_t> lvl(pk.n, -1);
+    for (int32_t l = 0; l < nl; ++l)
+        for (int32_t i = start[l]; i < start[l + 1]; ++i) {
+            expect(lvl[slots[i].k] == -1, "variable placed once");
+            lvl[slots[i].k] = l;
+        }
+    for (int32_t k = 0; k < pk.n; ++k) {
+        expect((lvl[k] >= 0) == (pk.var[k].width > 1), "variables that are not fixed are placed");
+        if (lvl[k] < 0 || pk.dense) continue;
+        const sa::VarRec &vr = pk.var[k];
+        for (int32_t q = vr.row; q < vr.row + vr.deg; ++q) {
+            const sa::IncRec &r = pk.inc[q];
+            const uint32_t no = r.meta >> 8;
+            for (uint32_t f = 0; f < no; ++f) {
+                const int32_t j = no <= 3 ? r.o[f] : pk.overflow[(size_t)r.o[0] + f];
+                if (j < k && lvl[j] >= 0) expect(lvl[j] < lvl[k], "lower neighbour in an earlier level");
+            }
+        }
+    }
 }
 
 }  // namespace
