@@ -279,6 +279,65 @@ __device__ __forceinline__ Acc dense_dot(const DevProblem &P, const ZT *z, int32
     return acc;
 }
 
+// Dense form, the paper's coefficient cache (Sec. 3.2): c1_i = h_i + sum_j J_ij z_j for every
+// variable of one replica, in LDS.  Threads tid, tid + nthr, ... fill their rows from the state.
+template <typename ZT>
+__device__ __forceinline__ void dense_cache_init(const DevProblem &P, const ZT *z, int64_t *c1, int tid, int nthr) {
+    const int32_t n = P.n;
+    for (int32_t i = tid; i < n; i += nthr) {
+        uint64_t acc = (uint64_t)P.h[i];
+        if (P.jbytes == 1) {
+            const int8_t *row = (const int8_t *)P.jd + (size_t)i * P.row_stride;
+            for (int32_t j = 0; j < n; ++j) acc += (uint64_t)(int64_t)row[j] * (uint64_t)(int64_t)z[j];
+        } else {
+            const int32_t *row = (const int32_t *)P.jd + (size_t)i * P.row_stride;
+            for (int32_t j = 0; j < n; ++j) acc += (uint64_t)(int64_t)row[j] * (uint64_t)(int64_t)z[j];
+        }
+        c1[i] = (int64_t)acc;
+    }
+}
+
+// Dense form with the coefficient cache, one window ahead: this lane's couplings J_k,lane and
+// J_k,lane+64 of row k (zero past N), h_k and the diagonal d_k.
+__device__ __forceinline__ void prefetch_dense_col(const DevProblem &P, int32_t k, int lane, int4 &jcol, uint64_t &h,
+                                                   int64_t &dk) {
+    jcol = make_int4(0, 0, 0, 0);
+    h = 0;
+    dk = 0;
+    if (k < 0) return;
+    const int32_t n = P.n;
+    if (P.jbytes == 1) {
+        const int8_t *row = (const int8_t *)P.jd + (size_t)k * P.row_stride;
+        jcol.y = lane < n ? row[lane] : 0;
+        jcol.z = lane + kWave < n ? row[lane + kWave] : 0;
+    } else {
+        const int32_t *row = (const int32_t *)P.jd + (size_t)k * P.row_stride;
+        jcol.y = lane < n ? row[lane] : 0;
+        jcol.z = lane + kWave < n ? row[lane + kWave] : 0;
+    }
+    h = (uint64_t)P.h[k];
+    dk = P.d[k];
+}
+
+// After z_k moved by dz: c1_i += J_ik dz for every i (the matrix's diagonal is zero, so c1_k does not
+// change).  Lane l owns i = l, l + 64, ...; `jcol`, when given, holds J_k,l and J_k,l+64 (loaded one
+// window ahead), which cover N <= 128.
+__device__ __forceinline__ void dense_cache_update(const DevProblem &P, int64_t *c1, int32_t k, int64_t dz, int lane,
+                                                   const int4 *jcol) {
+    const int32_t n = P.n;
+    if (jcol && n <= 2 * kWave) {
+        if (lane < n) atomicAdd((unsigned long long *)&c1[lane], (unsigned long long)((int64_t)jcol->y * dz));
+        if (lane + kWave < n)
+            atomicAdd((unsigned long long *)&c1[lane + kWave], (unsigned long long)((int64_t)jcol->z * dz));
+        return;
+    }
+    for (int32_t i = lane; i < n; i += kWave) {
+        const int64_t J = P.jbytes == 1 ? (int64_t)((const int8_t *)P.jd)[(size_t)k * P.row_stride + i]
+                                        : (int64_t)((const int32_t *)P.jd)[(size_t)k * P.row_stride + i];
+        atomicAdd((unsigned long long *)&c1[i], (unsigned long long)(J * dz));
+    }
+}
+
 // Uniform coefficients a_k^(m) (Sec. 3.2, T_k = sum_m a_k^(m) z_k^m) for m = 1..kMaxE; every
 // index is static so the coefficients stay in registers.
 template <int kMaxE, typename Acc>
@@ -290,7 +349,15 @@ struct Coeffs {
 template <int kMaxE, typename Acc, typename ZT>
 __device__ __forceinline__ void row_coeffs(const DevProblem &P, const ZT *z, int32_t k, int32_t row,
                                            int32_t deg, uint32_t emask, int lane, const IncRec &r0,
-                                           uint64_t coef0, Coeffs<kMaxE, Acc> &C) {
+                                           uint64_t coef0, Coeffs<kMaxE, Acc> &C, const int64_t *c1 = nullptr) {
+    if (P.dense && c1) {
+        // the coefficient cache: a^(1) from LDS, a^(2) = J_kk
+#pragma unroll
+        for (int m = 0; m <= kMaxE; ++m) C.a[m] = 0;
+        C.a[1] = (Acc)(uint64_t)c1[k];
+        if (kMaxE >= 2) C.a[kMaxE >= 2 ? 2 : 1] = (Acc)P.d[k];
+        return;
+    }
     if (P.dense) {
         // QUIO: a^(1) = h_k + sum_j J_kj z_j, a^(2) = J_kk (Sec. 3.2, the c^(1), c^(2) of QUIO)
 #pragma unroll
@@ -851,6 +918,7 @@ struct ReplicaCtx {
     bool shared;            // the replica's waves cooperate (barrier after each window)
     bool active;            // false: an idle team that only keeps the workgroup's barriers
     uint64_t *trace;        // this read's per-sweep hash words (s_end - s_begin), or nullptr
+    int64_t *c1;            // dense form: this replica's coefficient cache in LDS, or nullptr
 };
 
 // Initial state (given, or uniform on each box, Sec. 3.1) written by threads tid, tid+nthr, ...
@@ -952,7 +1020,10 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                 ndeg = (int32_t)lane_read32((uint32_t)sl.deg, jj);
                 if (kRule == SA_METROPOLIS && kRegChunk == 1) {
                     int4 q;
-                    prefetch_dense(P, (int32_t)lane_read32((uint32_t)sl.k, jj), lane, q, ncoef, nd);
+                    if (R.c1)
+                        prefetch_dense_col(P, (int32_t)lane_read32((uint32_t)sl.k, jj), lane, q, ncoef, nd);
+                    else
+                        prefetch_dense(P, (int32_t)lane_read32((uint32_t)sl.k, jj), lane, q, ncoef, nd);
                     nrec.meta = (uint32_t)q.x;
                     nrec.o[0] = q.y;
                     nrec.o[1] = q.z;
@@ -980,13 +1051,20 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         if (v >= zk) v += 1;
                         // (Metropolis kernels are built with kMaxE = 1 for any problem: the
                         // variable's own exponents decide)
-                        d = direct_delta<Acc, ZT, kRegChunk == 1>(P, z, k, row, deg, zk, v, lane, crec, ccoef, cd,
-                                                  (lane_read32(sl.emask, j) & ~2u) == 0);
+                        if (R.c1) {
+                            // dense form with the coefficient cache: dE in O(1)
+                            const Acc a1 = (Acc)(uint64_t)R.c1[k];
+                            const Acc dd = kRegChunk == 1 ? (Acc)cd : (Acc)P.d[k];
+                            d = to_i64<Acc>(a1 * (Acc)(v - zk) + dd * ((Acc)v * (Acc)v - (Acc)zk * (Acc)zk));
+                        } else {
+                            d = direct_delta<Acc, ZT, kRegChunk == 1>(P, z, k, row, deg, zk, v, lane, crec, ccoef, cd,
+                                                                      (lane_read32(sl.emask, j) & ~2u) == 0);
+                        }
                         accept = metropolis_accept(d, beta, U);
                     } else if (kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED) {
                         Coeffs<kMaxE, Acc> C;
                         const uint32_t em = lane_read32(sl.emask, j);
-                        row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
+                        row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C, R.c1);
                         next();
                         // closed form where dE is linear in the new value (no exponent above one)
                         const bool linear = kMaxE == 1 || (em & ~2u) == 0;
@@ -1000,7 +1078,7 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         if ((double)r0 * 0x1p-32 < r_opt) {
                             Coeffs<kMaxE, Acc> C;
                             const uint32_t em = lane_read32(sl.emask, j);
-                            row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C);
+                            row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C, R.c1);
                             if (kMaxE == 1 || (em & ~2u) == 0) {
                                 // dE = a1 (v - z_k): the smallest value for a1 >= 0 (all tie when
                                 // a1 = 0), the largest for a1 < 0, stepping off z_k
@@ -1023,6 +1101,11 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                         z[k] = (ZT)v;  // every lane stores the same value
                         E += d;
                         if (R.trace) H += hash_word(k, v) - hash_word(k, zk);
+                        if (R.c1) {
+                            const int4 jcol = make_int4((int)crec.meta, crec.o[0], crec.o[1], crec.o[2]);
+                            dense_cache_update(P, R.c1, k, v - zk, lane,
+                                               kRule == SA_METROPOLIS && kRegChunk == 1 ? &jcol : nullptr);
+                        }
                         if (!R.shared) state_write_fence<kStateInLds>();
                     }
                 }
@@ -1079,6 +1162,13 @@ __global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
     if (shared) window_barrier();
     else state_write_fence<kStateInLds>();
     int64_t E = energy_part(P, z, tid, nthr);
+    // dense form, one wave per replica, state in LDS: the coefficient cache follows the waves' states
+    int64_t *c1 = nullptr;
+    if (kStateInLds && A.dense_cache && !shared) {
+        c1 = (int64_t *)(lds_state + (((size_t)A.waves_per_group * n + 1) & ~(size_t)1)) + (size_t)wave * n;
+        dense_cache_init(P, z, c1, lane, kWave);
+        state_write_fence<kStateInLds>();
+    }
     uint64_t *trace = A.trace ? A.trace + (size_t)read * (size_t)(A.s_end - A.s_begin) : nullptr;
     if (trace && A.s_end > A.s_begin) {
         // the initial state's hash goes into the first sweep's word
@@ -1105,6 +1195,7 @@ __global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
     R.shared = shared;
     R.active = true;
     R.trace = trace;
+    R.c1 = c1;
     E += sweep_replica<kRule, kStateInLds, kRegChunk, kMaxE, Acc, int32_t>(R, z, lane);
 
     if (shared) {
@@ -1180,6 +1271,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64, 4) batch_kernel(BatchArgs B)
         R.shared = G > 1;
         R.active = active;
         R.trace = nullptr;
+        R.c1 = nullptr;
         if (D.rule == SA_METROPOLIS) {
             E += sweep_replica<SA_METROPOLIS, true, 0, 1, Acc, ZT>(R, z, lane);
         } else if (D.rule == SA_HEAT_BATH) {

@@ -108,6 +108,21 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
         lc.waves_per_group = wpg;
         lc.groups = (n_reads + wpg - 1) / wpg;
         lc.lds_bytes = lc.state_in_lds ? (int)(per_wave * wpg) : 0;
+        if (dense && lc.state_in_lds && n <= 1024) {
+            // the dense form keeps the coefficient cache (8 bytes per variable) after the states,
+            // with fewer replicas per workgroup if needed.  Each accepted move then updates N
+            // cached sums; above N = 1024 (16 per lane) that costs more than the row product it
+            // saves at every visit (measured on the N = 4096, W = 2001 heat bath: 677 against 400 ms)
+            auto cache_bytes = [&](int w) { return ((((int64_t)w * n + 1) & ~(int64_t)1) * 4) + (int64_t)w * n * 8; };
+            int w = wpg;
+            while (w > 1 && cache_bytes(w) > max_lds) --w;
+            if (cache_bytes(w) <= max_lds) {
+                lc.dense_cache = true;
+                lc.waves_per_group = w;
+                lc.groups = (n_reads + w - 1) / w;
+                lc.lds_bytes = (int)cache_bytes(w);
+            }
+        }
     }
     const int reg = lc.state_in_lds ? reg_in_lds : 0;
     lc.maxe_class = lc.state_in_lds ? maxe_class_of(max_exp)
@@ -115,7 +130,7 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     lc.reg_chunk = reg;
     lc.narrow = narrow_ok && lc.state_in_lds && lc.maxe_class <= 2 && !otm_wide;
     lc.variant = (lc.win_waves == 16 ? 1000000 : 0) + rule * 100000 + (lc.narrow ? 10000 : 0) +
-                 lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
+                 (lc.dense_cache ? 5000 : 0) + lc.maxe_class * 100 + reg * 2 + (lc.state_in_lds ? 1 : 0);
     return lc;
 }
 
