@@ -206,8 +206,23 @@ __device__ __forceinline__ Acc record_product(const DevProblem &P, const ZT *z, 
         prod *= no > 1 ? (Acc)z1 : (Acc)1;
         prod *= no > 2 ? (Acc)z2 : (Acc)1;
     } else {
-        const int32_t *o = P.overflow + r.o[0];
-        for (int f = 0; f < no; ++f) prod *= (Acc)(int64_t)z[o[f]];
+        // the list is 16-byte aligned and padded with -1 to whole int4: sixteen indices are loaded
+        // before any value is read, and a pad index multiplies by one
+        const int4 *o = (const int4 *)(P.overflow + r.o[0]);
+        for (int f0 = 0; f0 < no; f0 += 16) {
+            int4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = f0 + 4 * u < no ? o[f0 / 4 + u] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t ix[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int64_t zv = z[ix[c] < 0 ? 0 : ix[c]];
+                    prod *= ix[c] < 0 ? (Acc)1 : (Acc)zv;
+                }
+            }
+        }
     }
     return prod;
 }

@@ -398,13 +398,16 @@ int pack(const Canonical &c, Packed &p, std::string &err) {
             if (others.size() <= 3) {
                 for (size_t q = 0; q < 3; ++q) r.o[q] = q < others.size() ? others[q] : 0;
             } else {
-                if (others.size() >= (1u << 24) || p.overflow.size() > (size_t)INT32_MAX - others.size()) {
+                if (others.size() >= (1u << 24) || p.overflow.size() > (size_t)INT32_MAX - others.size() - 3) {
                     err = "term too long";
                     return SA_EINVAL;
                 }
+                // each list starts on a 16-byte boundary and is padded with -1 to whole groups of
+                // four, so that the device reads it four indices at a time
                 r.o[0] = (int32_t)p.overflow.size();
                 r.o[1] = r.o[2] = 0;
                 p.overflow.insert(p.overflow.end(), others.begin(), others.end());
+                while (p.overflow.size() % 4) p.overflow.push_back(-1);
             }
             const int64_t slot = fill[k]++;
             p.inc[slot] = r;

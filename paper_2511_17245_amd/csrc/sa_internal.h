@@ -53,7 +53,8 @@ struct VarRec {
 };
 // Incidence record of variable k in term t: meta = e_k(t) | (n_other << 8); the other factors
 // (indices repeated by exponent) inline in o[0..2] when n_other <= 3, else o[0] is the offset of
-// n_other indices in the overflow array.
+// n_other indices in the overflow array (a multiple of four; the list is padded with -1 to a
+// multiple of four entries).
 struct IncRec {
     uint32_t meta;
     int32_t o[3];

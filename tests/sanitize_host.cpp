@@ -54,7 +54,24 @@ int prepare(const Raw &r, sa::Packed &pk, std::string &err) {
     return sa::pack(c, pk, err);
 }
 
+// other-factor lists of long terms: 16-byte aligned, valid indices, padded with -1 to whole int4
+// (the device reads them four at a time)
+void overflow_lists(const sa::Packed &pk) {
+    for (const sa::IncRec &r : pk.inc) {
+        const uint32_t no = r.meta >> 8;
+        if (no <= 3) continue;
+        const size_t at = (size_t)r.o[0], padded = (no + 3) / 4 * 4;
+        expect(at % 4 == 0 && at + padded <= pk.overflow.size(), "overflow list aligned and in range");
+        if (at + padded > pk.overflow.size()) continue;
+        for (uint32_t f = 0; f < padded; ++f) {
+            const int32_t j = pk.overflow[at + f];
+            expect(f < no ? (j >= 0 && j < pk.n) : j == -1, "overflow index or pad");
+        }
+    }
+}
+
 void schedules(const sa::Packed &pk) {
+    overflow_lists(pk);
     for (int G : {1, 2, 4, 8, 16}) {
         std::vector<sa::SchedRec> s;
         const int32_t nw = sa::build_schedule(pk, G, s);
@@ -113,6 +130,26 @@ int main() {
         const int rc = prepare(r, pk, err);
         expect(rc == SA_OK || rc == SA_ERANGE, "random problem prepares");
         if (rc == SA_OK) schedules(pk);
+    }
+    // long terms: the multilinear chain of degree 30 (lists of 29 other factors) and degree 17
+    // with a squared factor
+    for (int32_t deg : {30, 17}) {
+        Raw r;
+        r.n = 40;
+        for (int32_t i = 0; i < r.n; ++i) {
+            r.lo.push_back(-1);
+            r.hi.push_back(1);
+        }
+        for (int32_t i = 0; i < r.n; ++i) {
+            std::vector<int32_t> v;
+            for (int32_t f = 0; f < deg; ++f) v.push_back((i + f) % r.n);
+            if (deg == 17) v.push_back(i);
+            r.term(-1, v);
+        }
+        sa::Packed pk;
+        expect(prepare(r, pk, err) == SA_OK, "long terms prepare");
+        expect(pk.max_other == (deg == 30 ? 29 : 17), "long terms keep every other factor");
+        schedules(pk);
     }
     // dense QUIO (stored as a matrix) with int8 and int32 couplings
     for (int64_t jmax : {10LL, 100000LL}) {
