@@ -50,7 +50,10 @@ extern "C" {
 /* ---- transition rules (Sec. 3.3) ---------------------------------------------------------- */
 #define SA_METROPOLIS 0        /* uniform nonzero change, accept min[1, exp(-dE/T)]   (Sec. 3.3.1) */
 #define SA_HEAT_BATH 1         /* draw the new value with probability exp(-dE/T)/sum  (Sec. 3.3.2) */
-#define SA_OPT_METROPOLIS 2    /* optimal transition with probability r = s/(S-1)     (Sec. 3.3.3) */
+#define SA_OPT_METROPOLIS 2    /* with probability r = s/(S-1) the optimal transition: the value
+                                  of smallest dE over the whole range (the unchanged value, dE = 0,
+                                  included; ties to the lowest value), else the Metropolis
+                                  proposal; Metropolis acceptance                      (Sec. 3.3.3) */
 #define SA_HEAT_BATH_CLOSED 3  /* heat bath; a variable whose dE is linear in its new value (no
                                   exponent above one) takes the O(1) inverse-transform draw of
                                   Sec. 3.3.2, the others the enumeration of SA_HEAT_BATH */
@@ -105,9 +108,10 @@ typedef struct {
     int32_t waves_per_replica;  /* 0: automatic.  G > 1 lets G wavefronts of one replica update G
                                    consecutive variables that share no term at the same time (the
                                    result is identical to the sequential sweep); 1, 2, 4, 8 or 16 */
-    int32_t otm_enum_max;       /* optimal transition: ranges of at most this many values take the
-                                   argmin by enumeration, wider ones from the stationary points of
-                                   the degree-<=4 energy difference (same result); 0: 2048 */
+    int32_t otm_enum_max;       /* optimal transition: ranges of at most this many values (and
+                                   of at most 64) take the argmin by enumeration, wider ones from
+                                   the sign changes of the forward differences of the degree-<=4
+                                   energy difference (exact: the same value); 0: 2048 */
     uint64_t *trace_hashes;     /* NULL: no tracing (default).  Otherwise n_reads x (sweep_end -
                                    sweep_begin) words, row-major (read, sweep), host or device memory
                                    as device_buffers says: the hash of each read's state after each

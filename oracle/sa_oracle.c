@@ -11,8 +11,9 @@
  *  - acceptance: dE <= 0 accepts, otherwise U < exp(-(beta * dE)) with U in [0, 1);
  *  - heat bath: weights exp(-beta (dE_v - min dE)) over all u_k - l_k + 1 values, summed one
  *    value at a time in increasing value order; first cumulative weight above U * total is chosen;
- *  - optimal transition: argmin over the nonzero changes, ties to the smallest new value, with
- *    probability r = s/(S-1); otherwise the Metropolis proposal; Metropolis acceptance;
+ *  - optimal transition: argmin of dE over the whole range (z_k itself included, dE = 0), ties
+ *    to the smallest value, with probability r = s/(S-1); otherwise the Metropolis proposal;
+ *    Metropolis acceptance (the optimal move, whose dE <= 0, is always accepted);
  *  - variables with l_k = u_k are skipped; zero coefficients are dropped.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -pthread -o libsa_oracle.so sa_oracle.c -lm
@@ -569,12 +570,12 @@ static int update_variable(chain_ctx *c, int32_t *z, int32_t k, uint32_t s, uint
         d = delta_from_coeffs(a, maxe, zk, v);
         accept = 1;
     } else {
-        /* optimal-transition Metropolis (Sec. 3.3.3) */
+        /* optimal-transition Metropolis (Sec. 3.3.3): the change of smallest dE over every value
+         * of the range, the unchanged value among them */
         if ((double)x[0] * 0x1p-32 < r_opt) {
             int64_t best = INT64_MAX;
             v = lo;
             for (int64_t cand = lo; cand < lo + W; ++cand) {
-                if (cand == zk) continue;
                 int64_t dc = delta_from_coeffs(a, maxe, zk, cand);
                 if (dc < best) {
                     best = dc;

@@ -698,15 +698,15 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
     return lo + (int64_t)src * (int64_t)c + (int64_t)(int32_t)lane_read32((uint32_t)hit, src);
 }
 
-// Optimal transition (Sec. 3.3.3): the nonzero change of smallest dE, ties to the smallest value.
+// Optimal transition (Sec. 3.3.3): the value of smallest dE over the whole range (z_k itself, with
+// dE = 0, included), ties to the smallest value.
 template <int kMaxE, typename Acc>
-__device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
-                                                  int64_t zk, int lane, int64_t &dbest) {
+__device__ __forceinline__ int64_t argmin_range(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
+                                                int64_t zk, int lane, int64_t &dbest) {
     int64_t best = INT64_MAX;
     int32_t bv = INT32_MAX;
     for (int64_t i = lane; i < W; i += kWave) {
         const int64_t v = lo + i;
-        if (v == zk) continue;
         const int64_t d = poly_delta(C, zk, v);
         if (d < best) {
             best = d;
@@ -717,108 +717,106 @@ __device__ __forceinline__ int64_t argmin_nonzero(const Coeffs<kMaxE, Acc> &C, i
     return wave_min_i32(best == dbest ? bv : INT32_MAX);
 }
 
-// Optimal transition over a wide range (Sec. 3.3.3 restricts the rule to energy differences of
-// degree <= 4, whose minimisers lie next to stationary points).  With p(v) = sum_m a_m v^m,
-// dE(v) = p(v) - p(z_k).  The smallest minimiser v* over [lo, hi] minus {z_k} is an end of the
-// range, z_k - 1 or z_k + 1, or else p(v*-1) > p(v*) <= p(v*+1), so the real polynomial has a
-// stationary point t with |t - v*| < 1.  Every real root of the first derivative (and, in case
-// rounding hides a nearly double root, of the second and third derivatives) is found in double
-// precision; the 64 integers around each such centre, around both ends and around z_k are then
-// evaluated exactly, and the wave takes the lexicographic (dE, v) minimum.  The result equals the
-// enumeration whenever each computed root is within 30 of the true one.
+// Optimal transition over a wide range, exact by construction.  With p(v) = sum_m a_m v^m (m <= 4:
+// Sec. 3.3.3 restricts the rule to energy differences of degree at most four), dE(v) = p(v) -
+// p(z_k).  The forward differences D1(v) = p(v+1) - p(v), D2(v) = D1(v+1) - D1(v) and D3(v) =
+// D2(v+1) - D2(v) are integer polynomials of degree 3, 2 and 1 in v, and D3 is monotone.  An
+// integer sequence that is monotone on a piece changes sign at most once there, at a point a
+// 64-way search finds exactly.  D3's sign change splits [lo, hi] into at most two pieces on each
+// of which D2 is monotone; D2's sign changes split those into at most four pieces on which D1 is
+// monotone.  Where D1 does not decrease, p falls until the first v with D1(v) >= 0 and does not
+// fall after it, so that v is the piece's smallest minimiser; where D1 does not increase, p's
+// minimum over the piece is at one of its ends.  The smallest minimiser over the range is the
+// lexicographic (dE, v) minimum over these points and the piece ends.
+//
+// The differences are evaluated as polynomials in 64-bit ring arithmetic.  The energy bound gives
+// |a_m| M^m < 2^62 with M = max(|lo|, |hi|), and a range of more than 64 values has M >= 32, so for
+// every v of the range |D1| < 2^62 * 10 / M, |D2| < 2^62 * 20 / M^2 and |D3| < 2^62 * 30 / M^3:
+// the ring results are the integers themselves.
 
-// Real roots of a x^2 + b x + c (a = 0: the linear root), preceded by the vertex -b/2a.
-__device__ __forceinline__ int quadratic_centres(double a, double b, double c, double *r) {
-    if (a == 0.0) {
-        if (b == 0.0) return 0;
-        r[0] = -c / b;
-        return 1;
-    }
-    int n = 0;
-    r[n++] = -b / (2.0 * a);
-    const double disc = b * b - 4.0 * a * c;
-    if (disc >= 0.0) {
-        const double q = -0.5 * (b + copysign(sqrt(disc), b));
-        r[n++] = q / a;
-        if (q != 0.0) r[n++] = c / q;
-    }
-    return n;
+// D_order(v), order 1..3, from the true coefficients a[1..4] (as ring elements)
+__device__ __forceinline__ int64_t forward_difference(const uint64_t *a, int order, int64_t v) {
+    const uint64_t x = (uint64_t)v, x2 = x * x, x3 = x2 * x;
+    uint64_t r;
+    if (order == 1)
+        r = a[1] + a[2] * (2 * x + 1) + a[3] * (3 * x2 + 3 * x + 1) + a[4] * (4 * x3 + 6 * x2 + 4 * x + 1);
+    else if (order == 2)
+        r = 2 * a[2] + a[3] * (6 * x + 6) + a[4] * (12 * x2 + 24 * x + 14);
+    else
+        r = 6 * a[3] + a[4] * (24 * x + 36);
+    return (int64_t)r;
 }
 
-// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 (c3 != 0): trigonometric form for three real roots,
-// Cardano's for one, each then improved by two Newton steps.
-__device__ __forceinline__ int cubic_roots(double c3, double c2, double c1, double c0, double *r) {
-    const double A = c2 / c3, B = c1 / c3, C = c0 / c3;
-    const double A3 = A / 3.0;
-    const double p = B - A * A3;                 // depressed cubic y^3 + p y + q, x = y - A/3
-    const double q = (2.0 * A3 * A3 - B) * A3 + C;
-    const double D = 0.25 * q * q + p * p * p / 27.0;
-    int n = 0;
-    if (D <= 0.0 && p < 0.0) {
-        const double m = 2.0 * sqrt(-p / 3.0);
-        double cs = -4.0 * q / (m * m * m);
-        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-        const double th = acos(cs) / 3.0;
-        const double tau = 2.0943951023931957;   // 2 pi / 3
-        r[n++] = m * cos(th) - A3;
-        r[n++] = m * cos(th - tau) - A3;
-        r[n++] = m * cos(th + tau) - A3;
-    } else {
-        const double sd = sqrt(D > 0.0 ? D : 0.0);
-        const double u = cbrt(-0.5 * q - copysign(sd, q));
-        r[n++] = (u != 0.0 ? u - p / (3.0 * u) : 0.0) - A3;
+// The smallest v in [x0, x1] with dir * D_order(v) >= 0, or x1 + 1 if there is none; dir * D_order
+// must not decrease on [x0, x1].  Wave-uniform arguments; each round the 64 lanes test the last
+// point of 64 equal blocks and the range shrinks to the first block that holds the answer (a range
+// of 2^33 values needs six rounds).
+__device__ __forceinline__ int64_t first_nonnegative(const uint64_t *a, int order, int dir, int64_t x0,
+                                                     int64_t x1, int lane) {
+    int64_t b0 = x0, b1 = x1;
+    for (int round = 0; round < 8 && b1 - b0 + 1 > kWave; ++round) {
+        const int64_t step = (b1 - b0 + kWave) / kWave;   // ceil(len / 64)
+        const int64_t s = b0 + (int64_t)lane * step;
+        const int64_t e = s + step - 1 < b1 ? s + step - 1 : b1;
+        const bool hit = s <= b1 && (int64_t)dir * forward_difference(a, order, e) >= 0;
+        const uint64_t mask = __ballot(hit);
+        if (mask == 0) return x1 + 1;
+        const int64_t j = __ffsll((unsigned long long)mask) - 1;
+        const int64_t nb0 = b0 + j * step;
+        b1 = nb0 + step - 1 < b1 ? nb0 + step - 1 : b1;
+        b0 = nb0;
     }
-    for (int i = 0; i < n; ++i) {
-        double x = r[i];
-        for (int it = 0; it < 2; ++it) {
-            const double f = ((c3 * x + c2) * x + c1) * x + c0;
-            const double g = (3.0 * c3 * x + 2.0 * c2) * x + c1;
-            const double xn = g != 0.0 ? x - f / g : x;
-            x = isfinite(xn) ? xn : x;
-        }
-        r[i] = x;
-    }
-    return n;
+    const int64_t v = b0 + lane;
+    const bool hit = v <= b1 && (int64_t)dir * forward_difference(a, order, v) >= 0;
+    const uint64_t mask = __ballot(hit);
+    return mask == 0 ? x1 + 1 : b0 + (__ffsll((unsigned long long)mask) - 1);
 }
 
 template <int kMaxE, typename Acc>
-__device__ __forceinline__ int64_t argmin_stationary(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
-                                                     int64_t zk, int lane, int64_t &dbest) {
+__device__ __forceinline__ int64_t argmin_wide(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
+                                               int64_t zk, int lane, int64_t &dbest) {
     const int64_t hi = lo + W - 1;
-    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    uint64_t a[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-    for (int m = 1; m <= (kMaxE < 4 ? kMaxE : 4); ++m) a[m] = (double)to_i64<Acc>(C.a[m]);
-    double cen[12];
+    for (int m = 1; m <= (kMaxE < 4 ? kMaxE : 4); ++m) a[m] = (uint64_t)to_i64<Acc>(C.a[m]);
+    // candidates: the range's ends; for each piece [y0, y1] of D1's index range on which D1 is
+    // monotone, the piece's ends (p over [y0, y1 + 1]) and, where D1 does not decrease, its first
+    // point with D1 >= 0
+    int64_t cand = lo;
     int nc = 0;
-    cen[nc++] = (double)(lo + 31);
-    cen[nc++] = (double)(hi - 32);
-    cen[nc++] = (double)zk;
-    // first derivative 4 a4 x^3 + 3 a3 x^2 + 2 a2 x + a1; second 12 a4 x^2 + 6 a3 x + 2 a2
-    if (a[4] != 0.0) {
-        nc += cubic_roots(4.0 * a[4], 3.0 * a[3], 2.0 * a[2], a[1], cen + nc);
-        nc += quadratic_centres(12.0 * a[4], 6.0 * a[3], 2.0 * a[2], cen + nc);
-    } else {
-        nc += quadratic_centres(3.0 * a[3], 2.0 * a[2], a[1], cen + nc);
-        if (a[3] != 0.0) cen[nc++] = -a[2] / (3.0 * a[3]);
+    auto add = [&](int64_t v) {
+        v = v > hi ? hi : v;
+        if (nc == lane) cand = v;
+        ++nc;
+    };
+    auto piece = [&](int64_t y0, int64_t y1, int dir1) {
+        add(y0);
+        add(y1 + 1);
+        if (dir1 > 0) add(first_nonnegative(a, 1, 1, y0, y1, lane));
+    };
+    add(lo);
+    add(hi);
+    // D3 is linear with slope 24 a4: its direction on the whole range
+    const int d3 = (int64_t)a[4] >= 0 ? 1 : -1;
+    const int64_t z3 = first_nonnegative(a, 3, d3, lo, hi, lane);
+    // D3 has sign -d3 (strictly) on [lo, z3 - 1] and sign d3 (or is 0) on [z3, hi], so D2 is
+    // monotone with direction -d3 on [lo, z3] and d3 on [z3, hi]; each is split where D2 changes
+    // sign, giving the pieces where D1 is monotone
+    const int64_t q0[2] = {lo, z3};
+    const int64_t q1[2] = {z3 <= hi ? z3 : hi, hi};
+    const int qd[2] = {-d3, d3};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (q0[i] > q1[i] || (i == 0 && z3 == lo)) continue;
+        const int64_t z2 = first_nonnegative(a, 2, qd[i], q0[i], q1[i], lane);
+        if (z2 > q0[i]) piece(q0[i], z2 <= q1[i] ? z2 : q1[i], -qd[i]);   // D2 of sign -qd
+        if (z2 <= q1[i]) piece(z2, q1[i], qd[i]);                           // D2 of sign qd, or 0
     }
     int64_t best = INT64_MAX;
     int32_t bv = INT32_MAX;
-    for (int i = 0; i < nc; ++i) {
-        // window [b, b + 63] around the centre, inside the range
-        const double c = cen[i];
-        int64_t b;
-        if (!(c > (double)lo + 31.0)) b = lo;
-        else if (!(c < (double)hi - 32.0)) b = hi - 63;
-        else b = (int64_t)floor(c) - 31;
-        b = b < lo ? lo : b;
-        const int64_t v = b + lane;
-        if (v <= hi && v != zk) {
-            const int64_t d = poly_delta(C, zk, v);
-            if (d < best || (d == best && v < bv)) {
-                best = d;
-                bv = (int32_t)v;
-            }
-        }
+    if (lane < nc) {
+        best = poly_delta(C, zk, cand);
+        bv = (int32_t)cand;
     }
     dbest = wave_min_i64(best);
     return wave_min_i32(best == dbest ? bv : INT32_MAX);
@@ -1095,15 +1093,15 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
                             const uint32_t em = lane_read32(sl.emask, j);
                             row_coeffs<kMaxE, Acc, ZT>(P, z, k, row, deg, em, lane, crec, ccoef, C, R.c1);
                             if (kMaxE == 1 || (em & ~2u) == 0) {
-                                // dE = a1 (v - z_k): the smallest value for a1 >= 0 (all tie when
-                                // a1 = 0), the largest for a1 < 0, stepping off z_k
+                                // dE = a1 (v - z_k): the lowest value for a1 >= 0 (every value ties
+                                // when a1 = 0), the highest for a1 < 0
                                 const int64_t a1 = to_i64<Acc>(C.a[1]);
-                                v = a1 >= 0 ? (lo == zk ? lo + 1 : lo) : (lo + W - 1 == zk ? lo + W - 2 : lo + W - 1);
+                                v = a1 >= 0 ? lo : lo + W - 1;
                                 d = to_i64<Acc>(C.a[1] * (Acc)(v - zk));
-                            } else if (kRegChunk == 1 && W > R.otm_enum_max)
-                                v = argmin_stationary<kMaxE, Acc>(C, lo, W, zk, lane, d);
+                            } else if (kRegChunk == 1 && W > R.otm_enum_max && W > kWave)
+                                v = argmin_wide<kMaxE, Acc>(C, lo, W, zk, lane, d);
                             else
-                                v = argmin_nonzero<kMaxE, Acc>(C, lo, W, zk, lane, d);
+                                v = argmin_range<kMaxE, Acc>(C, lo, W, zk, lane, d);
                         } else {
                             v = lo + (int64_t)(((uint64_t)r1 * (uint64_t)(W - 1)) >> 32);
                             if (v >= zk) v += 1;

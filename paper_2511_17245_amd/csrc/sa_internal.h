@@ -19,7 +19,7 @@ constexpr int kMaxExpStored = 255;
 // Heat-bath weights kept in registers when ceil(W/64) <= this; wider ranges recompute them.
 constexpr int kHeatBathRegChunk = 32;
 // Optimal transition: ranges up to this width take the argmin by enumeration, wider ones from the
-// stationary points of the energy difference.
+// sign changes of the energy difference's forward differences (the same value).
 constexpr int kOtmEnumMax = 2048;
 
 // Canonical polynomial: merged terms, nonzero coefficients, factors sorted (a power is a

@@ -11,7 +11,7 @@ namespace sa {
 using AnnealKernelFn = void (*)(AnnealArgs);
 
 // in_lds: states in LDS; reg_chunk: heat-bath weights per lane kept in registers (0: recomputed),
-// for Metropolis and the optimal transition 1 selects the dense-form / stationary-point variant;
+// for Metropolis and the optimal transition 1 selects the dense-form / wide-range argmin variant;
 // maxe_class: 1, 2, 4 or kMaxExpPoly; narrow: 32-bit energy differences; sixteen: 1024-thread
 // workgroups (16 cooperating waves).
 AnnealKernelFn metropolis_kernel(bool in_lds, int reg_chunk, bool narrow, bool sixteen);

@@ -81,8 +81,8 @@ LaunchChoice choose_launch(int rule, int32_t n, int32_t n_reads, int32_t max_wid
     const int64_t per_wave = (int64_t)n * (int64_t)sizeof(int32_t);
     const bool heat_bath = rule == SA_HEAT_BATH || rule == SA_HEAT_BATH_CLOSED;
     const int64_t chunk = ((int64_t)max_width + kWave - 1) / kWave;
-    // heat bath: weights per lane kept in registers; optimal transition: 1 = stationary-point
-    // argmin; Metropolis: 1 = dense form with prefetched coupling rows
+    // heat bath: weights per lane kept in registers; optimal transition: 1 = wide-range argmin
+    // from forward differences; Metropolis: 1 = dense form with prefetched coupling rows
     const bool otm_wide = rule == SA_OPT_METROPOLIS && max_width > otm_enum_max;
     const int reg_in_lds =
         heat_bath && !(rule == SA_HEAT_BATH_CLOSED && max_exp <= 1)

@@ -14,7 +14,7 @@ AnnealKernelFn otm_kernel(bool in_lds, int reg_chunk, int maxe_class, bool narro
     }
     if (!in_lds) return anneal_kernel<SA_OPT_METROPOLIS, false, 1, 4, uint64_t, 512>;
     if (reg_chunk == 1) {
-        // ranges wider than the enumeration limit: the stationary-point argmin is built in
+        // ranges wider than the enumeration limit: the forward-difference argmin is built in
         switch (maxe_class) {
             case 1: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 1, uint64_t, 512>;
             case 2: return anneal_kernel<SA_OPT_METROPOLIS, true, 1, 2, uint64_t, 512>;

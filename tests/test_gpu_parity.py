@@ -287,6 +287,118 @@ def test_otm_stationary_point_argmin_matches_enumeration():
                   otm_enum_max=enum_max)
 
 
+def _quartic_terms(var, c):
+    """Terms c[m] z_var^m, m = 1..4 (zero coefficients left out)."""
+    return [(int(c[m]), [var] * m) for m in range(1, 5) if c[m] != 0]
+
+
+def _expand(roots_sq, scale=1, tilt=0):
+    """Coefficients of scale * prod_{r in roots_sq} (v - r)^2 + tilt * v (two roots: a quartic)."""
+    poly = [1]
+    for r in roots_sq:
+        for _ in range(2):
+            nxt = [0] * (len(poly) + 1)
+            for i, a in enumerate(poly):
+                nxt[i] -= r * a
+                nxt[i + 1] += a
+            poly = nxt
+    c = [scale * a for a in poly] + [0] * (5 - len(poly))
+    c[1] += tilt
+    return c
+
+
+def _bound(terms, lo, hi):
+    M = [max(abs(a), abs(b)) for a, b in zip(lo, hi)]
+    tot = 0
+    for coef, vs in terms:
+        t = abs(coef)
+        for v in vs:
+            t *= M[v]
+        tot += t
+    return tot
+
+
+def test_otm_wide_argmin_on_adversarial_quartics():
+    # The optimal transition over ranges wider than the enumeration limit (forward-difference sign
+    # changes, exact by construction) on quartics built to defeat approximate root finding: equal
+    # double minima (ties to the lower one), nearly double minima tilted by +-1, concave quartics
+    # (minimum at an end), coefficients summing to just under the 2^62 energy bound, and a
+    # quadratic over a range of 2^31 - 1 values whose minimiser is known in closed form.  At r = 1
+    # every step takes the argmin, so after the first sweep each variable sits at the minimiser of
+    # its own quartic; the oracle enumerates the range.
+    r = rng(92)
+    M = 6000
+    terms, expect = [], []
+    for v in range(12):
+        kind = v % 4
+        a, b = sorted(int(x) for x in r.integers(-M + 10, M - 10, size=2))
+        if kind == 0:                       # (v-a)^2 (v-b)^2: equal minima at a and b, tie -> a
+            c, want = _expand([a, b]), a
+        elif kind == 1:                     # (v-a)^2 (v-a-1)^2 + t v
+            t = int(r.integers(-1, 2))
+            c = _expand([a, a + 1], tilt=t)
+            want = a if t >= 0 else a + 1
+        elif kind == 2:                     # -(v-a)^2 (v-b)^2: concave ends; the larger end value
+            c, want = _expand([a, b], scale=-1), None
+        else:                               # double minimum at one point
+            c, want = _expand([a, a]), a
+        terms += _quartic_terms(v, c)
+        expect.append(want)
+    lo, hi = [-M] * 12, [M] * 12
+    assert _bound(terms, lo, hi) < 2 ** 62
+    quartics = I.from_terms(12, terms, lo, hi, name="adversarial quartics")
+    # near the bound: one variable, a double well (c4 > 0, c2 < 0, c1 and c3 of random sign) whose
+    # terms take random shares of 0.98 * 2^62 at the range's ends
+    Mb = 9000
+    s4, s2, s3 = r.uniform(0.40, 0.55), r.uniform(0.35, 0.42), r.uniform(0.0, 0.02)
+    share = [0.98 - s4 - s2 - s3, s2, s3, s4]
+    sign = [0, int(r.choice([-1, 1])), -1, int(r.choice([-1, 1])), 1]
+    c = [0] + [max(1, int(share[m - 1] * 2 ** 62) // Mb ** m) * sign[m] for m in range(1, 5)]
+    near = I.from_terms(1, _quartic_terms(0, c), -Mb, Mb, name="quartic at the bound")
+    assert 0.9 * 2 ** 62 < _bound(_quartic_terms(0, c), [-Mb], [Mb]) < 2 ** 62
+    beta = np.full(3, 0.5)
+    for name, prob, want in (("adversarial quartics", quartics, expect), ("quartic at the bound", near, [None])):
+        P = oracle.Poly(prob)
+        say("otm adversarial", name)
+        zg, eg, launch = gpu_run(prob, sa.OPT_METROPOLIS, beta, 16, seed=5, otm_r=1.0)
+        zo, eo = P.anneal(sa.OPT_METROPOLIS, beta, 16, seed=5, otm_r=1.0)
+        assert np.array_equal(zg, zo) and np.array_equal(eg, eo), name
+        for k, w in enumerate(want):
+            if w is not None:
+                assert np.all(zg[:, k] == w), (name, k, w, zg[:, k])
+    # the widest range: E = z^2 - 2 t z over [-(2^30 - 1), 2^30 - 1] (2^31 - 1 values): argmin t,
+    # and for a tilt of exactly half a step both t and t + 1 give the same energy: the lower wins
+    t = 123456789
+    for c1, want in ((-2 * t, t), (-(2 * t + 1), t)):
+        huge = I.from_terms(1, [(1, [0, 0]), (c1, [0])], -(2 ** 30 - 1), 2 ** 30 - 1, name="huge quadratic")
+        say("otm huge range", c1)
+        zg, eg, launch = gpu_run(huge, sa.OPT_METROPOLIS, np.full(2, 0.5), 8, seed=6, otm_r=1.0)
+        assert np.all(zg[:, 0] == want), zg[:, 0]
+        assert np.all(eg == want * want + c1 * want)
+
+
+def test_dense_coefficient_cache_equals_the_row_product():
+    # A dense QUIO annealed one wavefront per replica keeps the coefficient cache c1 of Sec. 3.2 in
+    # LDS, updated on every accepted move; two wavefronts per replica recompute the row product at
+    # every visit.  Both must give the same reads (same integers), and every tracked energy must be
+    # the energy of its final state, for each rule and for int8 and int32 couplings.
+    r = rng(93)
+    cases = [("int8_w16", I.dense_quio(100, 0, 15, 10, 10, r)),
+             ("int32_w41", I.dense_quio(300, -20, 20, 3000, 700, r)),
+             ("n1024_w3", I.dense_quio(1024, -1, 1, 20, 20, r))]
+    for name, prob in cases:
+        P = oracle.Poly(prob)
+        beta, _, _ = P.schedule(40)
+        for rule in (sa.METROPOLIS, sa.HEAT_BATH, sa.OPT_METROPOLIS):
+            say("dense cache", name, sa.RULE_NAMES[rule])
+            zc, ec, lc = gpu_run(prob, rule, beta, 24, seed=13, G=1)
+            assert lc["kernel_variant"] // 1000 % 10 == 5, lc          # the cached variant ran
+            zr, er, lr = gpu_run(prob, rule, beta, 24, seed=13, G=2)
+            assert lr["kernel_variant"] // 1000 % 10 != 5, lr
+            assert_same(zc, ec, zr, er, f"{name} {sa.RULE_NAMES[rule]} cache vs row product")
+            assert all(int(ec[i]) == P.energy(zc[i]) for i in range(24))
+
+
 def test_energy_kernel_and_one_shot_api():
     r = rng(3)
     for dense in (I.dense_quio(130, -50, 50, 10, 10, r), I.dense_quio(75, -9, 9, 500, 30, r)):

@@ -249,16 +249,19 @@ def _heat_bath_kernel(dE, beta):
 
 
 def _otm_kernel(dE, zk, beta, r):
+    # Eq. of Sec. 3.3.3: with probability r the optimal change (argmin over the whole range, the
+    # unchanged value with dE = 0 included, ties to the smallest value; dE_min <= 0 is always
+    # accepted), otherwise a uniform proposal among the u - l other values, Metropolis acceptance
     vals = sorted(dE)
     R = len(vals) - 1
-    cand = [v for v in vals if v != zk]
-    dmin = min(dE[v] for v in cand)
-    vstar = min(v for v in cand if dE[v] == dmin)
+    others = [v for v in vals if v != zk]
+    dmin = min(dE[v] for v in vals)
+    vstar = min(v for v in vals if dE[v] == dmin)
     p = {v: 0.0 for v in vals}
-    for v in cand:
+    for v in others:
         p[v] += (1 - r) * min(1.0, math.exp(-beta * dE[v])) / R
     p[vstar] += r * min(1.0, math.exp(-beta * dE[vstar]))
-    p[zk] = 1.0 - sum(p[v] for v in cand)
+    p[zk] = 1.0 - sum(p[v] for v in others)
     return np.array([p[v] for v in vals])
 
 
@@ -322,23 +325,25 @@ def test_infinite_temperature_limits():
 
 
 def test_otm_greedy_branch_is_brute_force_argmin():
-    # r = 1: every proposal is argmin over the nonzero changes, ties to the smallest value;
-    # at a large beta a non-positive minimum is always taken.
+    # r = 1: every step takes the argmin of dE over the whole range (the unchanged value, dE = 0,
+    # included), ties to the smallest value; the minimum is <= 0 and always accepted, at any beta
     r = rng(303)
-    for _ in range(20):
+    seen_stay = seen_move = 0
+    for _ in range(40):
         p = I.tiny_random(r, 4, -3, 3, 12, 4, jmax=2)
         P = oracle.Poly(p)
         z = r.integers(p.lower, p.upper + 1)
         k = int(r.integers(0, 4))
         dE = brute.deltas(p, z, k)
-        cand = [v for v in dE if v != z[k]]
-        dmin = min(dE[v] for v in cand)
-        vstar = min(v for v in cand if dE[v] == dmin)
-        v = P.single_step(oracle.OPT_METROPOLIS, z, k, 0, 50.0, 1.0, 64, seed=3)
-        if dmin <= 0:
+        assert dE[int(z[k])] == 0
+        dmin = min(dE.values())
+        vstar = min(v for v in dE if dE[v] == dmin)
+        for beta in (0.0, 50.0):
+            v = P.single_step(oracle.OPT_METROPOLIS, z, k, 0, beta, 1.0, 64, seed=3)
             assert np.all(v == vstar)
-        else:
-            assert set(np.unique(v)) <= {vstar, int(z[k])}
+        seen_stay += vstar == z[k]
+        seen_move += vstar != z[k]
+    assert seen_stay and seen_move
 
 
 # ---------------------------------------------------------------------------------------------
@@ -466,18 +471,37 @@ def test_ml_model_reaches_analytic_ground_state():
     assert np.all(e >= egs) and np.mean(e == egs) >= 0.75
 
 
-def test_otm_optimal_move_leaves_a_strict_local_minimum():
-    # E = z^2 - 4z (= (z-2)^2 - 4) at z = 2: every nonzero change costs dE > 0, the best are
-    # v = 1 and v = 3 (dE = 1).  The optimal transition proposes among the nonzero changes
-    # (Sec. 3.3.3), ties to the smallest value, so at r = 1 the move 2 -> 1 happens with
-    # probability exp(-beta) and 2 -> 3 never.
-    from scipy import stats
+def test_otm_optimal_move_is_trapped_at_a_strict_local_minimum():
+    # E = z^2 - 4z (= (z-2)^2 - 4) at z = 2: every change costs dE > 0, so the argmin over the
+    # range is z = 2 itself and at r = 1 the chain never moves (Sec. 3.3.3: always taking the
+    # optimal transition traps the system in a local minimum).  From z = 5 it moves to 2.
     p = I.from_terms(1, [(1, [0, 0]), (-4, [0])], 0, 6)
     P = oracle.Poly(p)
-    beta, n = 0.5, 50_000
-    v = P.single_step(oracle.OPT_METROPOLIS, [2], 0, 0, beta, 1.0, n, seed=8)
-    assert set(np.unique(v)) <= {1, 2}
-    assert stats.binomtest(int((v == 1).sum()), n, math.exp(-beta)).pvalue > 1e-4
+    for beta in (0.0, 0.5):
+        assert np.all(P.single_step(oracle.OPT_METROPOLIS, [2], 0, 0, beta, 1.0, 2000, seed=8) == 2)
+        assert np.all(P.single_step(oracle.OPT_METROPOLIS, [5], 0, 0, beta, 1.0, 2000, seed=8) == 2)
+
+
+def test_otm_ties_on_a_flat_range_go_to_the_lowest_value():
+    # E = z0 z1 with z1 = 0: dE(z0 -> v) = 0 for every v, so the optimal change of z0 is the lowest
+    # value of its range, whatever z0 is (including when z0 already is the lowest value)
+    p = I.from_terms(2, [(3, [0, 1])], [-4, 0], [5, 0])
+    P = oracle.Poly(p)
+    for z0 in (-4, 0, 5):
+        assert np.all(P.single_step(oracle.OPT_METROPOLIS, [z0, 0], 0, 0, 1.0, 1.0, 500, seed=2) == -4)
+
+
+def test_otm_leads_on_the_degree_30_multilinear_chain():
+    # Secs. 4.3-4.4: on the multilinear model with p = 30, u = 1 (N = 100) the optimal-transition
+    # method gives the lowest energies at short runs, where Metropolis and heat bath stay near the
+    # flat E = 0 plateau.  A reading of the optimal transition that excluded the unchanged value
+    # would drive flat variables back and forth between -1 and 0 and stay on the plateau.
+    P = oracle.Poly(I.multilinear(100, 30, 1))
+    beta, _, _ = P.schedule(100)
+    means = {rule: P.anneal(rule, beta, 24, seed=30)[1].mean()
+             for rule in (oracle.METROPOLIS, oracle.HEAT_BATH, oracle.OPT_METROPOLIS)}
+    assert means[oracle.OPT_METROPOLIS] < -30
+    assert means[oracle.OPT_METROPOLIS] < min(means[oracle.METROPOLIS], means[oracle.HEAT_BATH]) - 20
 
 
 def test_initial_state_is_uniform_on_each_box():
