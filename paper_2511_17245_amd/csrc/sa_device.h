@@ -206,21 +206,17 @@ __device__ __forceinline__ Acc record_product(const DevProblem &P, const ZT *z, 
         prod *= no > 1 ? (Acc)z1 : (Acc)1;
         prod *= no > 2 ? (Acc)z2 : (Acc)1;
     } else {
-        // the list is 16-byte aligned and padded with -1 to whole int4: sixteen indices are loaded
-        // before any value is read, and a pad index multiplies by one
+        // the list is 16-byte aligned and padded with -1 to whole int4: four indices per load (a
+        // wider round of loads raises the register count of every kernel that holds this path),
+        // and a pad index multiplies by one
         const int4 *o = (const int4 *)(P.overflow + r.o[0]);
-        for (int f0 = 0; f0 < no; f0 += 16) {
-            int4 q[4];
+        for (int f0 = 0; f0 < no; f0 += 4) {
+            const int4 q = o[f0 / 4];
+            const int32_t ix[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = f0 + 4 * u < no ? o[f0 / 4 + u] : make_int4(-1, -1, -1, -1);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t ix[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int64_t zv = z[ix[c] < 0 ? 0 : ix[c]];
-                    prod *= ix[c] < 0 ? (Acc)1 : (Acc)zv;
-                }
+            for (int c = 0; c < 4; ++c) {
+                const int64_t zv = z[ix[c] < 0 ? 0 : ix[c]];
+                prod *= ix[c] < 0 ? (Acc)1 : (Acc)zv;
             }
         }
     }
@@ -1155,8 +1151,13 @@ __device__ __forceinline__ int64_t sweep_replica(const ReplicaCtx &R, ZT *z, int
 // ------------------------------------------------------------------------------------------------
 // kThreads: 512 (up to 8 waves per replica) or 1024 (16 waves; fewer registers per lane, so only
 // the variants that need no more than 128 VGPRs are built that way).
+// The generic-record Metropolis and OTM variants (the HUIO workloads) are held to 128 VGPRs, four
+// waves per SIMD: their cold paths (long terms, the wide-range argmin) would otherwise raise the
+// register count past 128 and cost a wave per SIMD on every problem.
 template <int kRule, bool kStateInLds, int kRegChunk, int kMaxE, typename Acc, int kThreads>
-__global__ void __launch_bounds__(kThreads) anneal_kernel(AnnealArgs A) {
+__global__ void __launch_bounds__(kThreads, (kThreads == 512 && kRegChunk == 0 && kRule != SA_HEAT_BATH &&
+                                             kRule != SA_HEAT_BATH_CLOSED) ? 4 : 1)
+    anneal_kernel(AnnealArgs A) {
     extern __shared__ int32_t lds_state[];
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)(threadIdx.x / kWave);
