@@ -79,6 +79,9 @@ __device__ __forceinline__ void walk_step(double (&w)[kR], int ql, double &carry
     carry = quad_bcast<kQ>(carry);
 }
 
+// Values per lane of the cold heat-bath draw (at most 4 kCold values of nonzero weight).
+constexpr int kCold = 7;
+
 // Heat-bath draw (Sec. 3.3.2) of one quad: returns the new value.  C: the quad's coefficients.
 // kR: values per lane (4 kR >= W).  jinf[i]: the lane's value index q kR + i as a double when
 // it lies inside this variable's range, +inf past it.
@@ -103,6 +106,64 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
             const double thr = U * (double)W32;
             const uint32_t below = (uint32_t)thr;   // floor: thr >= 0
             return lo + (int64_t)(below < W32 ? below : W32 - 1u);
+        }
+        // Cold draws.  The value at distance d from the minimising end has x = |a1| d, and when
+        // beta x >= 746 its weight is exactly 0 (the exponential clamps its argument at -746, where
+        // the result rounds to 0, as the oracle's exp underflows to 0).  D, the number of distances
+        // with beta x < 746, is found with that same comparison.  When D <= 4 kCold for every
+        // active quad of the wave, only those D values are evaluated, kc per lane (kc from the
+        // wave's largest D, so that the steps skipped are the same for the whole wave), in value
+        // order: the zero weights add nothing to any cumulative sum, and the W - D values outside
+        // the block have C = 0 (minimum at the top) or C = total (minimum at the bottom) and are
+        // counted as the full walk counts them.
+        if (kR >= 16 && kMaxE == 1) {
+            auto pass = [&](uint32_t d) { return beta * (slope_d * (double)d) < 746.0; };
+            const double t = 746.0 * __builtin_amdgcn_rcp(beta * slope_d);
+            uint32_t D = t < (double)W32 ? (uint32_t)__builtin_ceil(t) : W32;
+            D = D < 1u ? 1u : D;
+            if (D < W32 && pass(D)) ++D;
+            if (D < W32 && pass(D)) ++D;
+            if (D > 1u && !pass(D - 1u)) --D;
+            if (D > 1u && !pass(D - 1u)) --D;
+            if (__ballot(D > 4u * kCold) == 0) {
+                // the largest D over the active lanes, one bit at a time (D < 32)
+                uint32_t dmax = 0;
+#pragma unroll
+                for (int bit = 4; bit >= 0; --bit) {
+                    const uint32_t c = dmax | (1u << bit);
+                    if (__ballot(D >= c) != 0) dmax = c;
+                }
+                const uint32_t kc = (dmax + 3u) / 4u;   // uniform over the wave
+                double wc[kCold];
+                bool valid[kCold];
+#pragma unroll
+                for (int i = 0; i < kCold; ++i) {
+                    wc[i] = 0.0;
+                    valid[i] = false;
+                    if ((uint32_t)i < kc) {   // uniform over the wave
+                        const uint32_t pos = (uint32_t)ql * kc + (uint32_t)i;   // position in the block
+                        valid[i] = pos < D;
+                        // block in value order: distance pos from the bottom, or D - 1 - pos from the top
+                        const uint32_t d = from_top ? (valid[i] ? D - 1u - pos : 0u) : pos;
+                        const double wv = exp_nonpos(-(beta * (slope_d * (double)d)));
+                        wc[i] = valid[i] ? wv : 0.0;
+                    }
+                }
+                double carry = 0.0;
+                walk_step<0, kCold>(wc, ql, carry);
+                walk_step<1, kCold>(wc, ql, carry);
+                walk_step<2, kCold>(wc, ql, carry);
+                walk_step<3, kCold>(wc, ql, carry);
+                const double thr = U * carry;
+                uint32_t below = 0;
+#pragma unroll
+                for (int i = 0; i < kCold; ++i) below += valid[i] && wc[i] <= thr ? 1u : 0u;
+                below = quad_sum<uint32_t>(below);
+                // the W - D values outside the block: C = 0 below a top block, C = total above a
+                // bottom block
+                below += (from_top || carry <= thr) ? W32 - D : 0u;
+                return lo + (int64_t)(below < W32 ? below : W32 - 1u);
+            }
         }
         // |a1| times the distance: one rounding of the exact product, as the oracle's conversion of
         // the integer difference (slope * (W - 1) is exact in double: W <= 128)
