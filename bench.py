@@ -466,6 +466,28 @@ def bench_suite(args):
            "config": {"workload": "FC / ML / RI models, N = 100, 100 reads", "otm_enum_max": otm_enum_max},
            "checks": checks, "results": res}
     print(json.dumps(out), flush=True)
+    if args.figures_md:
+        write_suite_md(out, args.figures_md)
+
+
+def write_suite_md(out, path):
+    """A short text summary of a --suite run: its command, the checks, and the timing tables of
+    Figs. 1 and 2."""
+    res = out["results"]
+    lines = ["# Paper experiment suite (Sec. 4, Figs. 1-2): annealing time against range and degree, N = 100",
+             "", "Command: `python " + " ".join(sys.argv) + "`", "",
+             "1000 sweeps, 100 reads, automatic schedule; times are GPU kernel times of the launch that runs",
+             "all reads (best of two).", "", "## Checks", ""]
+    for k, v in out["checks"].items():
+        lines.append(f"- `{k}`: {json.dumps(v)}")
+    lines += ["", "## Time against the range 2u+1 (FC)", "", "| p | u | rule | ms | mean energy / ground state |",
+              "|---|---|---|---|---|"]
+    lines += [f"| {r['p']} | {r['u']} | {r['rule']} | {r['ms']:.2f} | {r['mean_energy_over_gs']:.4f} |"
+              for r in res["time_vs_range"]]
+    lines += ["", "## Time against the degree p (FC u = 1, ML u = 10)", "", "| model | p | rule | ms |", "|---|---|---|---|"]
+    lines += [f"| {r['model']} | {r['p']} | {r['rule']} | {r['ms']:.2f} |" for r in res["time_vs_p"]]
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 def bench_figures(args):
     """The configurations of the paper's Figs. 3-8 (Secs. 4.2-4.4) at N = 100 and its sample
