@@ -95,7 +95,7 @@ def workload(args):
 
 # the sources that define the device program and the data it reads: kernels, their argument
 # layout, the instance packing and the launch choice (geometry and waves per replica)
-KERNEL_SOURCES = ("sa_device.h", "sa_quad.h", "sa_kernels_quad.hip", "sa_kernels.hip", "sa_kernels_heat_bath.hip",
+KERNEL_SOURCES = ("sa_device.h", "sa_quad.h", "sa_kernels_quad.hip", "sa_kernels_quad_mo.hip", "sa_kernels.hip", "sa_kernels_heat_bath.hip",
                   "sa_kernels_heat_bath_closed.hip",
                   "sa_kernels_metropolis.hip", "sa_kernels_otm.hip", "sa_kernels_batch.hip",
                   "sa_kernels_batch16.hip", "sa_kernel_table.h", "sa_internal.h", "sa_host.cpp",

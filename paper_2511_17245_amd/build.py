@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa.so")
 # the annealing kernels are compiled per rule so that the files build in parallel
-SOURCES = ["sa_kernels_heat_bath.hip", "sa_kernels_quad.hip", "sa_kernels_batch.hip", "sa_kernels_batch16.hip", "sa_kernels_heat_bath_closed.hip",
+SOURCES = ["sa_kernels_heat_bath.hip", "sa_kernels_quad.hip", "sa_kernels_quad_mo.hip", "sa_kernels_batch.hip", "sa_kernels_batch16.hip", "sa_kernels_heat_bath_closed.hip",
            "sa_kernels_otm.hip", "sa_kernels_metropolis.hip", "sa_kernels.hip", "sa_noalloc.hip", "sa_api.cpp",
            "sa_host.cpp", "sa_batch.cpp", "sa_server.cpp"]
 

@@ -274,7 +274,7 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
     if (lv.n_levels < 0) {
         std::vector<int32_t> start;
         std::vector<SchedRec> slots;
-        const int32_t nl = build_levels(plan->packed, kQuadWaves * 16, start, slots);
+        const int32_t nl = build_levels(plan->packed, quad_waves(plan->rule) * 16, start, slots);
         const size_t sb = align256(start.size() * sizeof(int32_t));
         const size_t bytes = sb + std::max<size_t>(slots.size(), 1) * sizeof(SchedRec);
         hipError_t e = hipMalloc(&lv.dev, bytes);
@@ -305,26 +305,28 @@ int32_t uniform_width(const std::vector<SchedRec> &slots) {
 }
 
 bool quad_eligible(int rule, const Packed &pk, int device) {
-    if (rule != SA_HEAT_BATH && rule != SA_HEAT_BATH_CLOSED) return false;
-    if (pk.dense || pk.max_exp > 2 || pk.max_width > 4 * kQuadMaxR) return false;
+    const bool heat_bath = rule == SA_HEAT_BATH || rule == SA_HEAT_BATH_CLOSED;
+    if (pk.dense || pk.max_exp > (heat_bath ? 2 : 4) || pk.max_width > 4 * kQuadMaxR) return false;
     int max_lds = 65536;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    return shared_state_bytes(pk.n, kQuadWaves) <= max_lds;
+    return shared_state_bytes(pk.n, quad_waves(rule)) <= max_lds;
 }
 
-int choose_lanes(int requested, int waves_per_replica, bool eligible, int32_t n_levels, int32_t n_slots) {
+int choose_lanes(int rule, int requested, int waves_per_replica, bool eligible, int32_t n_levels, int32_t n_slots) {
     if (requested != 0 && requested != 4 && requested != 64)
         return fail(SA_EINVAL, "lanes_per_update must be 0, 4 or 64"), -1;
     if (requested == 64) return 64;
     if (requested == 4) {
         if (!eligible || waves_per_replica != 0)
-            return fail(SA_EINVAL, "lanes_per_update = 4 needs the heat bath on a sparse problem with exponents "
-                                   "<= 2, ranges of at most 128 values, its state in LDS and waves_per_replica = 0"),
+            return fail(SA_EINVAL, "lanes_per_update = 4 needs a sparse problem with ranges of at most 128 "
+                                   "values, exponents <= 2 (heat bath) or <= 4 (Metropolis, optimal "
+                                   "transition), its state in LDS and waves_per_replica = 0"),
                    -1;
         return 4;
     }
     if (!eligible || waves_per_replica != 0 || n_levels <= 0) return 64;
-    return (int64_t)n_slots >= 64 * (int64_t)n_levels ? 4 : 64;
+    // the quad kernel when its levels fill, on average, half a workgroup's quads
+    return (int64_t)n_slots * 2 >= (int64_t)quad_waves(rule) * 16 * (int64_t)n_levels ? 4 : 64;
 }
 
 int reg_chunk_class(int32_t max_width) {
@@ -453,7 +455,7 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
             return rc;
         }
     }
-    const int lanes = sa::choose_lanes(opts.lanes_per_update, G, eligible, lv ? lv->n_levels : 0,
+    const int lanes = sa::choose_lanes(plan->rule, opts.lanes_per_update, G, eligible, lv ? lv->n_levels : 0,
                                        lv ? lv->n_slots : 0);
     if (lanes < 0) {
         if (tmp) (void)hipFree(tmp);
@@ -474,25 +476,28 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
         q.slots = lv->slots;
         q.n_levels = lv->n_levels;
         q.uniform_width = lv->uniform_width;
+        q.otm_r = a.otm_r;
         q.z_init = zi_dev;
         q.z_out = z_dev;
         q.e_out = e_dev;
         q.trace = t_dev;
         std::string err;
-        rc = sa::launch_quad(plan->rule, q, plan->info.max_width, plan->info.max_exponent,
-                             plan->narrow_ok, stream, err);
+        const bool mo = plan->rule == SA_METROPOLIS || plan->rule == SA_OPT_METROPOLIS;
+        rc = (mo ? sa::launch_quad_mo : sa::launch_quad)(plan->rule, q, plan->info.max_width,
+                                                          plan->info.max_exponent, plan->narrow_ok, stream, err);
         if (rc == SA_OK && t_dev) rc = sa::launch_trace_prefix(t_dev, n_reads, n_traced, stream, err);
         if (rc != SA_OK) {
             if (tmp) (void)hipFree(tmp);
             return fail(rc, err);
         }
         plan->last = sa_launch_info{};
-        plan->last.waves_per_group = sa::kQuadWaves;
+        const int qw = sa::quad_waves(plan->rule);
+        plan->last.waves_per_group = qw;
         plan->last.groups = n_reads;
-        plan->last.lds_bytes = (int32_t)sa::shared_state_bytes(n, sa::kQuadWaves);
+        plan->last.lds_bytes = (int32_t)sa::shared_state_bytes(n, qw);
         plan->last.state_in_lds = 1;
         plan->last.kernel_variant = 2000000 + plan->rule * 100000;
-        plan->last.waves_per_replica = sa::kQuadWaves;
+        plan->last.waves_per_replica = qw;
         plan->last.lanes_per_update = 4;
         plan->last.n_levels = lv->n_levels;
     } else {

@@ -187,19 +187,28 @@ struct QuadArgs {
     const SchedRec *slots;       // level-major variables (device)
     int32_t n_levels;
     int32_t uniform_width;       // the common width W of every slot, or 0 when widths differ
+    double otm_r;                // < 0: r = s/(S-1); else a fixed r (optimal transition)
     const int32_t *z_init;
     int32_t *z_out;
     int64_t *e_out;
     uint64_t *trace;             // as AnnealArgs::trace
 };
-// Waves of the quad kernel's workgroup (one replica); values per lane it keeps in registers.
+// Waves of the quad kernel's workgroup (one replica): heat bath, and Metropolis / optimal
+// transition (one wave: a HUIO level holds about 16 variables, and a single wave needs no
+// barrier between levels); values per lane it keeps in registers.
 constexpr int kQuadWaves = 8;
+constexpr int kQuadWavesMO = 1;
 constexpr int kQuadMaxR = 32;
+inline int quad_waves(int rule) { return rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS ? kQuadWavesMO : kQuadWaves; }
 // Launches the quad kernel for rule (SA_HEAT_BATH or SA_HEAT_BATH_CLOSED), a problem whose widest
 // range is max_width <= 4 * kQuadMaxR and whose exponents are <= max_exp <= 2 (defined in
 // sa_kernels_quad.hip).
 int launch_quad(int rule, const QuadArgs &a, int32_t max_width, int32_t max_exp, bool narrow, void *stream,
                 std::string &err);
+// The same for SA_METROPOLIS and SA_OPT_METROPOLIS, exponents <= max_exp <= 4, kQuadWavesMO waves
+// (defined in sa_kernels_quad_mo.hip).
+int launch_quad_mo(int rule, const QuadArgs &a, int32_t max_width, int32_t max_exp, bool narrow, void *stream,
+                   std::string &err);
 
 struct LaunchChoice {
     int win_waves = 1;         // waves per replica (window width)

@@ -98,8 +98,9 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     std::vector<int32_t> lv_start;
     std::vector<sa::SchedRec> lv_slots;
     int32_t n_levels = 0;
-    if (eligible && G == 0 && opts.lanes_per_update != 64) n_levels = sa::build_levels(pk, sa::kQuadWaves * 16, lv_start, lv_slots);
-    const int lanes = sa::choose_lanes(opts.lanes_per_update, G, eligible, n_levels, (int32_t)lv_slots.size());
+    if (eligible && G == 0 && opts.lanes_per_update != 64)
+        n_levels = sa::build_levels(pk, sa::quad_waves(rule) * 16, lv_start, lv_slots);
+    const int lanes = sa::choose_lanes(rule, opts.lanes_per_update, G, eligible, n_levels, (int32_t)lv_slots.size());
     if (lanes < 0) return SA_EINVAL;
 
     int32_t active = 0;
@@ -133,10 +134,16 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     std::vector<char> image(total, 0);
     sa::stage_packed(pk, L, image.data());
     std::memcpy(image.data() + off_beta, beta.data(), sizeof(double) * (size_t)S);
-    if (!sch.empty()) std::memcpy(image.data() + off_sched, sch.data(), sch.size() * sizeof(sa::SchedRec));
-    if (!lv_start.empty()) std::memcpy(image.data() + off_sched, lv_start.data(), lv_start.size() * sizeof(int32_t));
-    if (!lv_slots.empty())
-        std::memcpy(image.data() + off_slots, lv_slots.data(), lv_slots.size() * sizeof(sa::SchedRec));
+    // only the schedule the chosen kernel reads: the levels are built whenever the quad kernel is
+    // eligible, also when the choice falls on the windows, and share their offset
+    if (lanes == 64) {
+        if (!sch.empty()) std::memcpy(image.data() + off_sched, sch.data(), sch.size() * sizeof(sa::SchedRec));
+    } else {
+        if (!lv_start.empty())
+            std::memcpy(image.data() + off_sched, lv_start.data(), lv_start.size() * sizeof(int32_t));
+        if (!lv_slots.empty())
+            std::memcpy(image.data() + off_slots, lv_slots.data(), lv_slots.size() * sizeof(sa::SchedRec));
+    }
     hipStream_t stream = (hipStream_t)opts.hip_stream;
     e = hipMemcpyAsync(area, image.data(), total, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);   // the host image is freed on return
@@ -183,11 +190,14 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
         q.slots = (const sa::SchedRec *)((char *)area + off_slots);
         q.n_levels = n_levels;
         q.uniform_width = sa::uniform_width(lv_slots);
+        q.otm_r = a.otm_r;
         q.z_init = a.z_init;
         q.z_out = a.z_out;
         q.e_out = a.e_out;
         q.trace = a.trace;
-        rc = sa::launch_quad(rule, q, pk.max_width, pk.max_exp, sa::dE_fits_32(canon), stream, err);
+        const bool mo = rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS;
+        rc = (mo ? sa::launch_quad_mo : sa::launch_quad)(rule, q, pk.max_width, pk.max_exp, sa::dE_fits_32(canon),
+                                                         stream, err);
     } else {
         rc = sa::launch_anneal(rule, a, lc, stream, err);
     }

@@ -211,25 +211,97 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
 }
 
 // The quad's coefficients a_k^(m) of variable k (row `row`, `deg` incidence records): lane q takes
-// records q, q + 4, ...; lanes past the row read the zero record.
-template <int kMaxE, typename Acc>
+// records q, q + 4, ...; lanes past the row read the zero record.  kBatch records per lane are
+// loaded before any is used (their other factors' values then come from LDS together), so a row of
+// up to 4 kBatch records costs one round trip to the caches.
+template <int kMaxE, typename Acc, int kBatch = 1>
 __device__ __forceinline__ void quad_coeffs(const DevProblem &P, const int32_t *z, int32_t row, int32_t deg,
                                             uint32_t emask, int ql, Coeffs<kMaxE, Acc> &C) {
+    if (sizeof(Acc) == 8 && kBatch > 1 && P.coef32) {
+        // every coefficient fits 32 bits: products and sums in 32-bit arithmetic, then sign-extended
+        // (exact: the true values are below 2^31)
+        Coeffs<kMaxE, uint32_t> C32;
+        quad_coeffs<kMaxE, uint32_t, kBatch>(P, z, row, deg, emask, ql, C32);
+#pragma unroll
+        for (int m = 0; m <= kMaxE; ++m) C.a[m] = (Acc)(int64_t)(int32_t)C32.a[m];
+        return;
+    }
     Acc part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
-    for (int32_t c0 = 0; c0 < deg; c0 += 4) {
-        const int32_t idx = c0 + ql < deg ? row + c0 + ql : P.inc_pad;
-        const IncRec r = P.inc[idx];
-        const uint64_t coef = (uint64_t)P.inc_coef[idx];
-        int e;
-        const Acc prod = record_product<Acc, int32_t>(P, z, r, coef, e);
+    for (int32_t c0 = 0; c0 < deg; c0 += 4 * kBatch) {
+        IncRec r[kBatch];
+        uint64_t coef[kBatch];
 #pragma unroll
-        for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
+        for (int u = 0; u < kBatch; ++u) {
+            const int32_t i = c0 + 4 * u + ql;
+            const int32_t idx = i < deg ? row + i : P.inc_pad;
+            r[u] = P.inc[idx];
+            coef[u] = (uint64_t)P.inc_coef[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            int e;
+            const Acc prod = record_product<Acc, int32_t>(P, z, r[u], coef[u], e);
+#pragma unroll
+            for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
+        }
     }
     C.a[0] = 0;
 #pragma unroll
     for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? quad_sum<Acc>(part[m]) : (Acc)0;
+}
+
+// dE of the single proposal z_k -> v (Metropolis), summed over the quad without forming every
+// coefficient: each record adds its product times (v^e - z_k^e), e its exponent of z_k (Sec. 3.2).
+// A linear variable whose coefficient fits 32 bits takes 32-bit products and sum, and one 64-bit
+// multiply by (v - z_k): the same integer.  kBatch records per lane in flight, as quad_coeffs.
+template <int kMaxE, typename Acc, int kBatch>
+__device__ __forceinline__ int64_t quad_direct_delta(const DevProblem &P, const int32_t *z, int32_t row,
+                                                     int32_t deg, int64_t zk, int64_t v, bool linear, int ql) {
+    auto rows = [&](auto &&use) {
+        for (int32_t c0 = 0; c0 < deg; c0 += 4 * kBatch) {
+            IncRec r[kBatch];
+            uint64_t coef[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int32_t i = c0 + 4 * u + ql;
+                const int32_t idx = i < deg ? row + i : P.inc_pad;
+                r[u] = P.inc[idx];
+                coef[u] = (uint64_t)P.inc_coef[idx];
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) use(r[u], coef[u]);
+        }
+    };
+    if (linear) {
+        if (sizeof(Acc) == 8 && P.coef32) {
+            uint32_t part = 0;
+            rows([&](const IncRec &r, uint64_t coef) {
+                int e;
+                part += record_product<uint32_t, int32_t>(P, z, r, coef, e);
+            });
+            return (int64_t)(int32_t)quad_sum<uint32_t>(part) * (v - zk);
+        }
+        Acc part = 0;
+        rows([&](const IncRec &r, uint64_t coef) {
+            int e;
+            part += record_product<Acc, int32_t>(P, z, r, coef, e);
+        });
+        return to_i64<Acc>(quad_sum<Acc>(part) * (Acc)(v - zk));
+    }
+    // v^m - z_k^m for m = 1..4 (kMaxE <= 4 here), as scalars so that they stay in registers
+    const Acc v1 = (Acc)v, z1 = (Acc)zk;
+    const Acc v2 = v1 * v1, z2 = z1 * z1;
+    const Acc d1 = v1 - z1, d2 = v2 - z2, d3 = v2 * v1 - z2 * z1, d4 = v2 * v2 - z2 * z2;
+    Acc part = 0;
+    rows([&](const IncRec &r, uint64_t coef) {
+        int e;
+        const Acc prod = record_product<Acc, int32_t>(P, z, r, coef, e);
+        const Acc dm = kMaxE >= 4 && e == 4 ? d4 : kMaxE >= 3 && e == 3 ? d3 : kMaxE >= 2 && e == 2 ? d2 : d1;
+        part += prod * dm;
+    });
+    return to_i64<Acc>(quad_sum<Acc>(part));
 }
 
 // a_k^(1) of variable k from its compact pair records (multilinear QUIO): h_k + sum_j J_kj z_j.
@@ -252,8 +324,34 @@ __device__ __forceinline__ Acc quad_a1_pairs(const DevProblem &P, const int32_t 
     return quad_sum<Acc>(part);
 }
 
+// Optimal transition of one quad (Sec. 3.3.3, reading R11): the value of smallest dE over the
+// whole range, z_k included, ties to the lowest value.  Lane q evaluates values q kR .. q kR +
+// kR - 1; returns the value, and its dE in dbest.
+template <int kR, int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t quad_argmin(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W, int64_t zk,
+                                               int ql, int64_t &dbest) {
+    int64_t best = INT64_MAX;
+    int64_t bv = INT64_MAX;
+    const uint32_t W32 = (uint32_t)W;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
+        const uint32_t j = (uint32_t)ql * (uint32_t)kR + (uint32_t)i;
+        if (j < W32) {
+            const int64_t d = poly_delta(C, zk, lo + (int64_t)j);
+            if (d < best) {   // values ascend within the lane: the first minimiser is the lowest
+                best = d;
+                bv = lo + (int64_t)j;
+            }
+        }
+    }
+    dbest = quad_min_i64(best);
+    return quad_min_i64(best == dbest ? bv : INT64_MAX);
+}
+
 // kRule: SA_HEAT_BATH, or SA_HEAT_BATH_CLOSED (the O(1) draw of Sec. 3.3.2 for variables whose
-// energy difference is linear, the enumeration for the others).  kR: values per lane (W <= 4 kR).
+// energy difference is linear, the enumeration for the others), SA_METROPOLIS or SA_OPT_METROPOLIS
+// (one proposal per update; the optimal transition by enumeration over the quad).  kR: values per
+// lane (W <= 4 kR).
 template <int kRule, int kR, int kMaxE, typename Acc, int kWaves>
 __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
     extern __shared__ int32_t lds_state[];
@@ -292,29 +390,37 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
             jinf[i] = j < W32 ? (double)j : __builtin_huge_val();
         }
     };
-    if (Wu) set_jinf(Wu);
+    constexpr bool kHeatBath = kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED;
+    if (kHeatBath && Wu) set_jinf(Wu);
     int64_t dE = 0;    // this quad's applied energy changes (the same in its four lanes)
     uint64_t H = 0;    // this quad's change of the state hash in the current sweep (tracing)
     for (int32_t s = A.s_begin; s < A.s_end; ++s) {
         const double beta = A.beta[s];
+        const double r_opt =
+            A.otm_r >= 0.0 ? A.otm_r : (A.n_sweeps > 1 ? (double)s / (double)(A.n_sweeps - 1) : 0.0);
+        // the slot this lane fetches for round ql of the batch at `batch` (a level ending at b1)
+        auto slot_of = [&](int32_t batch, int32_t b1) {
+            const int32_t my_idx = batch + ql * kQuads + qid;
+            SchedRec m;
+            if (my_idx < b1) {
+                m = A.slots[my_idx];
+            } else {
+                m.k = 0;
+                m.lo = 0;
+                m.width = 1;
+                m.row = 0;
+                m.deg = 0;
+                m.emask = 0;
+                m.pad[0] = 0;
+            }
+            return m;
+        };
         for (int32_t l = 0; l < A.n_levels; ++l) {
             const int32_t b0 = A.level_start[l], b1 = A.level_start[l + 1];
             // batches of four rounds: lane q of a quad fetches the slot of the batch's round q and
             // draws its random words; in round q the quad reads them from lane q
             for (int32_t batch = b0; batch < b1; batch += 4 * kQuads) {
-                const int32_t my_idx = batch + ql * kQuads + qid;
-                SchedRec ms;
-                if (my_idx < b1) {
-                    ms = A.slots[my_idx];
-                } else {
-                    ms.k = 0;
-                    ms.lo = 0;
-                    ms.width = 1;
-                    ms.row = 0;
-                    ms.deg = 0;
-                    ms.emask = 0;
-                    ms.pad[0] = 0;
-                }
+                const SchedRec ms = slot_of(batch, b1);
                 uint32_t y0 = (uint32_t)ms.k, y1 = (uint32_t)s, y2 = (uint32_t)read, y3 = A.instance_id;
                 philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
                 for (int q = 0; q < 4; ++q) {
@@ -330,6 +436,7 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                     const uint32_t emask = from_q(ms.emask);
                     const int32_t h = (int32_t)from_q((uint32_t)ms.pad[0]);
                     const uint32_t x1 = from_q(y1), x2 = from_q(y2), x3 = from_q(y3);
+                    const uint32_t x0 = kHeatBath ? 0u : from_q(y0);
                     if (idx < b1) {
                         const double U = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
                         const int64_t zk = z[k];
@@ -337,26 +444,59 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                         if (kMaxE == 1 && P.pair) {
                             C.a[0] = 0;
                             C.a[1] = quad_a1_pairs<Acc>(P, z, row, deg, h, ql);
-                        } else {
-                            quad_coeffs<kMaxE, Acc>(P, z, row, deg, emask, ql, C);
+                        } else if (kRule != SA_METROPOLIS) {
+                            // four records per lane in flight for the optimal transition, whose
+                            // kernels have the registers for them
+                            quad_coeffs<kMaxE, Acc, kHeatBath ? 1 : 4>(P, z, row, deg, emask, ql, C);
                         }
                         const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
-                        int64_t v;
-                        if (kRule == SA_HEAT_BATH_CLOSED && linear) {
-                            v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, x1);
-                        } else {
-                            if (!Wu) set_jinf((uint32_t)W);
-                            v = quad_heat_bath<kR, kMaxE, Acc>(C, lo, W, zk, beta, U, ql, linear, jinf);
+                        int64_t v, d = 0;
+                        bool accept = true;
+                        if constexpr (kRule == SA_METROPOLIS) {
+                            // the proposal first, then dE of that one value from the records
+                            v = lo + (int64_t)(((uint64_t)x1 * (uint64_t)(W - 1)) >> 32);
+                            if (v >= zk) v += 1;
+                            d = kMaxE == 1 && P.pair ? to_i64<Acc>(C.a[1] * (Acc)(v - zk))
+                                                     : quad_direct_delta<kMaxE, Acc, 4>(P, z, row, deg, zk, v, linear, ql);
                         }
-                        if (v != zk) {
+                        if constexpr (kHeatBath) {
+                            if (kRule == SA_HEAT_BATH_CLOSED && linear) {
+                                v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, x1);
+                            } else {
+                                if (!Wu) set_jinf((uint32_t)W);
+                                v = quad_heat_bath<kR, kMaxE, Acc>(C, lo, W, zk, beta, U, ql, linear, jinf);
+                            }
+                        } else {
+                            // the words of the one-wavefront kernel: x0 the optimal-transition branch,
+                            // x1 the proposal, (x2, x3) the acceptance
+                            if (kRule == SA_METROPOLIS) {
+                                // proposal and dE above
+                            } else if (kRule == SA_OPT_METROPOLIS && (double)x0 * 0x1p-32 < r_opt) {
+                                if (linear) {
+                                    // dE = a1 (v - z_k): the lowest value for a1 >= 0, the highest for a1 < 0
+                                    v = to_i64<Acc>(C.a[1]) >= 0 ? lo : lo + W - 1;
+                                    d = to_i64<Acc>(C.a[1] * (Acc)(v - zk));
+                                } else {
+                                    v = quad_argmin<kR, kMaxE, Acc>(C, lo, W, zk, ql, d);
+                                }
+                            } else {
+                                v = lo + (int64_t)(((uint64_t)x1 * (uint64_t)(W - 1)) >> 32);
+                                if (v >= zk) v += 1;
+                                d = poly_delta(C, zk, v);
+                            }
+                            accept = metropolis_accept(d, beta, U);
+                        }
+                        if (accept && v != zk) {
                             z[k] = (int32_t)v;   // the quad's four lanes store the same value
-                            dE += poly_delta(C, zk, v);
+                            dE += kHeatBath ? poly_delta(C, zk, v) : d;
                             if (trace) H += hash_word(k, v) - hash_word(k, zk);
                         }
                     }
                 }
             }
-            window_barrier();
+            // the next level reads what this one wrote: a workgroup barrier between waves (one
+            // wave's LDS accesses complete in order, so a single wave needs none)
+            if constexpr (kWaves > 1) window_barrier();
         }
         if (trace) {
             const uint64_t hw = wave_sum_u64(ql == 0 ? H : 0ull);

@@ -1,6 +1,7 @@
 """GPU: the quad kernel (one update per four lanes over the sweep's dependency levels) against the
-oracle.  Its heat-bath cumulative weights are added in value order, the oracle's order, so reads
-part only where an exponential's last bit decides a draw; the bar is tests/parity.py's."""
+oracle, for the heat bath, Metropolis and the optimal transition.  Its heat-bath cumulative weights
+are added in value order, the oracle's order, so reads part only where an exponential's last bit
+decides a draw; the bar is tests/parity.py's."""
 import numpy as np
 import pytest
 
@@ -22,7 +23,8 @@ def rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def quad_run(prob, rule, beta, n_reads, seed, instance_id=0, init=None, s0=0, s1=0, trace=False, lanes=4):
+def quad_run(prob, rule, beta, n_reads, seed, instance_id=0, init=None, s0=0, s1=0, trace=False, lanes=4,
+             otm_r=-1.0):
     import torch
     plan = sa.Plan(prob, rule)
     z = torch.empty((n_reads, prob.n_vars), dtype=torch.int32, device="cuda")
@@ -32,7 +34,7 @@ def quad_run(prob, rule, beta, n_reads, seed, instance_id=0, init=None, s0=0, s1
     h = torch.empty(n_reads * n_traced, dtype=torch.int64, device="cuda") if trace else None
     plan.run_device(len(beta), n_reads, seed, z, e, beta=beta, stream=torch.cuda.current_stream().cuda_stream,
                     instance_id=instance_id, init_states=zi, sweep_begin=s0, sweep_end=s1, trace=h,
-                    lanes_per_update=lanes)
+                    lanes_per_update=lanes, otm_r=otm_r)
     torch.cuda.synchronize()
     launch = plan.last_launch()
     plan.close()
@@ -43,20 +45,20 @@ def quad_run(prob, rule, beta, n_reads, seed, instance_id=0, init=None, s0=0, s1
     return out
 
 
-def vs_oracle(label, prob, rule, beta, n_reads, seed, instance_id=0):
+def vs_oracle(label, prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0):
     P = oracle.Poly(prob)
-    zg, eg, launch = quad_run(prob, rule, beta, n_reads, seed, instance_id)
-    zo, eo = P.anneal(rule, beta, n_reads, seed, instance_id)
+    zg, eg, launch = quad_run(prob, rule, beta, n_reads, seed, instance_id, otm_r=otm_r)
+    zo, eo = P.anneal(rule, beta, n_reads, seed, instance_id, otm_r=otm_r)
     assert all(int(eg[i]) == P.energy(zg[i]) for i in range(n_reads))
 
     def explain(i):
-        _, _, _, h = quad_run(prob, rule, beta, i + 1, seed, instance_id, trace=True)
+        _, _, _, h = quad_run(prob, rule, beta, i + 1, seed, instance_id, trace=True, otm_r=otm_r)
 
         def after(s, z):
             zz, _, _ = quad_run(prob, rule, beta, i + 1, seed, instance_id, init=np.tile(z, (i + 1, 1)),
-                                s0=s, s1=s + 1)
+                                s0=s, s1=s + 1, otm_r=otm_r)
             return zz[i]
-        return parity.localise(P, rule, beta, seed, instance_id, i, h[i], after)
+        return parity.localise(P, rule, beta, seed, instance_id, i, h[i], after, otm_r=otm_r)
     parity.check(f"{label} {launch}", n_reads, lambda i: eg[i] == eo[i] and np.array_equal(zg[i], zo[i]),
                  explain)
 
@@ -92,6 +94,35 @@ def test_quad_kernel_against_the_oracle(case):
         vs_oracle(f"{name}/{sa.RULE_NAMES[rule]}", prob, rule, beta, reads, 600 + rule, instance_id=5)
 
 
+def mo_cases():
+    r = rng(4141)
+    yield "huio_w101_deg4", I.cfg3_huio(n=400, m=4000).problem, 25, 48
+    yield "huio_powers_w17", I.random_huio(300, 1500, [1, 2, 3, 4], -8, 8, 5, r), 25, 32
+    yield "er_w7", I.erdos_renyi_quio(600, 8.0, -3, 3, 10, 10, r), 25, 32
+    yield "squares_w41", I.random_huio(500, 1500, [1, 2], -20, 20, 6, r), 25, 32
+    yield "er_w128", I.erdos_renyi_quio(400, 4.0, -64, 63, 7, 7, r), 20, 24
+    yield "wide_coefs_64bit", I.random_huio(300, 900, [1, 2, 3], -60, 60, 20000, r), 15, 16
+    yield "ml_p5_long_terms", I.multilinear(120, 5, 2), 25, 16
+    fixed = I.random_huio(300, 1200, [2, 3], -5, 6, 4, r)
+    fixed.lower[::4] = 1
+    fixed.upper[::4] = 1
+    yield "fixed_vars", fixed, 20, 16
+    yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
+    yield "uneven_widths", I.Problem(300, *[getattr(I.random_huio(300, 1200, [1, 2, 3], -4, 4, 5, r), f)
+                                            for f in ("term_ptr", "factor_var", "coef")],
+                                     np.arange(300, dtype=np.int32) % 7 - 12, np.arange(300, dtype=np.int32) % 11), 20, 16
+
+
+@pytest.mark.parametrize("case", list(mo_cases()), ids=lambda c: c[0])
+def test_quad_metropolis_and_optimal_transition_against_the_oracle(case):
+    name, prob, sweeps, reads = case
+    P = oracle.Poly(prob)
+    beta, _, _ = P.schedule(sweeps)
+    for rule, r in ((sa.METROPOLIS, -1.0), (sa.OPT_METROPOLIS, -1.0), (sa.OPT_METROPOLIS, 1.0)):
+        say(name, sa.RULE_NAMES[rule], f"r={r} N={prob.n_vars} S={sweeps} R={reads}")
+        vs_oracle(f"{name}/{sa.RULE_NAMES[rule]}/r={r}", prob, rule, beta, reads, 700 + rule, instance_id=6, otm_r=r)
+
+
 def test_quad_trace_resume_and_determinism():
     prob = I.cfg2_sparse_quio(n=2000).problem
     P = oracle.Poly(prob)
@@ -122,7 +153,8 @@ def test_quad_is_chosen_automatically_for_the_sparse_workload_and_rejected_elsew
     r = rng(1)
     for prob, rule in [(I.dense_quio(80, -5, 5, 5, 5, r), sa.HEAT_BATH),
                        (I.erdos_renyi_quio(200, 4.0, -100, 100, 5, 5, r), sa.HEAT_BATH),
-                       (I.erdos_renyi_quio(200, 4.0, -5, 5, 5, 5, r), sa.METROPOLIS),
+                       (I.erdos_renyi_quio(200, 4.0, -100, 100, 5, 5, r), sa.OPT_METROPOLIS),
+                       (I.from_terms(2, [(1, [0, 0, 0, 0, 0]), (2, [0, 1])], -3, 3), sa.METROPOLIS),
                        (I.from_terms(3, [(1, [0, 0, 0]), (2, [1, 2]), (-1, [0, 1])], -3, 3), sa.HEAT_BATH)]:
         with pytest.raises(sa.SAError) as ex:
             quad_run(prob, rule, np.full(2, 0.1), 2, 1)
