@@ -274,7 +274,11 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
     if (lv.n_levels < 0) {
         std::vector<int32_t> start;
         std::vector<SchedRec> slots;
-        const int32_t nl = build_levels(plan->packed, quad_waves(plan->rule) * 16, start, slots);
+        const bool mo = plan->rule == SA_METROPOLIS || plan->rule == SA_OPT_METROPOLIS;
+        int32_t n_real = 0;
+        const int32_t nl = mo ? build_rounds(plan->packed, slots, n_real)
+                              : build_levels(plan->packed, quad_waves(plan->rule) * 16, start, slots);
+        if (!mo) n_real = (int32_t)slots.size();
         const size_t sb = align256(start.size() * sizeof(int32_t));
         const size_t bytes = sb + std::max<size_t>(slots.size(), 1) * sizeof(SchedRec);
         hipError_t e = hipMalloc(&lv.dev, bytes);
@@ -289,8 +293,9 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy(levels)");
         lv.start = (const int32_t *)lv.dev;
         lv.slots = (const SchedRec *)((char *)lv.dev + sb);
-        lv.n_slots = (int32_t)slots.size();
-        lv.uniform_width = uniform_width(slots);
+        lv.n_slots = n_real;
+        lv.n_rounds = mo ? (int32_t)(slots.size() / kRoundQuads) : 0;
+        lv.uniform_width = mo ? 0 : uniform_width(slots);
         lv.n_levels = nl;
     }
     *out = &lv;
@@ -475,6 +480,7 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
         q.level_start = lv->start;
         q.slots = lv->slots;
         q.n_levels = lv->n_levels;
+        q.n_rounds = lv->n_rounds;
         q.uniform_width = lv->uniform_width;
         q.otm_r = a.otm_r;
         q.z_init = zi_dev;

@@ -596,4 +596,23 @@ int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level
     return n_levels;
 }
 
+int32_t build_rounds(const Packed &p, std::vector<SchedRec> &rounds, int32_t &n_real) {
+    std::vector<int32_t> start;
+    std::vector<SchedRec> slots;
+    const int32_t n_levels = build_levels(p, kRoundQuads, start, slots);
+    const SchedRec idle{-1, 0, 1, 0, 0, 0u, {0, 0}};
+    rounds.clear();
+    for (int32_t l = 0; l < n_levels; ++l) {
+        for (int32_t i = start[(size_t)l]; i < start[(size_t)l + 1]; ++i) {
+            const int32_t k = slots[(size_t)i].k;
+            const VarRec &vr = p.var[(size_t)k];
+            rounds.push_back(SchedRec{k, vr.lo, vr.width, vr.row, vr.deg, p.emask[(size_t)k], {0, 0}});
+        }
+        while (rounds.size() % (size_t)kRoundQuads) rounds.push_back(idle);
+    }
+    while (rounds.size() % (size_t)(kRoundQuads * kRoundBatch)) rounds.push_back(idle);
+    n_real = (int32_t)slots.size();
+    return n_levels;
+}
+
 }  // namespace sa

@@ -122,6 +122,13 @@ int32_t build_schedule(const Packed &p, int G, std::vector<SchedRec> &out);
 // allows.  Returns the number of levels; slots are level-major, level_start has one more entry.
 int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level_start,
                      std::vector<SchedRec> &slots);
+// Rounds of the one-wave quad kernel: the levels of 16 (one wavefront of quads), each cut into
+// rounds of 16 slots and padded to whole rounds with idle slots (k = -1, no records), and the sweep
+// padded with idle rounds to a multiple of kRoundBatch rounds.  Every slot points at its
+// variable's incidence records.  Returns the number of levels; n_real counts the variables placed.
+constexpr int32_t kRoundQuads = 16;
+constexpr int32_t kRoundBatch = 4;
+int32_t build_rounds(const Packed &p, std::vector<SchedRec> &rounds, int32_t &n_real);
 
 // Device view of a packed plan.
 struct DevProblem {
@@ -184,8 +191,9 @@ struct QuadArgs {
     uint32_t key0, key1;
     uint32_t instance_id;
     const int32_t *level_start;  // n_levels + 1 offsets into slots (device)
-    const SchedRec *slots;       // level-major variables (device)
+    const SchedRec *slots;       // level-major variables, or n_rounds rounds of kRoundQuads (device)
     int32_t n_levels;
+    int32_t n_rounds;            // Metropolis / optimal transition: rounds per sweep (build_rounds)
     int32_t uniform_width;       // the common width W of every slot, or 0 when widths differ
     double otm_r;                // < 0: r = s/(S-1); else a fixed r (optimal transition)
     const int32_t *z_init;

@@ -95,12 +95,17 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
 
     // lanes per update, as sa_anneal_ex chooses them
     const bool eligible = sa::quad_eligible(rule, pk, device);
+    // the levels (heat bath) or the rounds (Metropolis, optimal transition) of the quad kernel
+    const bool mo = rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS;
     std::vector<int32_t> lv_start;
     std::vector<sa::SchedRec> lv_slots;
-    int32_t n_levels = 0;
-    if (eligible && G == 0 && opts.lanes_per_update != 64)
-        n_levels = sa::build_levels(pk, sa::quad_waves(rule) * 16, lv_start, lv_slots);
-    const int lanes = sa::choose_lanes(rule, opts.lanes_per_update, G, eligible, n_levels, (int32_t)lv_slots.size());
+    int32_t n_levels = 0, n_real = 0;
+    if (eligible && G == 0 && opts.lanes_per_update != 64) {
+        n_levels = mo ? sa::build_rounds(pk, lv_slots, n_real) : sa::build_levels(pk, sa::quad_waves(rule) * 16,
+                                                                                     lv_start, lv_slots);
+        if (!mo) n_real = (int32_t)lv_slots.size();
+    }
+    const int lanes = sa::choose_lanes(rule, opts.lanes_per_update, G, eligible, n_levels, n_real);
     if (lanes < 0) return SA_EINVAL;
 
     int32_t active = 0;
@@ -189,13 +194,13 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
         q.level_start = (const int32_t *)((char *)area + off_sched);
         q.slots = (const sa::SchedRec *)((char *)area + off_slots);
         q.n_levels = n_levels;
-        q.uniform_width = sa::uniform_width(lv_slots);
+        q.n_rounds = mo ? (int32_t)(lv_slots.size() / sa::kRoundQuads) : 0;
+        q.uniform_width = mo ? 0 : sa::uniform_width(lv_slots);
         q.otm_r = a.otm_r;
         q.z_init = a.z_init;
         q.z_out = a.z_out;
         q.e_out = a.e_out;
         q.trace = a.trace;
-        const bool mo = rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS;
         rc = (mo ? sa::launch_quad_mo : sa::launch_quad)(rule, q, pk.max_width, pk.max_exp, sa::dE_fits_32(canon),
                                                          stream, err);
     } else {

@@ -54,11 +54,12 @@ struct sa_plan {
     Sched sched[17];  // index G = 1, 2, 4, 8, 16
     // dependency levels of the sweep (the quad kernel), built on first use
     struct Levels {
-        void *dev = nullptr;          // level_start (n_levels + 1 int32) then the slots
+        void *dev = nullptr;          // level_start (n_levels + 1 int32) then the slots, or the rounds
         const int32_t *start = nullptr;
         const sa::SchedRec *slots = nullptr;
         int32_t n_levels = -1;        // -1: not built
-        int32_t n_slots = 0;
+        int32_t n_slots = 0;          // variables placed (idle slots of the rounds not counted)
+        int32_t n_rounds = 0;         // Metropolis / optimal transition: rounds of kRoundQuads slots
         int32_t uniform_width = 0;    // common width of every slot, 0 when they differ
     };
     Levels levels;
