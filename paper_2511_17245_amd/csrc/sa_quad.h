@@ -211,97 +211,24 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
 }
 
 // The quad's coefficients a_k^(m) of variable k (row `row`, `deg` incidence records): lane q takes
-// records q, q + 4, ...; lanes past the row read the zero record.  kBatch records per lane are
-// loaded before any is used (their other factors' values then come from LDS together), so a row of
-// up to 4 kBatch records costs one round trip to the caches.
-template <int kMaxE, typename Acc, int kBatch = 1>
+// records q, q + 4, ...; lanes past the row read the zero record.
+template <int kMaxE, typename Acc>
 __device__ __forceinline__ void quad_coeffs(const DevProblem &P, const int32_t *z, int32_t row, int32_t deg,
                                             uint32_t emask, int ql, Coeffs<kMaxE, Acc> &C) {
-    if (sizeof(Acc) == 8 && kBatch > 1 && P.coef32) {
-        // every coefficient fits 32 bits: products and sums in 32-bit arithmetic, then sign-extended
-        // (exact: the true values are below 2^31)
-        Coeffs<kMaxE, uint32_t> C32;
-        quad_coeffs<kMaxE, uint32_t, kBatch>(P, z, row, deg, emask, ql, C32);
-#pragma unroll
-        for (int m = 0; m <= kMaxE; ++m) C.a[m] = (Acc)(int64_t)(int32_t)C32.a[m];
-        return;
-    }
     Acc part[kMaxE + 1];
 #pragma unroll
     for (int m = 0; m <= kMaxE; ++m) part[m] = 0;
-    for (int32_t c0 = 0; c0 < deg; c0 += 4 * kBatch) {
-        IncRec r[kBatch];
-        uint64_t coef[kBatch];
+    for (int32_t c0 = 0; c0 < deg; c0 += 4) {
+        const int32_t i = c0 + ql;
+        const int32_t idx = i < deg ? row + i : P.inc_pad;
+        int e;
+        const Acc prod = record_product<Acc, int32_t>(P, z, P.inc[idx], (uint64_t)P.inc_coef[idx], e);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int32_t i = c0 + 4 * u + ql;
-            const int32_t idx = i < deg ? row + i : P.inc_pad;
-            r[u] = P.inc[idx];
-            coef[u] = (uint64_t)P.inc_coef[idx];
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            int e;
-            const Acc prod = record_product<Acc, int32_t>(P, z, r[u], coef[u], e);
-#pragma unroll
-            for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
-        }
+        for (int m = 1; m <= kMaxE; ++m) part[m] += (kMaxE == 1 || e == m) ? prod : (Acc)0;
     }
     C.a[0] = 0;
 #pragma unroll
     for (int m = 1; m <= kMaxE; ++m) C.a[m] = (emask & (1u << m)) ? quad_sum<Acc>(part[m]) : (Acc)0;
-}
-
-// dE of the single proposal z_k -> v (Metropolis), summed over the quad without forming every
-// coefficient: each record adds its product times (v^e - z_k^e), e its exponent of z_k (Sec. 3.2).
-// A linear variable whose coefficient fits 32 bits takes 32-bit products and sum, and one 64-bit
-// multiply by (v - z_k): the same integer.  kBatch records per lane in flight, as quad_coeffs.
-template <int kMaxE, typename Acc, int kBatch>
-__device__ __forceinline__ int64_t quad_direct_delta(const DevProblem &P, const int32_t *z, int32_t row,
-                                                     int32_t deg, int64_t zk, int64_t v, bool linear, int ql) {
-    auto rows = [&](auto &&use) {
-        for (int32_t c0 = 0; c0 < deg; c0 += 4 * kBatch) {
-            IncRec r[kBatch];
-            uint64_t coef[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int32_t i = c0 + 4 * u + ql;
-                const int32_t idx = i < deg ? row + i : P.inc_pad;
-                r[u] = P.inc[idx];
-                coef[u] = (uint64_t)P.inc_coef[idx];
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) use(r[u], coef[u]);
-        }
-    };
-    if (linear) {
-        if (sizeof(Acc) == 8 && P.coef32) {
-            uint32_t part = 0;
-            rows([&](const IncRec &r, uint64_t coef) {
-                int e;
-                part += record_product<uint32_t, int32_t>(P, z, r, coef, e);
-            });
-            return (int64_t)(int32_t)quad_sum<uint32_t>(part) * (v - zk);
-        }
-        Acc part = 0;
-        rows([&](const IncRec &r, uint64_t coef) {
-            int e;
-            part += record_product<Acc, int32_t>(P, z, r, coef, e);
-        });
-        return to_i64<Acc>(quad_sum<Acc>(part) * (Acc)(v - zk));
-    }
-    // v^m - z_k^m for m = 1..4 (kMaxE <= 4 here), as scalars so that they stay in registers
-    const Acc v1 = (Acc)v, z1 = (Acc)zk;
-    const Acc v2 = v1 * v1, z2 = z1 * z1;
-    const Acc d1 = v1 - z1, d2 = v2 - z2, d3 = v2 * v1 - z2 * z1, d4 = v2 * v2 - z2 * z2;
-    Acc part = 0;
-    rows([&](const IncRec &r, uint64_t coef) {
-        int e;
-        const Acc prod = record_product<Acc, int32_t>(P, z, r, coef, e);
-        const Acc dm = kMaxE >= 4 && e == 4 ? d4 : kMaxE >= 3 && e == 3 ? d3 : kMaxE >= 2 && e == 2 ? d2 : d1;
-        part += prod * dm;
-    });
-    return to_i64<Acc>(quad_sum<Acc>(part));
 }
 
 // a_k^(1) of variable k from its compact pair records (multilinear QUIO): h_k + sum_j J_kj z_j.
@@ -324,7 +251,7 @@ __device__ __forceinline__ Acc quad_a1_pairs(const DevProblem &P, const int32_t 
     return quad_sum<Acc>(part);
 }
 
-// Optimal transition of one quad (Sec. 3.3.3, reading R11): the value of smallest dE over the
+// Optimal transition of one quad (Sec. 3.3.3, as read here): the value of smallest dE over the
 // whole range, z_k included, ties to the lowest value.  Lane q evaluates values q kR .. q kR +
 // kR - 1; returns the value, and its dE in dbest.
 template <int kR, int kMaxE, typename Acc>
@@ -349,9 +276,8 @@ __device__ __forceinline__ int64_t quad_argmin(const Coeffs<kMaxE, Acc> &C, int6
 }
 
 // kRule: SA_HEAT_BATH, or SA_HEAT_BATH_CLOSED (the O(1) draw of Sec. 3.3.2 for variables whose
-// energy difference is linear, the enumeration for the others), SA_METROPOLIS or SA_OPT_METROPOLIS
-// (one proposal per update; the optimal transition by enumeration over the quad).  kR: values per
-// lane (W <= 4 kR).
+// energy difference is linear, the enumeration for the others).  kR: values per lane (W <= 4 kR).
+// Metropolis and the optimal transition have a kernel of their own (sa_quad_mo.h).
 template <int kRule, int kR, int kMaxE, typename Acc, int kWaves>
 __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
     extern __shared__ int32_t lds_state[];
@@ -390,14 +316,12 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
             jinf[i] = j < W32 ? (double)j : __builtin_huge_val();
         }
     };
-    constexpr bool kHeatBath = kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED;
-    if (kHeatBath && Wu) set_jinf(Wu);
+    static_assert(kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED, "heat-bath rules only");
+    if (Wu) set_jinf(Wu);
     int64_t dE = 0;    // this quad's applied energy changes (the same in its four lanes)
     uint64_t H = 0;    // this quad's change of the state hash in the current sweep (tracing)
     for (int32_t s = A.s_begin; s < A.s_end; ++s) {
         const double beta = A.beta[s];
-        const double r_opt =
-            A.otm_r >= 0.0 ? A.otm_r : (A.n_sweeps > 1 ? (double)s / (double)(A.n_sweeps - 1) : 0.0);
         // the slot this lane fetches for round ql of the batch at `batch` (a level ending at b1)
         auto slot_of = [&](int32_t batch, int32_t b1) {
             const int32_t my_idx = batch + ql * kQuads + qid;
@@ -436,7 +360,6 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                     const uint32_t emask = from_q(ms.emask);
                     const int32_t h = (int32_t)from_q((uint32_t)ms.pad[0]);
                     const uint32_t x1 = from_q(y1), x2 = from_q(y2), x3 = from_q(y3);
-                    const uint32_t x0 = kHeatBath ? 0u : from_q(y0);
                     if (idx < b1) {
                         const double U = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
                         const int64_t zk = z[k];
@@ -444,51 +367,20 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                         if (kMaxE == 1 && P.pair) {
                             C.a[0] = 0;
                             C.a[1] = quad_a1_pairs<Acc>(P, z, row, deg, h, ql);
-                        } else if (kRule != SA_METROPOLIS) {
-                            // four records per lane in flight for the optimal transition, whose
-                            // kernels have the registers for them
-                            quad_coeffs<kMaxE, Acc, kHeatBath ? 1 : 4>(P, z, row, deg, emask, ql, C);
+                        } else {
+                            quad_coeffs<kMaxE, Acc>(P, z, row, deg, emask, ql, C);
                         }
                         const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
-                        int64_t v, d = 0;
-                        bool accept = true;
-                        if constexpr (kRule == SA_METROPOLIS) {
-                            // the proposal first, then dE of that one value from the records
-                            v = lo + (int64_t)(((uint64_t)x1 * (uint64_t)(W - 1)) >> 32);
-                            if (v >= zk) v += 1;
-                            d = kMaxE == 1 && P.pair ? to_i64<Acc>(C.a[1] * (Acc)(v - zk))
-                                                     : quad_direct_delta<kMaxE, Acc, 4>(P, z, row, deg, zk, v, linear, ql);
-                        }
-                        if constexpr (kHeatBath) {
-                            if (kRule == SA_HEAT_BATH_CLOSED && linear) {
-                                v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, x1);
-                            } else {
-                                if (!Wu) set_jinf((uint32_t)W);
-                                v = quad_heat_bath<kR, kMaxE, Acc>(C, lo, W, zk, beta, U, ql, linear, jinf);
-                            }
+                        int64_t v;
+                        if (kRule == SA_HEAT_BATH_CLOSED && linear) {
+                            v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, x1);
                         } else {
-                            // the words of the one-wavefront kernel: x0 the optimal-transition branch,
-                            // x1 the proposal, (x2, x3) the acceptance
-                            if (kRule == SA_METROPOLIS) {
-                                // proposal and dE above
-                            } else if (kRule == SA_OPT_METROPOLIS && (double)x0 * 0x1p-32 < r_opt) {
-                                if (linear) {
-                                    // dE = a1 (v - z_k): the lowest value for a1 >= 0, the highest for a1 < 0
-                                    v = to_i64<Acc>(C.a[1]) >= 0 ? lo : lo + W - 1;
-                                    d = to_i64<Acc>(C.a[1] * (Acc)(v - zk));
-                                } else {
-                                    v = quad_argmin<kR, kMaxE, Acc>(C, lo, W, zk, ql, d);
-                                }
-                            } else {
-                                v = lo + (int64_t)(((uint64_t)x1 * (uint64_t)(W - 1)) >> 32);
-                                if (v >= zk) v += 1;
-                                d = poly_delta(C, zk, v);
-                            }
-                            accept = metropolis_accept(d, beta, U);
+                            if (!Wu) set_jinf((uint32_t)W);
+                            v = quad_heat_bath<kR, kMaxE, Acc>(C, lo, W, zk, beta, U, ql, linear, jinf);
                         }
-                        if (accept && v != zk) {
+                        if (v != zk) {
                             z[k] = (int32_t)v;   // the quad's four lanes store the same value
-                            dE += kHeatBath ? poly_delta(C, zk, v) : d;
+                            dE += poly_delta(C, zk, v);
                             if (trace) H += hash_word(k, v) - hash_word(k, zk);
                         }
                     }

@@ -63,6 +63,22 @@ def vs_oracle(label, prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0)
                  explain)
 
 
+def hub_huio(r):
+    """HUIO of 200 variables where variable 0 sits in about 150 terms and variable 1 in about 70
+    (rows longer than the 64 records per update that the Metropolis / optimal-transition kernel
+    loads one round ahead), some of them with four other factors."""
+    base = I.random_huio(200, 500, [2, 3], -6, 6, 4, r)
+    terms = [(int(base.coef[t]), base.factor_var[base.term_ptr[t]:base.term_ptr[t + 1]].tolist())
+             for t in range(len(base.coef))]
+    for _ in range(150):
+        terms.append((int(r.integers(-4, 5)) or 1, [0, int(r.integers(2, 200))]))
+    for _ in range(60):
+        terms.append((int(r.integers(-4, 5)) or 1, [1, 1, int(r.integers(2, 200))]))
+    for _ in range(10):
+        terms.append((int(r.integers(-2, 3)) or 1, [1] + [int(x) for x in r.integers(2, 200, size=4)]))
+    return I.from_terms(200, terms, -6, 6)
+
+
 def cases():
     r = rng(4040)
     yield "er_w101_n3000", I.cfg2_sparse_quio(n=3000).problem, 30, 48
@@ -79,6 +95,7 @@ def cases():
     yield "fixed_vars_w18", fixed, 20, 16
     yield "wide_coefs_64bit", I.random_huio(300, 900, [1, 2], -60, 60, 20000, r), 15, 16
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
+    yield "hub_rows", hub_huio(r), 20, 16
     yield "uneven_widths", I.Problem(300, *[getattr(I.erdos_renyi_quio(300, 5.0, -4, 4, 6, 6, r), f)
                                             for f in ("term_ptr", "factor_var", "coef")],
                                      np.arange(300, dtype=np.int32) % 7 - 12, np.arange(300, dtype=np.int32) % 11)
@@ -108,6 +125,7 @@ def mo_cases():
     fixed.upper[::4] = 1
     yield "fixed_vars", fixed, 20, 16
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
+    yield "hub_rows", hub_huio(r), 20, 16
     yield "uneven_widths", I.Problem(300, *[getattr(I.random_huio(300, 1200, [1, 2, 3], -4, 4, 5, r), f)
                                             for f in ("term_ptr", "factor_var", "coef")],
                                      np.arange(300, dtype=np.int32) % 7 - 12, np.arange(300, dtype=np.int32) % 11), 20, 16
@@ -123,11 +141,13 @@ def test_quad_metropolis_and_optimal_transition_against_the_oracle(case):
         vs_oracle(f"{name}/{sa.RULE_NAMES[rule]}/r={r}", prob, rule, beta, reads, 700 + rule, instance_id=6, otm_r=r)
 
 
-def test_quad_trace_resume_and_determinism():
-    prob = I.cfg2_sparse_quio(n=2000).problem
+@pytest.mark.parametrize("kind", ["heat_bath", "metropolis_otm"])
+def test_quad_trace_resume_and_determinism(kind):
+    prob = I.cfg2_sparse_quio(n=2000).problem if kind == "heat_bath" else I.cfg3_huio(n=600, m=6000).problem
     P = oracle.Poly(prob)
     beta, _, _ = P.schedule(20)
-    for rule in HB:
+    for rule in (HB if kind == "heat_bath" else (sa.METROPOLIS, sa.OPT_METROPOLIS)):
+        say(kind, sa.RULE_NAMES[rule], "trace, resume at sweep 7, repeat")
         z, e, _, h = quad_run(prob, rule, beta, 16, 9, trace=True)
         _, _, ho = P.anneal(rule, beta, 16, 9, trace=True)
         assert np.array_equal(h, ho)
