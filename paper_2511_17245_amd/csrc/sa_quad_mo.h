@@ -44,52 +44,84 @@ struct RoundRecs {
 template <bool kNarrow>
 __device__ __forceinline__ void load_round(const DevProblem &P, int32_t row, int32_t deg, int ql,
                                            RoundRecs<kNarrow> &R) {
+    // 32-bit byte offsets from the arrays' (uniform) bases: the instance is far below 4 GiB
+    const char *inc = (const char *)P.inc;
+    const char *coef = (const char *)P.inc_coef;
 #pragma unroll
     for (int u = 0; u < kMoAhead; ++u) {
         const int32_t i = 4 * u + ql;
-        const int32_t idx = i < deg ? row + i : P.inc_pad;
-        R.r[u] = P.inc[idx];
+        const uint32_t idx = (uint32_t)(i < deg ? row + i : P.inc_pad);
+        R.r[u] = *(const IncRec *)(inc + idx * 16u);
         if constexpr (kNarrow)
-            R.c[u] = ((const uint32_t *)P.inc_coef)[2 * (size_t)idx];   // low word (little-endian)
+            R.c[u] = *(const uint32_t *)(coef + idx * 8u);   // low word (little-endian)
         else
-            R.c[u] = (uint64_t)P.inc_coef[idx];
+            R.c[u] = *(const uint64_t *)(coef + idx * 8u);
     }
 }
 
-// a[m] += the products J_t prod(other factors) of this lane's records whose exponent of z_k is m
+// The LDS reads of group g (records 4g .. 4g + 3) of this lane: the other factors' values.
+template <bool kNarrow>
+__device__ __forceinline__ void read_group(const int32_t *z, const RoundRecs<kNarrow> &R, int g,
+                                           int32_t (&zv)[4][3]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const IncRec &r = R.r[4 * g + u];
+        // unused inline slots hold index 0; a long record reads z_0 (masked: no branch)
+        const int32_t inl = -(int32_t)((r.meta >> 8) <= 3u);
+        zv[u][0] = z[r.o[0] & inl];
+        zv[u][1] = z[r.o[1] & inl];
+        zv[u][2] = z[r.o[2] & inl];
+    }
+}
+
+// a[m] += the products J_t prod(other factors) of group g's records whose exponent of z_k is m
 // (Sec. 3.2: a_k^(m)), for the records with at most three other factors, which are inline; a
-// record with more sets `longs` and is added by the caller.  Records of a group of four are
-// read from LDS together before any product is formed.
+// record with more sets `longs` and is added by the caller.  When no record of the group, in any
+// lane, holds z_k to a power above one, every product goes to a_k^(1) (the zero record adds 0).
+template <int kMaxE, typename Part, bool kNarrow>
+__device__ __forceinline__ void add_group(const RoundRecs<kNarrow> &R, int g, const int32_t (&zv)[4][3],
+                                          Part (&a)[kMaxE + 1], bool &longs) {
+    Part p[4];
+    bool high = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const IncRec &r = R.r[4 * g + u];
+        const uint32_t no = r.meta >> 8;
+        Part q = (Part)R.c[4 * g + u];
+        q *= no > 0 ? (Part)(int64_t)zv[u][0] : (Part)1;
+        q *= no > 1 ? (Part)(int64_t)zv[u][1] : (Part)1;
+        q *= no > 2 ? (Part)(int64_t)zv[u][2] : (Part)1;
+        longs |= no > 3;
+        p[u] = no <= 3 ? q : (Part)0;
+        high |= (r.meta & 0xFFu) > 1u;
+    }
+    if (kMaxE == 1 || __ballot(high) == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[1] += p[u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t e = R.r[4 * g + u].meta & 0xFFu;
+#pragma unroll
+            for (int m = 1; m <= kMaxE; ++m) a[m] += e == (uint32_t)m ? p[u] : (Part)0;
+        }
+    }
+}
+
+// All groups a quad's row reaches (the wave runs as many as its longest row needs); the LDS reads
+// of the next group go out before the current group's products.
 template <int kMaxE, typename Part, bool kNarrow>
 __device__ __forceinline__ void add_records(const int32_t *z, const RoundRecs<kNarrow> &R, int32_t deg,
                                             Part (&a)[kMaxE + 1], bool &longs) {
+    constexpr int kGroups = kMoAhead / 4;
+    int32_t zA[4][3], zB[4][3];
+    read_group<kNarrow>(z, R, 0, zA);
 #pragma unroll
-    for (int g = 0; g < kMoAhead / 4; ++g) {
-        if (__ballot(deg > 16 * g) == 0) break;   // uniform: no quad's row reaches this group
-        int32_t zv[4][3];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const IncRec &r = R.r[4 * g + u];
-            // unused inline slots hold index 0; a long record reads z_0 (masked: no branch)
-            const int32_t inl = -(int32_t)((r.meta >> 8) <= 3u);
-            zv[u][0] = z[r.o[0] & inl];
-            zv[u][1] = z[r.o[1] & inl];
-            zv[u][2] = z[r.o[2] & inl];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const IncRec &r = R.r[4 * g + u];
-            const uint32_t no = r.meta >> 8;
-            const int e = (int)(r.meta & 0xFFu);
-            Part p = (Part)R.c[4 * g + u];
-            p *= no > 0 ? (Part)(int64_t)zv[u][0] : (Part)1;
-            p *= no > 1 ? (Part)(int64_t)zv[u][1] : (Part)1;
-            p *= no > 2 ? (Part)(int64_t)zv[u][2] : (Part)1;
-            longs |= no > 3;
-            p = no <= 3 ? p : (Part)0;
-#pragma unroll
-            for (int m = 1; m <= kMaxE; ++m) a[m] += (kMaxE == 1 || e == m) ? p : (Part)0;
-        }
+    for (int g = 0; g < kGroups; ++g) {
+        const bool more = g + 1 < kGroups && __ballot(deg > 16 * (g + 1)) != 0;   // uniform
+        if (more) read_group<kNarrow>(z, R, g + 1, (g & 1) ? zA : zB);
+        add_group<kMaxE, Part, kNarrow>(R, g, (g & 1) ? zB : zA, a, longs);
+        if (!more) break;
     }
 }
 
