@@ -85,14 +85,15 @@ constexpr int kCold = 7;
 // Heat-bath draw (Sec. 3.3.2) of one quad: returns the new value.  C: the quad's coefficients.
 // kR: values per lane (4 kR >= W).  jinf[i]: the lane's value index q kR + i as a double when
 // it lies inside this variable's range, +inf past it.
-template <int kR, int kMaxE, typename Acc>
+template <int kR, int kMaxE, typename Acc, bool kFact>
 __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W, int64_t zk,
                                                   double beta, double U, int ql, bool linear_in,
-                                                  const double (&jinf)[kR]) {
+                                                  const double (&jinf)[kR], uint32_t Wu) {
     const uint32_t W32 = (uint32_t)W;
     const uint32_t j0 = (uint32_t)ql * (uint32_t)kR;
     const bool linear = kMaxE == 1 || linear_in;
     double w[kR];
+    uint32_t skip = 0;   // places before the range that the count below includes
     if (linear) {
         // dE(v) = a1 (v - z_k): its minimum is at an end of the range, and dE_v - dE_min is |a1|
         // times the distance of v from that end (an exact integer, converted to double with one
@@ -165,16 +166,64 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
                 return lo + (int64_t)(below < W32 ? below : W32 - 1u);
             }
         }
-        // |a1| times the distance: one rounding of the exact product, as the oracle's conversion of
-        // the integer difference (slope * (W - 1) is exact in double: W <= 128)
-        const double s_slope = from_top ? -slope_d : slope_d;
-        const double o_slope = from_top ? slope_d * (double)(W32 - 1u) : 0.0;
+        // Factored weights (kFact: every variable of the launch has the same width W, kR >= 16 and
+        // nd = 4 kR - W <= kR / 4).  The weight at distance d from the minimising end is e^(-c d),
+        // c = beta |a1|, and d = D + t splits it into e^(-c D) e^(-c t): per lane, one exponential
+        // per group of 8 values (its base distance D) and the 8 shared e^(-c t), t = 0..7 (two per
+        // lane of the quad), then one product per value.  The nd places past the range are laid
+        // at the first nd places of lane 0 (minimum at the top: the lanes' windows end at the top
+        // of the range, lane q holding indices W - (4 - q) kR ..) or the last nd of lane 3
+        // (minimum at the bottom: lane q holds q kR ..), where they weigh 0; both layouts are in
+        // value order, so the walk below is the same.  A product rounds once more than the direct
+        // exponential of the oracle, and the two exponents are rounded apart: a draw can differ
+        // only where U C_u falls within a few ulp of a cumulative weight.
+        if constexpr (kFact) {
+            // the lane's smallest distance (both layouts)
+            const uint32_t a = from_top ? (3u - (uint32_t)ql) * (uint32_t)kR : (uint32_t)ql * (uint32_t)kR;
+            auto wexp = [&](uint32_t d) { return exp_nonpos(-(beta * (slope_d * (double)d))); };
+            // e^(-c t), t = 0..7, in the order the lane's groups take them: t = s at the bottom,
+            // t = 7 - s at the top (a group's distances descend there)
+            const double e0 = wexp(2u * (uint32_t)ql), e1 = wexp(2u * (uint32_t)ql + 1u);
+            const double E[8] = {quad_bcast<0>(e0), quad_bcast<0>(e1), quad_bcast<1>(e0), quad_bcast<1>(e1),
+                                 quad_bcast<2>(e0), quad_bcast<2>(e1), quad_bcast<3>(e0), quad_bcast<3>(e1)};
+            double Eo[8];
 #pragma unroll
-        for (int i = 0; i < kR; ++i) {
-            // a value past the range has index +inf, so x = +inf and the argument -(beta x) = -inf
-            // (beta x > 0 here), which the exponential clamps to a weight of exactly 0
-            const double x = __builtin_fabs(fma(jinf[i], s_slope, o_slope));
-            w[i] = exp_nonpos(-(beta * x));
+            for (int t = 0; t < 8; ++t) Eo[t] = from_top ? E[7 - t] : E[t];
+            // group m (slots 8m .. 8m + 7) starts at distance a + 8m (bottom) or ends at a +
+            // kR - 1 - 8m (top); the kR mod 8 slots after the whole groups take Eo[8 - kR % 8 + r]
+            // with a base chosen to match
+            constexpr int kG = kR / 8, kRest = kR % 8;
+            double F[kG + 1];
+#pragma unroll
+            for (int m = 0; m < kG; ++m)
+                F[m] = wexp(a + (from_top ? (uint32_t)(kR - 8 - 8 * m) : (uint32_t)(8 * m)));
+            if (kRest) F[kG] = wexp(a + (from_top ? 0u : (uint32_t)(8 * kG - 8 + kRest)));
+            // only a lane's first and last kR / 4 values can lie past the range
+            constexpr int kEdge = kR / 4;
+            const int32_t jlane = from_top ? (int32_t)W32 - (4 - ql) * kR : ql * kR;   // index of slot 0
+#pragma unroll
+            for (int i = 0; i < kR; ++i) {
+                const double f = i < 8 * kG ? F[i / 8] * Eo[i % 8] : F[kG] * Eo[8 - kRest + (i - 8 * kG)];
+                if (i < kEdge || i >= kR - kEdge)
+                    w[i] = (uint32_t)(jlane + i) < W32 ? f : 0.0;
+                else
+                    w[i] = f;
+            }
+            const uint32_t nd = 4u * (uint32_t)kR - Wu;   // places past the range, the same for every quad
+            // the nd empty places before the range (minimum at the top) have C = 0 and are counted
+            skip = from_top ? nd : 0u;
+        } else {
+            // |a1| times the distance: one rounding of the exact product, as the oracle's conversion of
+            // the integer difference (slope * (W - 1) is exact in double: W <= 128)
+            const double s_slope = from_top ? -slope_d : slope_d;
+            const double o_slope = from_top ? slope_d * (double)(W32 - 1u) : 0.0;
+#pragma unroll
+            for (int i = 0; i < kR; ++i) {
+                // a value past the range has index +inf, so x = +inf and the argument -(beta x) = -inf
+                // (beta x > 0 here), which the exponential clamps to a weight of exactly 0
+                const double x = __builtin_fabs(fma(jinf[i], s_slope, o_slope));
+                w[i] = exp_nonpos(-(beta * x));
+            }
         }
     } else {
         int64_t dmin = INT64_MAX;
@@ -206,7 +255,7 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
     uint32_t below = 0;
 #pragma unroll
     for (int i = 0; i < kR; ++i) below += w[i] <= thr ? 1u : 0u;
-    below = quad_sum<uint32_t>(below);
+    below = quad_sum<uint32_t>(below) - skip;
     return lo + (int64_t)(below < W32 ? below : W32 - 1u);
 }
 
@@ -277,8 +326,10 @@ __device__ __forceinline__ int64_t quad_argmin(const Coeffs<kMaxE, Acc> &C, int6
 
 // kRule: SA_HEAT_BATH, or SA_HEAT_BATH_CLOSED (the O(1) draw of Sec. 3.3.2 for variables whose
 // energy difference is linear, the enumeration for the others).  kR: values per lane (W <= 4 kR).
-// Metropolis and the optimal transition have a kernel of their own (sa_quad_mo.h).
-template <int kRule, int kR, int kMaxE, typename Acc, int kWaves>
+// kFact: the factored weights of linear variables (quad_heat_bath), for launches whose variables
+// all have one width W with 4 kR - W <= kR / 4.  Metropolis and the optimal transition have a
+// kernel of their own (sa_quad_mo.h).
+template <int kRule, int kR, int kMaxE, typename Acc, int kWaves, bool kFact = false>
 __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
     extern __shared__ int32_t lds_state[];
     const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -317,7 +368,7 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
         }
     };
     static_assert(kRule == SA_HEAT_BATH || kRule == SA_HEAT_BATH_CLOSED, "heat-bath rules only");
-    if (Wu) set_jinf(Wu);
+    if (!kFact && Wu) set_jinf(Wu);   // the factored weights need no indexes
     int64_t dE = 0;    // this quad's applied energy changes (the same in its four lanes)
     uint64_t H = 0;    // this quad's change of the state hash in the current sweep (tracing)
     for (int32_t s = A.s_begin; s < A.s_end; ++s) {
@@ -375,8 +426,8 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                         if (kRule == SA_HEAT_BATH_CLOSED && linear) {
                             v = heat_bath_closed(to_i64<Acc>(C.a[1]), lo, W, beta, U, x1);
                         } else {
-                            if (!Wu) set_jinf((uint32_t)W);
-                            v = quad_heat_bath<kR, kMaxE, Acc>(C, lo, W, zk, beta, U, ql, linear, jinf);
+                            if (!kFact && !Wu) set_jinf((uint32_t)W);
+                            v = quad_heat_bath<kR, kMaxE, Acc, kFact>(C, lo, W, zk, beta, U, ql, linear, jinf, Wu);
                         }
                         if (v != zk) {
                             z[k] = (int32_t)v;   // the quad's four lanes store the same value

@@ -63,6 +63,12 @@ def vs_oracle(label, prob, rule, beta, n_reads, seed, instance_id=0, otm_r=-1.0)
                  explain)
 
 
+def uneven(p):
+    """The terms of p over 300 variables whose widths run through 7..23 (bounds i % 7 - 12 .. i % 11)."""
+    n = np.arange(300, dtype=np.int32)
+    return I.Problem(300, p.term_ptr, p.factor_var, p.coef, n % 7 - 12, n % 11)
+
+
 def hub_huio(r):
     """HUIO of 200 variables where variable 0 sits in about 150 terms and variable 1 in about 70
     (rows longer than the 64 records per update that the Metropolis / optimal-transition kernel
@@ -87,6 +93,11 @@ def cases():
     yield "er_w33", I.erdos_renyi_quio(700, 5.0, -16, 16, 10, 10, r), 25, 32
     yield "er_w64", I.erdos_renyi_quio(700, 5.0, -32, 31, 10, 10, r), 25, 32
     yield "er_w128", I.erdos_renyi_quio(600, 4.0, -64, 63, 7, 7, r), 20, 24
+    # the factored weights at the most places past the range their classes allow (98 of 104,
+    # 60 of 64), and beside the enumeration of quadratic variables in one launch (width 101)
+    yield "er_w98", I.erdos_renyi_quio(700, 6.0, -49, 48, 9, 9, r), 25, 32
+    yield "er_w60", I.erdos_renyi_quio(700, 6.0, -30, 29, 9, 9, r), 25, 32
+    yield "squares_w101", I.random_huio(700, 2100, [1, 2], -50, 50, 4, r), 25, 32
     squares = I.random_huio(800, 2400, [1, 2], -20, 20, 6, r)      # z_i^2 terms: enumeration
     yield "squares_w41", squares, 25, 32
     fixed = I.erdos_renyi_quio(400, 6.0, -8, 9, 8, 8, r)
@@ -96,9 +107,7 @@ def cases():
     yield "wide_coefs_64bit", I.random_huio(300, 900, [1, 2], -60, 60, 20000, r), 15, 16
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
     yield "hub_rows", hub_huio(r), 20, 16
-    yield "uneven_widths", I.Problem(300, *[getattr(I.erdos_renyi_quio(300, 5.0, -4, 4, 6, 6, r), f)
-                                            for f in ("term_ptr", "factor_var", "coef")],
-                                     np.arange(300, dtype=np.int32) % 7 - 12, np.arange(300, dtype=np.int32) % 11)
+    yield "uneven_widths", uneven(I.erdos_renyi_quio(300, 5.0, -4, 4, 6, 6, r))
 
 
 @pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
@@ -126,9 +135,7 @@ def mo_cases():
     yield "fixed_vars", fixed, 20, 16
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
     yield "hub_rows", hub_huio(r), 20, 16
-    yield "uneven_widths", I.Problem(300, *[getattr(I.random_huio(300, 1200, [1, 2, 3], -4, 4, 5, r), f)
-                                            for f in ("term_ptr", "factor_var", "coef")],
-                                     np.arange(300, dtype=np.int32) % 7 - 12, np.arange(300, dtype=np.int32) % 11), 20, 16
+    yield "uneven_widths", uneven(I.random_huio(300, 1200, [1, 2, 3], -4, 4, 5, r)), 20, 16
 
 
 @pytest.mark.parametrize("case", list(mo_cases()), ids=lambda c: c[0])
