@@ -246,15 +246,35 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
             w[i] = j < W32 ? wv : 0.0;
         }
     }
-    double carry = 0.0;
-    walk_step<0, kR>(w, ql, carry);
-    walk_step<1, kR>(w, ql, carry);
-    walk_step<2, kR>(w, ql, carry);
-    walk_step<3, kR>(w, ql, carry);
-    const double thr = U * carry;   // carry: the sum of all W weights, C at the last value
     uint32_t below = 0;
+    if constexpr (kFact) {
+        // Blocked sums (the factored weights already differ from the oracle's in the last bits):
+        // every lane forms the running sums of its own values at once, the quad adds the lanes'
+        // totals in value order, and a lane counts its values with run <= U S - (the sum of the
+        // earlier lanes' weights).
+        double run = 0.0;
 #pragma unroll
-    for (int i = 0; i < kR; ++i) below += w[i] <= thr ? 1u : 0u;
+        for (int i = 0; i < kR; ++i) {
+            run += w[i];
+            w[i] = run;
+        }
+        const double t0 = quad_bcast<0>(run), t1 = quad_bcast<1>(run), t2 = quad_bcast<2>(run);
+        const double c1 = t0, c2 = c1 + t1, c3 = c2 + t2;
+        const double total = c3 + quad_bcast<3>(run);
+        const double before = ql == 0 ? 0.0 : ql == 1 ? c1 : ql == 2 ? c2 : c3;
+        const double lim = U * total - before;
+#pragma unroll
+        for (int i = 0; i < kR; ++i) below += w[i] <= lim ? 1u : 0u;
+    } else {
+        double carry = 0.0;
+        walk_step<0, kR>(w, ql, carry);
+        walk_step<1, kR>(w, ql, carry);
+        walk_step<2, kR>(w, ql, carry);
+        walk_step<3, kR>(w, ql, carry);
+        const double thr = U * carry;   // carry: the sum of all W weights, C at the last value
+#pragma unroll
+        for (int i = 0; i < kR; ++i) below += w[i] <= thr ? 1u : 0u;
+    }
     below = quad_sum<uint32_t>(below) - skip;
     return lo + (int64_t)(below < W32 ? below : W32 - 1u);
 }
