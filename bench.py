@@ -23,9 +23,11 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-# FP64 flops per heat-bath weight w = exp(-beta * dE): one multiply, the exp evaluation and the
-# two additions of the blocked cumulative sum (running sum + block offset).  The exp evaluation
-# is counted as the FP64 operations the gfx950 exp sequence executes (FMA = 2 flops).
+# The heat bath's algorithmic FP64 work per weight w = exp(-beta * dE), as the method states it:
+# one multiply, one exponential evaluated directly (the FP64 operations of the gfx950 exp sequence,
+# FMA = 2 flops) and the additions of the cumulative sum.  The kernel's factored weights for
+# linear variables execute fewer (one exponential per group of 8 values); the counter record
+# gives the executed instructions, reported beside this figure.
 FP64_FLOPS_PER_WEIGHT = 30.0
 # VALU issue: a wave64 VALU instruction occupies one of the 4 SIMDs of a compute unit for 4 cycles
 VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4   # 10^9 wave instructions/s
@@ -95,8 +97,8 @@ def workload(args):
 
 # the sources that define the device program and the data it reads: kernels, their argument
 # layout, the instance packing and the launch choice (geometry and waves per replica)
-KERNEL_SOURCES = ("sa_device.h", "sa_quad.h", "sa_kernels_quad.hip", "sa_kernels_quad_mo.hip", "sa_kernels.hip", "sa_kernels_heat_bath.hip",
-                  "sa_kernels_heat_bath_closed.hip",
+KERNEL_SOURCES = ("sa_device.h", "sa_quad.h", "sa_quad_mo.h", "sa_kernels_quad.hip", "sa_kernels_quad_mo.hip",
+                  "sa_kernels.hip", "sa_kernels_heat_bath.hip", "sa_kernels_heat_bath_closed.hip",
                   "sa_kernels_metropolis.hip", "sa_kernels_otm.hip", "sa_kernels_batch.hip",
                   "sa_kernels_batch16.hip", "sa_kernel_table.h", "sa_internal.h", "sa_host.cpp",
                   "sa_api.cpp")
@@ -1035,7 +1037,9 @@ def main():
         flops = updates * W_mean * FP64_FLOPS_PER_WEIGHT
         achieved = flops / (ms / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic}
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "basis": "algorithmic: W weights x 30 FP64 flops per update (one direct exponential "
+                         "each); executed instructions in valu_issue"}
     else:
         # Metropolis / OTM: the incidence records come from the caches (measured HBM traffic is a
         # small fraction of them), and the counters show VALU issue as the busy resource: the
@@ -1075,6 +1079,7 @@ def main():
         vi = crec["valu_insts_per_update"] * value / 1e9
         out["valu_issue"] = {"achieved": vi, "peak": VALU_ISSUE_PEAK_G, "unit": "G wave-instructions/s",
                              "frac": vi / VALU_ISSUE_PEAK_G, "insts_per_update": crec["valu_insts_per_update"],
+                             "fp64_insts_per_update": crec.get("fp64_insts_per_update"),
                              "source": crec.get("profile")}
     if args.config == "cfg2" and not args.no_closed_form:
         # the paper's O(1) heat-bath draw on the same workload (its variables are all linear)

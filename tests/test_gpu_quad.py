@@ -96,6 +96,8 @@ def cases():
     # the factored weights at the most places past the range their classes allow (98 of 104,
     # 60 of 64), and beside the enumeration of quadratic variables in one launch (width 101)
     yield "er_w98", I.erdos_renyi_quio(700, 6.0, -49, 48, 9, 9, r), 25, 32
+    # mean degree 1: a few levels of over a thousand variables, several batches of rounds each
+    yield "er_w101_big_levels", I.erdos_renyi_quio(3000, 1.0, -50, 50, 9, 9, r), 20, 16
     yield "er_w60", I.erdos_renyi_quio(700, 6.0, -30, 29, 9, 9, r), 25, 32
     yield "squares_w101", I.random_huio(700, 2100, [1, 2], -50, 50, 4, r), 25, 32
     squares = I.random_huio(800, 2400, [1, 2], -20, 20, 6, r)      # z_i^2 terms: enumeration
