@@ -105,13 +105,17 @@ KERNEL_SOURCES = ("sa_device.h", "sa_quad.h", "sa_quad_mo.h", "sa_kernels_quad.h
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel sources: HBM traffic measured with counters applies only to the kernels
-    built from exactly these sources."""
+    """Hash of the kernel sources' code: HBM traffic measured with counters applies only to the
+    kernels built from exactly this code.  Line comments and blank space are left out (no source
+    holds "//" inside a string), so that editing a comment keeps the counter records."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(CSRC, name), "r", encoding="utf-8") as f:
+            code = re.sub(r"//[^\n]*", "", f.read())
+        code = "\n".join(line.strip() for line in code.splitlines() if line.strip())
+        h.update(name.encode() + b"\0" + code.encode())
     return h.hexdigest()[:16]
 
 

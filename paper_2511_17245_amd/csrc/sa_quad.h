@@ -15,7 +15,10 @@
 // range weigh zero); the cumulative weights C_v are formed in value order, one value at a time --
 // lane 0 adds its c weights, hands the running sum to lane 1, and so on -- so they are the exact
 // sums of the plain sequential definition; the drawn value is the first v with C_v > U * C_u,
-// i.e. the number of C_v <= U * C_u (C never decreases), summed over the quad.
+// i.e. the number of C_v <= U * C_u (C never decreases), summed over the quad.  The factored
+// variant (every variable of the launch has one width) forms a linear variable's weights as
+// products of two exponentials and adds them in lane blocks (quad_heat_bath): its sums differ
+// from the sequential ones in the last bits.
 #pragma once
 
 #include "sa_device.h"
