@@ -277,7 +277,10 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
         const bool mo = plan->rule == SA_METROPOLIS || plan->rule == SA_OPT_METROPOLIS;
         int32_t n_real = 0;
         const int32_t nl = mo ? build_rounds(plan->packed, slots, n_real)
-                              : build_levels(plan->packed, quad_waves(plan->rule) * 16, start, slots);
+                              : build_levels(plan->packed,
+                                             quad_waves(plan->rule, plan->packed.max_width, plan->packed.max_exp,
+                                                        quad_uniform_width(plan->packed)) * 16,
+                                             start, slots);
         if (!mo) n_real = (int32_t)slots.size();
         const size_t sb = align256(start.size() * sizeof(int32_t));
         const size_t bytes = sb + std::max<size_t>(slots.size(), 1) * sizeof(SchedRec);
@@ -314,10 +317,11 @@ bool quad_eligible(int rule, const Packed &pk, int device) {
     if (pk.dense || pk.max_exp > (heat_bath ? 2 : 4) || pk.max_width > 4 * kQuadMaxR) return false;
     int max_lds = 65536;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    return shared_state_bytes(pk.n, quad_waves(rule)) <= max_lds;
+    return shared_state_bytes(pk.n, quad_waves(rule, pk.max_width, pk.max_exp, quad_uniform_width(pk))) <= max_lds;
 }
 
-int choose_lanes(int rule, int requested, int waves_per_replica, bool eligible, int32_t n_levels, int32_t n_slots) {
+int choose_lanes(int32_t quads, int requested, int waves_per_replica, bool eligible, int32_t n_levels,
+                 int32_t n_slots) {
     if (requested != 0 && requested != 4 && requested != 64)
         return fail(SA_EINVAL, "lanes_per_update must be 0, 4 or 64"), -1;
     if (requested == 64) return 64;
@@ -331,7 +335,7 @@ int choose_lanes(int rule, int requested, int waves_per_replica, bool eligible, 
     }
     if (!eligible || waves_per_replica != 0 || n_levels <= 0) return 64;
     // the quad kernel when its levels fill, on average, half a workgroup's quads
-    return (int64_t)n_slots * 2 >= (int64_t)quad_waves(rule) * 16 * (int64_t)n_levels ? 4 : 64;
+    return (int64_t)n_slots * 2 >= (int64_t)quads * (int64_t)n_levels ? 4 : 64;
 }
 
 int reg_chunk_class(int32_t max_width) {
@@ -460,7 +464,9 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
             return rc;
         }
     }
-    const int lanes = sa::choose_lanes(plan->rule, opts.lanes_per_update, G, eligible, lv ? lv->n_levels : 0,
+    const int qwaves = sa::quad_waves(plan->rule, plan->packed.max_width, plan->packed.max_exp,
+                                      sa::quad_uniform_width(plan->packed));
+    const int lanes = sa::choose_lanes(qwaves * 16, opts.lanes_per_update, G, eligible, lv ? lv->n_levels : 0,
                                        lv ? lv->n_slots : 0);
     if (lanes < 0) {
         if (tmp) (void)hipFree(tmp);
@@ -497,7 +503,7 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
             return fail(rc, err);
         }
         plan->last = sa_launch_info{};
-        const int qw = sa::quad_waves(plan->rule);
+        const int qw = qwaves;
         plan->last.waves_per_group = qw;
         plan->last.groups = n_reads;
         plan->last.lds_bytes = (int32_t)sa::shared_state_bytes(n, qw);

@@ -596,6 +596,16 @@ int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level
     return n_levels;
 }
 
+int32_t quad_uniform_width(const Packed &p) {
+    int32_t w = 0;
+    for (const VarRec &vr : p.var) {
+        if (vr.width <= 1) continue;
+        if (w == 0) w = vr.width;
+        else if (vr.width != w) return 0;
+    }
+    return w;
+}
+
 int32_t build_rounds(const Packed &p, std::vector<SchedRec> &rounds, int32_t &n_real) {
     std::vector<int32_t> start;
     std::vector<SchedRec> slots;

@@ -201,13 +201,40 @@ struct QuadArgs {
     int64_t *e_out;
     uint64_t *trace;             // as AnnealArgs::trace
 };
-// Waves of the quad kernel's workgroup (one replica): heat bath, and Metropolis / optimal
-// transition (one wave: a HUIO level holds about 16 variables, and a single wave needs no
-// barrier between levels); values per lane it keeps in registers.
+// Waves of the quad kernel's workgroup (one replica): heat bath, 8 or 16 (below), and Metropolis /
+// optimal transition, one (a HUIO level holds about 16 variables, and a single wave needs no
+// barrier between levels); the most values per lane it keeps in registers.
 constexpr int kQuadWaves = 8;
+constexpr int kQuadWavesHigh = 16;
 constexpr int kQuadWavesMO = 1;
 constexpr int kQuadMaxR = 32;
-inline int quad_waves(int rule) { return rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS ? kQuadWavesMO : kQuadWaves; }
+// Values per lane of the quad heat bath: the smallest class of 8, 16, 26, 32 holding ceil(W / 4)
+// (W = 101 takes 26: 104 places).
+constexpr int32_t quad_r_class(int32_t max_width) {
+    const int32_t c = (max_width + 3) / 4;
+    return c <= 8 ? 8 : c <= 16 ? 16 : c <= 26 ? 26 : kQuadMaxR;
+}
+// The factored weights of linear variables (sa_quad.h): heat bath, one width W for every variable,
+// r >= 16 values per lane and at most r / 4 of the quad's 4 r places past the range.
+constexpr bool quad_factored(int rule, int32_t r, int32_t uniform_width) {
+    return rule == SA_HEAT_BATH && r >= 16 && uniform_width > 0 && 4 * r - uniform_width >= 0 &&
+           4 * r - uniform_width <= r / 4;
+}
+// The heat-bath variants that hold at most 128 VGPRs, so that a workgroup of 16 waves (four per
+// SIMD, rounds of 256 updates) fits without spilling: they run 16 waves, the others 8.
+constexpr bool quad_high(int rule, int32_t r, int32_t max_exp, bool fact) {
+    return rule == SA_HEAT_BATH_CLOSED ? (max_exp <= 1 || r == 8)
+                                       : (r == 8 || (fact && (max_exp <= 1 ? r <= 26 : r == 16)));
+}
+// Waves per replica of the quad kernel for a problem whose widest range is max_width, whose
+// exponents are at most max_exp and whose variables all have width uniform_width (0: not one width).
+constexpr int quad_waves(int rule, int32_t max_width, int32_t max_exp, int32_t uniform_width) {
+    if (rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS) return kQuadWavesMO;
+    const int32_t r = quad_r_class(max_width);
+    return quad_high(rule, r, max_exp, quad_factored(rule, r, uniform_width)) ? kQuadWavesHigh : kQuadWaves;
+}
+// The common width of the variables that are not fixed, or 0 when they differ (or there are none).
+int32_t quad_uniform_width(const Packed &p);
 // Launches the quad kernel for rule (SA_HEAT_BATH or SA_HEAT_BATH_CLOSED), a problem whose widest
 // range is max_width <= 4 * kQuadMaxR and whose exponents are <= max_exp <= 2 (defined in
 // sa_kernels_quad.hip).

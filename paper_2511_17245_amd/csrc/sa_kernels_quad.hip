@@ -6,24 +6,23 @@ namespace {
 
 using QuadFn = void (*)(QuadArgs);
 
-// values per lane: the smallest class holding ceil(W / 4) (W = 101 takes 26: 104 slots)
-constexpr uint32_t kClasses[] = {8, 16, 26, (uint32_t)kQuadMaxR};
-uint32_t r_class(uint32_t c) {
-    for (uint32_t r : kClasses)
-        if (c <= r) return r;
-    return (uint32_t)kQuadMaxR;
+// the variant of class R: 16 waves where quad_high allows them, else 8
+template <int kRule, int R, int kMaxE, typename Acc, bool kFact>
+QuadFn variant() {
+    constexpr int kW = quad_high(kRule, R, kMaxE, kFact) ? kQuadWavesHigh : kQuadWaves;
+    return quad_kernel<kRule, R, kMaxE, Acc, kW, kFact>;
 }
 
 template <int kRule, int kMaxE, typename Acc, bool kFact>
-QuadFn pick_r(uint32_t r) {
-    if (r == 8) return quad_kernel<kRule, 8, kMaxE, Acc, kQuadWaves>;   // no factored form below 16
-    if (r == 16) return quad_kernel<kRule, 16, kMaxE, Acc, kQuadWaves, kFact>;
-    if (r == 26) return quad_kernel<kRule, 26, kMaxE, Acc, kQuadWaves, kFact>;
-    return quad_kernel<kRule, kQuadMaxR, kMaxE, Acc, kQuadWaves, kFact>;
+QuadFn pick_r(int32_t r) {
+    if (r == 8) return variant<kRule, 8, kMaxE, Acc, false>();   // no factored form below 16
+    if (r == 16) return variant<kRule, 16, kMaxE, Acc, kFact>();
+    if (r == 26) return variant<kRule, 26, kMaxE, Acc, kFact>();
+    return variant<kRule, kQuadMaxR, kMaxE, Acc, kFact>();
 }
 
 template <int kRule, bool kFact>
-QuadFn pick(uint32_t r, int32_t max_exp, bool narrow) {
+QuadFn pick(int32_t r, int32_t max_exp, bool narrow) {
     if (max_exp <= 1) return narrow ? pick_r<kRule, 1, uint32_t, kFact>(r) : pick_r<kRule, 1, uint64_t, kFact>(r);
     return narrow ? pick_r<kRule, 2, uint32_t, kFact>(r) : pick_r<kRule, 2, uint64_t, kFact>(r);
 }
@@ -37,15 +36,15 @@ int launch_quad(int rule, const QuadArgs &a, int32_t max_width, int32_t max_exp,
         err = "quad kernel: unsupported problem shape";
         return SA_EUNSUPPORTED;
     }
-    const uint32_t r = r_class(c);
-    // the factored weights of linear variables: one width for every variable, at most r / 4 of the
-    // quad's 4 r places past the range (the closed form draws linear variables without weights)
-    const bool fact = rule == SA_HEAT_BATH && r >= 16 && a.uniform_width > 0 &&
-                      4u * r - (uint32_t)a.uniform_width <= r / 4u;
+    const int32_t r = quad_r_class(max_width);
+    // the factored weights of linear variables (the closed form draws them without weights); the
+    // waves per replica follow from the same choice (quad_waves), as the levels were built for
+    const bool fact = quad_factored(rule, r, a.uniform_width);
+    const int waves = quad_waves(rule, max_width, max_exp, a.uniform_width);
     QuadFn fn = rule == SA_HEAT_BATH_CLOSED ? pick<SA_HEAT_BATH_CLOSED, false>(r, max_exp, narrow)
                 : fact                      ? pick<SA_HEAT_BATH, true>(r, max_exp, narrow)
                                             : pick<SA_HEAT_BATH, false>(r, max_exp, narrow);
-    const int lds = (int)shared_state_bytes(a.P.n, kQuadWaves);
+    const int lds = (int)shared_state_bytes(a.P.n, waves);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) {
@@ -53,7 +52,7 @@ int launch_quad(int rule, const QuadArgs &a, int32_t max_width, int32_t max_exp,
             return SA_EDEVICE;
         }
     }
-    hipLaunchKernelGGL(fn, dim3((unsigned)a.n_reads), dim3(kQuadWaves * kWave), (size_t)lds, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)a.n_reads), dim3(waves * kWave), (size_t)lds, (hipStream_t)stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         err = std::string("kernel launch: ") + hipGetErrorString(e);

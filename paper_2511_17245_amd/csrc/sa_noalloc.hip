@@ -97,15 +97,15 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     const bool eligible = sa::quad_eligible(rule, pk, device);
     // the levels (heat bath) or the rounds (Metropolis, optimal transition) of the quad kernel
     const bool mo = rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS;
+    const int qwaves = sa::quad_waves(rule, pk.max_width, pk.max_exp, sa::quad_uniform_width(pk));
     std::vector<int32_t> lv_start;
     std::vector<sa::SchedRec> lv_slots;
     int32_t n_levels = 0, n_real = 0;
     if (eligible && G == 0 && opts.lanes_per_update != 64) {
-        n_levels = mo ? sa::build_rounds(pk, lv_slots, n_real) : sa::build_levels(pk, sa::quad_waves(rule) * 16,
-                                                                                     lv_start, lv_slots);
+        n_levels = mo ? sa::build_rounds(pk, lv_slots, n_real) : sa::build_levels(pk, qwaves * 16, lv_start, lv_slots);
         if (!mo) n_real = (int32_t)lv_slots.size();
     }
-    const int lanes = sa::choose_lanes(rule, opts.lanes_per_update, G, eligible, n_levels, n_real);
+    const int lanes = sa::choose_lanes(qwaves * 16, opts.lanes_per_update, G, eligible, n_levels, n_real);
     if (lanes < 0) return SA_EINVAL;
 
     int32_t active = 0;

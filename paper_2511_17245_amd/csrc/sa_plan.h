@@ -97,11 +97,12 @@ int32_t uniform_width(const std::vector<SchedRec> &slots);
 // Whether the quad kernel can run `rule` on this packed problem with n replicas' state in LDS.
 bool quad_eligible(int rule, const Packed &pk, int device);
 // Lanes per update (64 or 4) for a run: `requested` (0 = automatic) checked against eligibility;
-// the automatic choice takes the quad kernel when its levels fill half of a workgroup's quads on
-// average (64 variables for the heat bath's 128 quads, 8 for the 16 quads of Metropolis and the
-// optimal transition).
+// the automatic choice takes the quad kernel when its levels fill half of a workgroup's `quads`
+// on average (64 or 128 variables for the heat bath's 128 or 256 quads, 8 for the 16 quads of
+// Metropolis and the optimal transition).
 // Returns -1 (with the error recorded) for a request the problem cannot take.
-int choose_lanes(int rule, int requested, int waves_per_replica, bool eligible, int32_t n_levels, int32_t n_slots);
+int choose_lanes(int32_t quads, int requested, int waves_per_replica, bool eligible, int32_t n_levels,
+                 int32_t n_slots);
 // SA_EUNSUPPORTED / SA_EINVAL (with the message recorded) when the GPU kernels cannot run `rule`
 // on a problem whose largest exponent is max_exp.
 int check_rule_support(int rule, int32_t max_exp);
