@@ -282,8 +282,13 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
                                                         quad_uniform_width(plan->packed)) * 16,
                                              start, slots);
         if (!mo) n_real = (int32_t)slots.size();
+        std::vector<MoRec> mrec;
+        std::vector<uint8_t> mcoef;
+        if (mo) build_mo_records(plan->packed, slots, plan->dp.coef32 != 0, mrec, mcoef);
         const size_t sb = align256(start.size() * sizeof(int32_t));
-        const size_t bytes = sb + std::max<size_t>(slots.size(), 1) * sizeof(SchedRec);
+        const size_t rb = sb + align256(std::max<size_t>(slots.size(), 1) * sizeof(SchedRec));
+        const size_t cb = rb + align256(mrec.size() * sizeof(MoRec));
+        const size_t bytes = cb + std::max<size_t>(mcoef.size(), 1);
         hipError_t e = hipMalloc(&lv.dev, bytes);
         if (e != hipSuccess) {
             lv.dev = nullptr;
@@ -292,10 +297,14 @@ int get_levels(sa_plan *plan, sa_plan::Levels **out) {
         std::vector<char> img(bytes, 0);
         std::memcpy(img.data(), start.data(), start.size() * sizeof(int32_t));
         if (!slots.empty()) std::memcpy(img.data() + sb, slots.data(), slots.size() * sizeof(SchedRec));
+        if (!mrec.empty()) std::memcpy(img.data() + rb, mrec.data(), mrec.size() * sizeof(MoRec));
+        if (!mcoef.empty()) std::memcpy(img.data() + cb, mcoef.data(), mcoef.size());
         e = hipMemcpy(lv.dev, img.data(), bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy(levels)");
         lv.start = (const int32_t *)lv.dev;
         lv.slots = (const SchedRec *)((char *)lv.dev + sb);
+        lv.mrec = mo ? (const MoRec *)((char *)lv.dev + rb) : nullptr;
+        lv.mcoef = mo ? (const void *)((char *)lv.dev + cb) : nullptr;
         lv.n_slots = n_real;
         lv.n_rounds = mo ? (int32_t)(slots.size() / kRoundQuads) : 0;
         lv.uniform_width = mo ? 0 : uniform_width(slots);
@@ -317,7 +326,9 @@ bool quad_eligible(int rule, const Packed &pk, int device) {
     if (pk.dense || pk.max_exp > (heat_bath ? 2 : 4) || pk.max_width > 4 * kQuadMaxR) return false;
     int max_lds = 65536;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
-    return shared_state_bytes(pk.n, quad_waves(rule, pk.max_width, pk.max_exp, quad_uniform_width(pk))) <= max_lds;
+    const bool mo = rule == SA_METROPOLIS || rule == SA_OPT_METROPOLIS;   // + the constant 1 after the state
+    return shared_state_bytes(pk.n + (mo ? 1 : 0), quad_waves(rule, pk.max_width, pk.max_exp, quad_uniform_width(pk))) <=
+           max_lds;
 }
 
 int choose_lanes(int32_t quads, int requested, int waves_per_replica, bool eligible, int32_t n_levels,
@@ -487,6 +498,8 @@ int plan_run(sa_plan *plan, const sa_schedule *sched, int32_t n_reads, uint64_t 
         q.slots = lv->slots;
         q.n_levels = lv->n_levels;
         q.n_rounds = lv->n_rounds;
+        q.mrec = lv->mrec;
+        q.mcoef = lv->mcoef;
         q.uniform_width = lv->uniform_width;
         q.otm_r = a.otm_r;
         q.z_init = zi_dev;

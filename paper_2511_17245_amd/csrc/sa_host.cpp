@@ -596,6 +596,45 @@ int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level
     return n_levels;
 }
 
+void build_mo_records(const Packed &p, std::vector<SchedRec> &rounds, bool coef32, std::vector<MoRec> &rec,
+                      std::vector<uint8_t> &coef) {
+    const size_t n_rounds = rounds.size() / (size_t)kRoundQuads;
+    const size_t per_round = (size_t)kMoAhead * (size_t)kRoundQuads * 4;   // records of a round (64 lanes)
+    const uint32_t one = (uint32_t)p.n * 4u;                                  // LDS offset of the constant 1
+    rec.assign(n_rounds * per_round, MoRec{0u, {one, one, one}});
+    const size_t cw = coef32 ? 4 : 8;
+    coef.assign(n_rounds * per_round * cw, 0);
+    for (size_t r = 0; r < n_rounds; ++r) {
+        for (int32_t q = 0; q < kRoundQuads; ++q) {
+            SchedRec &s = rounds[r * (size_t)kRoundQuads + (size_t)q];
+            s.pad[0] = 0;
+            if (s.k < 0) continue;
+            bool rest = s.deg > 4 * kMoAhead;
+            const int32_t m = std::min<int32_t>(s.deg, 4 * kMoAhead);
+            for (int32_t i = 0; i < m; ++i) {
+                const size_t idx = (r * (size_t)kMoAhead + (size_t)(i / 4)) * 64 + (size_t)(q * 4 + i % 4);
+                const IncRec &ir = p.inc[(size_t)s.row + (size_t)i];
+                const uint32_t no = ir.meta >> 8;
+                MoRec &mr = rec[idx];
+                mr.meta = ir.meta;
+                if (no > 3) {   // a long record: added from the incidence records, zero here
+                    rest = true;
+                    continue;
+                }
+                for (uint32_t f = 0; f < no; ++f) mr.zoff[f] = (uint32_t)ir.o[f] * 4u;
+                const int64_t c = p.inc_coef[(size_t)s.row + (size_t)i];
+                if (coef32) {
+                    const int32_t c32 = (int32_t)c;
+                    std::memcpy(coef.data() + idx * cw, &c32, sizeof(c32));
+                } else {
+                    std::memcpy(coef.data() + idx * cw, &c, sizeof(c));
+                }
+            }
+            s.pad[0] = rest ? 1 : 0;
+        }
+    }
+}
+
 int32_t quad_uniform_width(const Packed &p) {
     int32_t w = 0;
     for (const VarRec &vr : p.var) {

@@ -129,6 +129,22 @@ int32_t build_levels(const Packed &p, int32_t quads, std::vector<int32_t> &level
 constexpr int32_t kRoundQuads = 16;
 constexpr int32_t kRoundBatch = 4;
 int32_t build_rounds(const Packed &p, std::vector<SchedRec> &rounds, int32_t &n_real);
+// Records per lane that the Metropolis / OTM quad kernel reads for one round (a row of up to
+// 4 kMoAhead incidences; longer rows take the rest from the incidence records).
+constexpr int32_t kMoAhead = 16;
+// A round's record as that kernel reads it: meta as in IncRec, and the LDS byte offsets of the
+// other factors' values -- 4 n (the state's element n, which holds 1) for an unused place.
+struct MoRec {
+    uint32_t meta;
+    uint32_t zoff[3];
+};
+// Round-major copy of the rounds' records: record u of lane L (quad L / 4, its record 4 u + L % 4)
+// of round r at ((r kMoAhead + u) 64 + L), with zero coefficients past a row and for records with
+// more than three other factors (coefficients as int32 when coef32, else int64).  Marks in
+// pad[0] of a round's slot whether its row needs the rest read from the incidence records (more
+// than 4 kMoAhead records, or a long record).
+void build_mo_records(const Packed &p, std::vector<SchedRec> &rounds, bool coef32, std::vector<MoRec> &rec,
+                      std::vector<uint8_t> &coef);
 
 // Device view of a packed plan.
 struct DevProblem {
@@ -194,6 +210,8 @@ struct QuadArgs {
     const SchedRec *slots;       // level-major variables, or n_rounds rounds of kRoundQuads (device)
     int32_t n_levels;
     int32_t n_rounds;            // Metropolis / optimal transition: rounds per sweep (build_rounds)
+    const MoRec *mrec;           // Metropolis / optimal transition: the rounds' records (build_mo_records)
+    const void *mcoef;           // and their coefficients (int32 when P.coef32, else int64)
     int32_t uniform_width;       // the common width W of every slot, or 0 when widths differ
     double otm_r;                // < 0: r = s/(S-1); else a fixed r (optimal transition)
     const int32_t *z_init;

@@ -46,7 +46,12 @@ int launch_quad_mo(int rule, const QuadArgs &a, int32_t max_width, int32_t max_e
     QuadFn fn = !rec32                          ? pick<false, uint64_t>(rule, c, max_exp)
                 : narrow && max_exp <= 2        ? pick<true, uint32_t>(rule, c, max_exp)
                                                 : pick<true, uint64_t>(rule, c, max_exp);
-    const int lds = (int)shared_state_bytes(a.P.n, kQuadWavesMO);
+    if (a.n_rounds > 0 && (a.mrec == nullptr || a.mcoef == nullptr)) {
+        err = "quad kernel: the rounds' records are missing";
+        return SA_EINVAL;
+    }
+    // the state and, after it, the constant 1 that the records' unused places point at
+    const int lds = (int)shared_state_bytes(a.P.n + 1, kQuadWavesMO);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) {

@@ -107,6 +107,9 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     }
     const int lanes = sa::choose_lanes(qwaves * 16, opts.lanes_per_update, G, eligible, n_levels, n_real);
     if (lanes < 0) return SA_EINVAL;
+    std::vector<sa::MoRec> mrec;
+    std::vector<uint8_t> mcoef;
+    if (lanes == 4 && mo) sa::build_mo_records(pk, lv_slots, sa::coefs_fit_32(canon), mrec, mcoef);
 
     int32_t active = 0;
     for (const auto &vr : pk.var) active += vr.width > 1 ? 1 : 0;
@@ -129,9 +132,11 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
     const size_t off_beta = L.total;
     const size_t off_sched = off_beta + sa::align256(sizeof(double) * (size_t)S);
     const size_t off_slots = off_sched + sa::align256(lv_start.size() * sizeof(int32_t));
+    const size_t off_mrec = off_slots + sa::align256(std::max<size_t>(lv_slots.size(), 1) * sizeof(sa::SchedRec));
+    const size_t off_mcoef = off_mrec + sa::align256(mrec.size() * sizeof(sa::MoRec));
     const size_t total = lanes == 64
                              ? off_sched + sa::align256(std::max<size_t>(sch.size(), 1) * sizeof(sa::SchedRec))
-                             : off_slots + sa::align256(std::max<size_t>(lv_slots.size(), 1) * sizeof(sa::SchedRec));
+                             : off_mcoef + sa::align256(std::max<size_t>(mcoef.size(), 1));
     if (total > kScratchBytes)
         return sa::fail(SA_ENOMEM, "sa_anneal_noalloc: the problem needs " + std::to_string(total) +
                                        " bytes of staging; the static area holds " +
@@ -148,6 +153,8 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
             std::memcpy(image.data() + off_sched, lv_start.data(), lv_start.size() * sizeof(int32_t));
         if (!lv_slots.empty())
             std::memcpy(image.data() + off_slots, lv_slots.data(), lv_slots.size() * sizeof(sa::SchedRec));
+        if (!mrec.empty()) std::memcpy(image.data() + off_mrec, mrec.data(), mrec.size() * sizeof(sa::MoRec));
+        if (!mcoef.empty()) std::memcpy(image.data() + off_mcoef, mcoef.data(), mcoef.size());
     }
     hipStream_t stream = (hipStream_t)opts.hip_stream;
     e = hipMemcpyAsync(area, image.data(), total, hipMemcpyHostToDevice, stream);
@@ -195,6 +202,8 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
         q.slots = (const sa::SchedRec *)((char *)area + off_slots);
         q.n_levels = n_levels;
         q.n_rounds = mo ? (int32_t)(lv_slots.size() / sa::kRoundQuads) : 0;
+        q.mrec = mo ? (const sa::MoRec *)((char *)area + off_mrec) : nullptr;
+        q.mcoef = mo ? (const void *)((char *)area + off_mcoef) : nullptr;
         q.uniform_width = mo ? 0 : sa::uniform_width(lv_slots);
         q.otm_r = a.otm_r;
         q.z_init = a.z_init;

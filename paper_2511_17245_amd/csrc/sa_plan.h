@@ -60,6 +60,8 @@ struct sa_plan {
         int32_t n_levels = -1;        // -1: not built
         int32_t n_slots = 0;          // variables placed (idle slots of the rounds not counted)
         int32_t n_rounds = 0;         // Metropolis / optimal transition: rounds of kRoundQuads slots
+        const sa::MoRec *mrec = nullptr;   // and their records' round-major copy (build_mo_records)
+        const void *mcoef = nullptr;
         int32_t uniform_width = 0;    // common width of every slot, 0 when they differ
     };
     Levels levels;

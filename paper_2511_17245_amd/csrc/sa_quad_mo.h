@@ -7,10 +7,14 @@
 // prescribe, so every variable reads its neighbours as the sequential index-order sweep does.
 // One wavefront per replica is all the parallelism a HUIO sweep of 2000 variables offers 1024
 // replicas, so there is one wave per SIMD and nothing else to hide memory latency behind: the
-// kernel does it itself.  Each round issues the loads of the next round's incidence records (16
-// per lane: rows of up to 64 records) before it works on its own, and every second round reloads
-// the schedule slots of the next batch of four rounds, so a round waits only on LDS.  The records
-// hold no state; only their other factors' values, read from LDS in the round that uses them, do.
+// kernel does it itself.  Each round issues the loads of the next round's records (16 per lane:
+// rows of up to 64 records) before it works on its own, and every second round reloads the
+// schedule slots of the next batch of four rounds, so a round waits only on LDS.  The records
+// come from a round-major copy (build_mo_records) whose places are addressed by the round index
+// alone and hold the other factors as LDS byte offsets, an unused one pointing at the constant 1
+// kept after the state: a record's product is three multiplies, with no index arithmetic or
+// selects.  The records hold no state; only their other factors' values, read from LDS in the
+// round that uses them, do.
 //
 // Random words: lane q of a quad draws Philox for round q of the batch (the counter of the
 // variable of that round); the quad reads them from lane q in round q.  x0 chooses the branch of
@@ -24,86 +28,69 @@
 namespace sa {
 namespace {
 
-// records per lane loaded one round ahead (a row of up to 4 kMoAhead incidences)
-constexpr int kMoAhead = 16;
 // s_waitcnt operand (gfx9 encoding): vmcnt 0, expcnt and lgkmcnt at their maxima (no wait)
 constexpr int kWaitVmcnt0 = 0x0F70;
 
-// One round's incidence records for this lane: records ql, ql + 4, ... of its quad's row (the
-// zero record past the row).  kNarrow: every coefficient fits 32 bits, and only the low word is
-// loaded.
+// One round's records for this lane (the round-major copy of build_mo_records): record u holds the
+// quad's incidence 4 u + ql, or a zero record past the row.  kNarrow: every coefficient fits 32
+// bits and the copy holds them as int32.
 template <bool kNarrow>
 struct RoundRecs {
-    IncRec r[kMoAhead];
+    uint4 r[kMoAhead];   // meta, then the LDS byte offsets of the three other factors
     std::conditional_t<kNarrow, uint32_t, uint64_t> c[kMoAhead];
 };
 
-// Every load of the round is issued, past the row too, so that the count of loads in flight is
-// the same in every round (the waits the compiler places for the current round then leave the
-// next round's loads in flight).
+// A round's records sit at one offset from the copy's base per lane (record u a further u * 64
+// records on), so the loads take no per-record arithmetic; every load is issued, so that the count
+// of loads in flight is the same in every round (the waits the compiler places for the current
+// round then leave the next round's loads in flight).
 template <bool kNarrow>
-__device__ __forceinline__ void load_round(const DevProblem &P, int32_t row, int32_t deg, int ql,
-                                           RoundRecs<kNarrow> &R) {
-    // 32-bit byte offsets from the arrays' (uniform) bases: the instance is far below 4 GiB
-    const char *inc = (const char *)P.inc;
-    const char *coef = (const char *)P.inc_coef;
+__device__ __forceinline__ void load_round(const QuadArgs &A, int32_t r, int lane, RoundRecs<kNarrow> &R) {
+    using Coef = std::conditional_t<kNarrow, uint32_t, uint64_t>;
+    const size_t base = (size_t)r * kMoAhead * 64 + (size_t)lane;
+    const uint4 *rec = (const uint4 *)A.mrec + base;
+    const Coef *coef = (const Coef *)A.mcoef + base;
 #pragma unroll
     for (int u = 0; u < kMoAhead; ++u) {
-        const int32_t i = 4 * u + ql;
-        const uint32_t idx = (uint32_t)(i < deg ? row + i : P.inc_pad);
-        R.r[u] = *(const IncRec *)(inc + idx * 16u);
-        if constexpr (kNarrow)
-            R.c[u] = *(const uint32_t *)(coef + idx * 8u);   // low word (little-endian)
-        else
-            R.c[u] = *(const uint64_t *)(coef + idx * 8u);
+        R.r[u] = rec[u * 64];
+        R.c[u] = coef[u * 64];
     }
 }
 
-// The LDS reads of group g (records 4g .. 4g + 3) of this lane: the other factors' values.
+// The LDS reads of group g (records 4g .. 4g + 3) of this lane: the other factors' values, 1 for
+// an unused place (the state's element n).
 template <bool kNarrow>
 __device__ __forceinline__ void read_group(const int32_t *z, const RoundRecs<kNarrow> &R, int g,
                                            int32_t (&zv)[4][3]) {
+    const char *zb = (const char *)z;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const IncRec &r = R.r[4 * g + u];
-        // unused inline slots hold index 0; a long record reads z_0 (masked: no branch)
-        const int32_t inl = -(int32_t)((r.meta >> 8) <= 3u);
-        zv[u][0] = z[r.o[0] & inl];
-        zv[u][1] = z[r.o[1] & inl];
-        zv[u][2] = z[r.o[2] & inl];
+        const uint4 &r = R.r[4 * g + u];
+        zv[u][0] = *(const int32_t *)(zb + r.y);
+        zv[u][1] = *(const int32_t *)(zb + r.z);
+        zv[u][2] = *(const int32_t *)(zb + r.w);
     }
 }
 
 // a[m] += the products J_t prod(other factors) of group g's records whose exponent of z_k is m
-// (Sec. 3.2: a_k^(m)), for the records with at most three other factors, which are inline; a
-// record with more sets `longs` and is added by the caller.  When no record of the group, in any
-// lane, holds z_k to a power above one, every product goes to a_k^(1) (the zero record adds 0).
+// (Sec. 3.2: a_k^(m)); long records are zero in the copy and added by the caller.  `linear`: no
+// quad of the wave has a term with z_k to a power above one, and every product goes to a_k^(1)
+// (a zero record adds 0).
 template <int kMaxE, typename Part, bool kNarrow>
 __device__ __forceinline__ void add_group(const RoundRecs<kNarrow> &R, int g, const int32_t (&zv)[4][3],
-                                          Part (&a)[kMaxE + 1], bool &longs) {
-    Part p[4];
-    bool high = false;
+                                          Part (&a)[kMaxE + 1], bool linear) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const IncRec &r = R.r[4 * g + u];
-        const uint32_t no = r.meta >> 8;
-        Part q = (Part)R.c[4 * g + u];
-        q *= no > 0 ? (Part)(int64_t)zv[u][0] : (Part)1;
-        q *= no > 1 ? (Part)(int64_t)zv[u][1] : (Part)1;
-        q *= no > 2 ? (Part)(int64_t)zv[u][2] : (Part)1;
-        longs |= no > 3;
-        p[u] = no <= 3 ? q : (Part)0;
-        high |= (r.meta & 0xFFu) > 1u;
-    }
-    if (kMaxE == 1 || __ballot(high) == 0) {
+        Part p = (Part)R.c[4 * g + u];
+        p *= (Part)(int64_t)zv[u][0];
+        p *= (Part)(int64_t)zv[u][1];
+        p *= (Part)(int64_t)zv[u][2];
+        if (kMaxE == 1 || linear) {
+            a[1] += p;
+        } else {
+            const uint32_t e = R.r[4 * g + u].x & 0xFFu;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[1] += p[u];
-    } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t e = R.r[4 * g + u].meta & 0xFFu;
-#pragma unroll
-            for (int m = 1; m <= kMaxE; ++m) a[m] += e == (uint32_t)m ? p[u] : (Part)0;
+            for (int m = 1; m <= kMaxE; ++m) a[m] += e == (uint32_t)m ? p : (Part)0;
         }
     }
 }
@@ -112,7 +99,7 @@ __device__ __forceinline__ void add_group(const RoundRecs<kNarrow> &R, int g, co
 // of the next group go out before the current group's products.
 template <int kMaxE, typename Part, bool kNarrow>
 __device__ __forceinline__ void add_records(const int32_t *z, const RoundRecs<kNarrow> &R, int32_t deg,
-                                            Part (&a)[kMaxE + 1], bool &longs) {
+                                            Part (&a)[kMaxE + 1], bool linear) {
     constexpr int kGroups = kMoAhead / 4;
     int32_t zA[4][3], zB[4][3];
     read_group<kNarrow>(z, R, 0, zA);
@@ -120,7 +107,7 @@ __device__ __forceinline__ void add_records(const int32_t *z, const RoundRecs<kN
     for (int g = 0; g < kGroups; ++g) {
         const bool more = g + 1 < kGroups && __ballot(deg > 16 * (g + 1)) != 0;   // uniform
         if (more) read_group<kNarrow>(z, R, g + 1, (g & 1) ? zA : zB);
-        add_group<kMaxE, Part, kNarrow>(R, g, (g & 1) ? zB : zA, a, longs);
+        add_group<kMaxE, Part, kNarrow>(R, g, (g & 1) ? zB : zA, a, linear);
         if (!more) break;
     }
 }
@@ -143,6 +130,7 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
 
     init_state(P, z, A.z_init ? A.z_init + (size_t)read * n : nullptr, (uint32_t)read, A.instance_id, A.key0,
                A.key1, lane, kWave);
+    if (lane == 0) z[n] = 1;   // the value of an unused factor place in the records' copy
     window_barrier();
     int64_t E = energy_part(P, z, lane, kWave);
     uint64_t *trace = A.trace ? A.trace + (size_t)read * (size_t)(A.s_end - A.s_begin) : nullptr;
@@ -162,7 +150,7 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
         auto from = [&](int q, int32_t v) { return __builtin_amdgcn_ds_bpermute(((lane & ~3) | q) << 2, v); };
         SchedRec ms, msN = slot_at(0);
         RoundRecs<kNarrow> RA, RB;
-        load_round<kNarrow>(P, from(0, msN.row), from(0, msN.deg), ql, RA);
+        load_round<kNarrow>(A, 0, lane, RA);
         uint32_t y0 = 0, y1 = 0, y2 = 0, y3 = 0;
 
         for (int32_t s = A.s_begin; s < A.s_end; ++s) {
@@ -178,20 +166,21 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
                 const int32_t row = from(q, ms.row);
                 const int32_t deg = from(q, ms.deg);
                 const uint32_t emask = (uint32_t)from(q, (int32_t)ms.emask);
+                const int32_t rest = from(q, ms.pad[0]);   // the row continues past the copy
                 const uint32_t x0 = (uint32_t)from(q, (int32_t)y0), x1 = (uint32_t)from(q, (int32_t)y1);
                 const uint32_t x2 = (uint32_t)from(q, (int32_t)y2), x3 = (uint32_t)from(q, (int32_t)y3);
                 const bool valid = k >= 0;
                 const int64_t zk = z[valid ? k : 0];
 
+                const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
                 Part a[kMaxE + 1];
 #pragma unroll
                 for (int m = 0; m <= kMaxE; ++m) a[m] = 0;
-                bool longs = false;
-                add_records<kMaxE, Part, kNarrow>(z, cur, deg, a, longs);
-                if (__ballot(longs || deg > 4 * kMoAhead) != 0) {
-                    // records with more than three other factors, and rows longer than the loads
-                    // ahead cover: one by one from memory
-                    for (int32_t i = ql; i < deg; i += 4) {
+                add_records<kMaxE, Part, kNarrow>(z, cur, deg, a, __ballot(!linear) == 0);
+                if (__ballot(rest != 0) != 0) {
+                    // records with more than three other factors, and rows longer than the copy
+                    // covers: one by one from the incidence records
+                    for (int32_t i = ql; rest && i < deg; i += 4) {
                         const IncRec r = P.inc[row + i];
                         if (i >= 4 * kMoAhead || (r.meta >> 8) > 3u) {
                             int e;
@@ -211,7 +200,6 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
                     const Part sum = quad_sum<Part>(a[m]);
                     C.a[m] = kNarrow ? (Acc)(int64_t)(int32_t)(uint32_t)sum : (Acc)sum;
                 }
-                const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
                 const double U = (double)((((uint64_t)x2 << 32) | x3) >> 11) * 0x1p-53;
                 int64_t v, d;
                 if (kRule == SA_OPT_METROPOLIS && (double)x0 * 0x1p-32 < r_opt) {
@@ -248,14 +236,11 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
                 // in every pair of rounds so that no load depends on a branch
                 const int32_t nb = (t | 3) + 1;
                 msN = slot_at(nb < R ? nb : 0);
-                // round t: the records of round t + 1 (same batch) go out first
-                load_round<kNarrow>(P, from((t + 1) & 3, ms.row), from((t + 1) & 3, ms.deg), ql, RB);
+                // round t: the records of round t + 1 go out first
+                load_round<kNarrow>(A, t + 1, lane, RB);
                 round(t & 3, RA);
-                // round t + 1: the records of round t + 2, the next batch's first round after a batch
-                const int q2 = (t + 2) & 3;
-                const bool next = q2 == 0;
-                load_round<kNarrow>(P, from(q2, next ? msN.row : ms.row), from(q2, next ? msN.deg : ms.deg), ql,
-                                    RA);
+                // round t + 1: the records of round t + 2 (after the last round, the next sweep's first)
+                load_round<kNarrow>(A, t + 2 < R ? t + 2 : 0, lane, RA);
                 round((t + 1) & 3, RB);
             }
             if (trace) {

@@ -3,6 +3,7 @@
 // reach its edges, for a build with the address and undefined-behaviour sanitizers.  Prints "ok".
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <random>
 #include <string>
 #include <vector>
@@ -101,6 +102,56 @@ void schedules(const sa::Packed &pk) {
                 if (j < k && lvl[j] >= 0) expect(lvl[j] < lvl[k], "lower neighbour in an earlier level");
             }
         }
+    }
+    if (pk.dense) return;
+    // the rounds of the Metropolis / OTM quad kernel and their records' round-major copy: place
+    // (r, u, lane q * 4 + l) holds incidence 4 u + l of round r's quad q, its other factors as LDS
+    // byte offsets (4 n for an unused place), a zero coefficient for a long record or past the row
+    std::vector<sa::SchedRec> rounds;
+    int32_t n_real = 0;
+    sa::build_rounds(pk, rounds, n_real);
+    expect(rounds.size() % (size_t)(sa::kRoundQuads * sa::kRoundBatch) == 0, "whole batches of rounds");
+    for (bool c32 : {false, true}) {
+        std::vector<sa::MoRec> rec;
+        std::vector<uint8_t> coef;
+        sa::build_mo_records(pk, rounds, c32, rec, coef);
+        const size_t nr = rounds.size() / (size_t)sa::kRoundQuads, cw = c32 ? 4 : 8;
+        expect(rec.size() == nr * (size_t)sa::kMoAhead * 64 && coef.size() == rec.size() * cw, "copy size");
+        const uint32_t one = (uint32_t)pk.n * 4u;
+        for (size_t r = 0; r < nr; ++r)
+            for (int32_t q = 0; q < sa::kRoundQuads; ++q) {
+                const sa::SchedRec &s = rounds[r * (size_t)sa::kRoundQuads + (size_t)q];
+                bool rest = s.k >= 0 && s.deg > 4 * sa::kMoAhead;
+                for (int32_t i = 0; i < 4 * sa::kMoAhead; ++i) {
+                    const size_t idx = (r * (size_t)sa::kMoAhead + (size_t)(i / 4)) * 64 + (size_t)(q * 4 + i % 4);
+                    const sa::MoRec &m = rec[idx];
+                    int64_t c = 0;
+                    if (c32) {
+                        int32_t c4;
+                        std::memcpy(&c4, coef.data() + idx * cw, 4);
+                        c = c4;
+                    } else {
+                        std::memcpy(&c, coef.data() + idx * cw, 8);
+                    }
+                    if (s.k < 0 || i >= s.deg) {
+                        expect(c == 0 && m.zoff[0] == one && m.zoff[1] == one && m.zoff[2] == one, "zero place");
+                        continue;
+                    }
+                    const sa::IncRec &ir = pk.inc[(size_t)s.row + (size_t)i];
+                    const uint32_t no = ir.meta >> 8;
+                    expect(m.meta == ir.meta, "record meta");
+                    if (no > 3) {
+                        rest = true;
+                        expect(c == 0, "long record zero in the copy");
+                        continue;
+                    }
+                    const int64_t want = pk.inc_coef[(size_t)s.row + (size_t)i];
+                    expect(c32 ? (int32_t)c == (int32_t)want : c == want, "record coefficient");
+                    for (uint32_t f = 0; f < 3; ++f)
+                        expect(m.zoff[f] == (f < no ? (uint32_t)ir.o[f] * 4u : one), "factor offsets");
+                }
+                expect((s.pad[0] != 0) == rest, "rest flag");
+            }
     }
 }
 
