@@ -105,8 +105,18 @@ int run_noalloc(const sa_instance *inst, const sa_bounds *bounds, const sa_sched
         n_levels = mo ? sa::build_rounds(pk, lv_slots, n_real) : sa::build_levels(pk, qwaves * 16, lv_start, lv_slots);
         if (!mo) n_real = (int32_t)lv_slots.size();
     }
-    const int lanes = sa::choose_lanes(qwaves * 16, opts.lanes_per_update, G, eligible, n_levels, n_real);
+    int lanes = sa::choose_lanes(qwaves * 16, opts.lanes_per_update, G, eligible, n_levels, n_real);
     if (lanes < 0) return SA_EINVAL;
+    if (lanes == 4 && mo && opts.lanes_per_update == 0) {
+        // the rounds' record copy takes 64 kMoAhead records per round; when the image would not fit
+        // the static area, the automatic choice takes the windows instead (the same results)
+        const size_t cw = sa::coefs_fit_32(canon) ? 4 : 8;
+        const size_t need = sa::packed_layout(pk).total + sa::align256(sizeof(double) * (size_t)S) +
+                            sa::align256(lv_slots.size() * sizeof(sa::SchedRec)) +
+                            (lv_slots.size() / (size_t)sa::kRoundQuads) * (size_t)sa::kMoAhead * 64 *
+                                (sizeof(sa::MoRec) + cw) + 1024;
+        if (need > kScratchBytes) lanes = 64;
+    }
     std::vector<sa::MoRec> mrec;
     std::vector<uint8_t> mcoef;
     if (lanes == 4 && mo) sa::build_mo_records(pk, lv_slots, sa::coefs_fit_32(canon), mrec, mcoef);

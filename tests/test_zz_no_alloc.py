@@ -43,6 +43,26 @@ def test_no_alloc_equals_anneal_ex_on_two_calls():
         assert np.array_equal(ha, hb), label
 
 
+def test_no_alloc_takes_the_windows_when_the_round_records_do_not_fit():
+    # 40,000 variables: the Metropolis quad kernel's round-major record copy (about 20 KB per round
+    # of 16 updates) would take over 50 MB, beyond the 32 MiB area, while the instance fits: the
+    # automatic choice takes the windows, whose results are the quad kernel's (sa_anneal_ex)
+    prob = I.random_huio(40_000, 60_000, [2, 3], -4, 4, 3, np.random.Generator(np.random.PCG64(9)))
+    plan = sa.Plan(prob, sa.METROPOLIS)
+    import torch
+    z = torch.empty((2, prob.n_vars), dtype=torch.int32, device="cuda")
+    e = torch.empty(2, dtype=torch.int64, device="cuda")
+    plan.run_device(3, 2, 7, z, e, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert plan.last_launch()["lanes_per_update"] == 4 and plan.last_launch()["n_levels"] > 0
+    plan.close()
+    say("big HUIO", "no-alloc")
+    za, ea = run(prob, sa.METROPOLIS, 3, 2, 7, no_alloc=True)
+    say("big HUIO", "anneal_ex")
+    zb, eb = run(prob, sa.METROPOLIS, 3, 2, 7, no_alloc=False)
+    assert np.array_equal(za, zb) and np.array_equal(ea, eb)
+
+
 def test_no_alloc_rejects_host_outputs_and_oversize_problems():
     prob = I.cfg3_huio(n=200, m=2000).problem
     m = sa._Marshalled(prob)
