@@ -96,7 +96,7 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
     const uint32_t j0 = (uint32_t)ql * (uint32_t)kR;
     const bool linear = kMaxE == 1 || linear_in;
     double w[kR];
-    uint32_t skip = 0;   // places before the range that the count below includes
+    bool rev = false;    // the weights run in distance order from the top of the range down
     if (linear) {
         // dE(v) = a1 (v - z_k): its minimum is at an end of the range, and dE_v - dE_min is |a1|
         // times the distance of v from that end (an exact integer, converted to double with one
@@ -122,15 +122,18 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
         // counted as the full walk counts them.
         if (kR >= 16 && kMaxE == 1) {
             auto pass = [&](uint32_t d) { return beta * (slope_d * (double)d) < 746.0; };
-            const double t = 746.0 * __builtin_amdgcn_rcp(beta * slope_d);
-            uint32_t D = t < (double)W32 ? (uint32_t)__builtin_ceil(t) : W32;
-            D = D < 1u ? 1u : D;
-            if (D < W32 && pass(D)) ++D;
-            if (D < W32 && pass(D)) ++D;
-            if (D > 1u && !pass(D - 1u)) --D;
-            if (D > 1u && !pass(D - 1u)) --D;
-            if (__ballot(D > 4u * kCold) == 0) {
-                // the largest D over the active lanes, one bit at a time (D < 32)
+            // pass is monotone in d, so D > 4 kCold exactly when the range holds more than 4 kCold
+            // values and distance 4 kCold passes: D itself is needed only for the cold draw
+            const bool wide = W32 > 4u * kCold && pass(4u * kCold);
+            if (__ballot(wide) == 0) {
+                const double t = 746.0 * __builtin_amdgcn_rcp(beta * slope_d);
+                uint32_t D = t < (double)W32 ? (uint32_t)__builtin_ceil(t) : W32;
+                D = D < 1u ? 1u : D;
+                if (D < W32 && pass(D)) ++D;
+                if (D < W32 && pass(D)) ++D;
+                if (D > 1u && !pass(D - 1u)) --D;
+                if (D > 1u && !pass(D - 1u)) --D;
+                // the largest D over the active lanes, one bit at a time (D <= 4 kCold < 32)
                 uint32_t dmax = 0;
 #pragma unroll
                 for (int bit = 4; bit >= 0; --bit) {
@@ -172,49 +175,30 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
         // Factored weights (kFact: every variable of the launch has the same width W, kR >= 16 and
         // nd = 4 kR - W <= kR / 4).  The weight at distance d from the minimising end is e^(-c d),
         // c = beta |a1|, and d = D + t splits it into e^(-c D) e^(-c t): per lane, one exponential
-        // per group of 8 values (its base distance D) and the 8 shared e^(-c t), t = 0..7 (two per
-        // lane of the quad), then one product per value.  The nd places past the range are laid
-        // at the first nd places of lane 0 (minimum at the top: the lanes' windows end at the top
-        // of the range, lane q holding indices W - (4 - q) kR ..) or the last nd of lane 3
-        // (minimum at the bottom: lane q holds q kR ..), where they weigh 0; both layouts are in
-        // value order, so the walk below is the same.  A product rounds once more than the direct
-        // exponential of the oracle, and the two exponents are rounded apart: a draw can differ
-        // only where U C_u falls within a few ulp of a cumulative weight.
+        // per group of 8 places (its base distance D) and the 8 shared e^(-c t), t = 0..7 (two per
+        // lane of the quad), then one product per place.  The layout is by distance in both
+        // orientations: lane q holds distances q kR .. q kR + kR - 1, so the places past the range
+        // are the last nd of lane 3 (left out of the total below), and a minimum at the top makes
+        // the walk run from the top of the range down.  A product rounds once more than the direct
+        // exponential of the oracle, and the two exponents are rounded apart: a draw can differ only
+        // where U C_u falls within a few ulp of a cumulative weight.
         if constexpr (kFact) {
-            // the lane's smallest distance (both layouts)
-            const uint32_t a = from_top ? (3u - (uint32_t)ql) * (uint32_t)kR : (uint32_t)ql * (uint32_t)kR;
+            const uint32_t a = (uint32_t)ql * (uint32_t)kR;   // the lane's smallest distance
             auto wexp = [&](uint32_t d) { return exp_nonpos(-(beta * (slope_d * (double)d))); };
-            // e^(-c t), t = 0..7, in the order the lane's groups take them: t = s at the bottom,
-            // t = 7 - s at the top (a group's distances descend there)
             const double e0 = wexp(2u * (uint32_t)ql), e1 = wexp(2u * (uint32_t)ql + 1u);
             const double E[8] = {quad_bcast<0>(e0), quad_bcast<0>(e1), quad_bcast<1>(e0), quad_bcast<1>(e1),
                                  quad_bcast<2>(e0), quad_bcast<2>(e1), quad_bcast<3>(e0), quad_bcast<3>(e1)};
-            double Eo[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) Eo[t] = from_top ? E[7 - t] : E[t];
-            // group m (slots 8m .. 8m + 7) starts at distance a + 8m (bottom) or ends at a +
-            // kR - 1 - 8m (top); the kR mod 8 slots after the whole groups take Eo[8 - kR % 8 + r]
-            // with a base chosen to match
+            // group m (places 8m .. 8m + 7) starts at distance a + 8m; the kR mod 8 places after the
+            // whole groups take E[8 - kR % 8 + r] with a base chosen to match
             constexpr int kG = kR / 8, kRest = kR % 8;
             double F[kG + 1];
 #pragma unroll
-            for (int m = 0; m < kG; ++m)
-                F[m] = wexp(a + (from_top ? (uint32_t)(kR - 8 - 8 * m) : (uint32_t)(8 * m)));
-            if (kRest) F[kG] = wexp(a + (from_top ? 0u : (uint32_t)(8 * kG - 8 + kRest)));
-            // only a lane's first and last kR / 4 values can lie past the range
-            constexpr int kEdge = kR / 4;
-            const int32_t jlane = from_top ? (int32_t)W32 - (4 - ql) * kR : ql * kR;   // index of slot 0
+            for (int m = 0; m < kG; ++m) F[m] = wexp(a + (uint32_t)(8 * m));
+            if (kRest) F[kG] = wexp(a + (uint32_t)(8 * kG - 8 + kRest));
 #pragma unroll
-            for (int i = 0; i < kR; ++i) {
-                const double f = i < 8 * kG ? F[i / 8] * Eo[i % 8] : F[kG] * Eo[8 - kRest + (i - 8 * kG)];
-                if (i < kEdge || i >= kR - kEdge)
-                    w[i] = (uint32_t)(jlane + i) < W32 ? f : 0.0;
-                else
-                    w[i] = f;
-            }
-            const uint32_t nd = 4u * (uint32_t)kR - Wu;   // places past the range, the same for every quad
-            // the nd empty places before the range (minimum at the top) have C = 0 and are counted
-            skip = from_top ? nd : 0u;
+            for (int i = 0; i < kR; ++i)
+                w[i] = i < 8 * kG ? F[i / 8] * E[i % 8] : F[kG] * E[8 - kRest + (i - 8 * kG)];
+            rev = from_top;
         } else {
             // |a1| times the distance: one rounding of the exact product, as the oracle's conversion of
             // the integer difference (slope * (W - 1) is exact in double: W <= 128)
@@ -253,21 +237,37 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
     if constexpr (kFact) {
         // Blocked sums (the factored weights already differ from the oracle's in the last bits):
         // every lane forms the running sums of its own values at once, the quad adds the lanes'
-        // totals in value order, and a lane counts its values with run <= U S - (the sum of the
-        // earlier lanes' weights).
+        // totals in walk order, and a lane counts its places with run <= U S - (the sum of the
+        // earlier lanes' weights).  Lane 3's last nd places lie past the range (nd the same for
+        // every quad): its total is its running sum at the last place inside, and a place past the
+        // range is counted only where every place inside is.  In reverse (minimum at the top) the
+        // cumulative weight from the top R_d stands for C: v_j is drawn for the first d = W - 1 - j
+        // with R_d >= (1 - U) S, so j = W - 1 - #{d : R_d < (1 - U) S}, counted as run <= the
+        // next double below the limit.
         double run = 0.0;
 #pragma unroll
         for (int i = 0; i < kR; ++i) {
             run += w[i];
             w[i] = run;
         }
+        const uint32_t nd = 4u * (uint32_t)kR - Wu;
+        double last = run;
+#pragma unroll
+        for (int e = 1; e <= kR / 4; ++e) last = nd == (uint32_t)e ? w[kR - 1 - e] : last;
         const double t0 = quad_bcast<0>(run), t1 = quad_bcast<1>(run), t2 = quad_bcast<2>(run);
         const double c1 = t0, c2 = c1 + t1, c3 = c2 + t2;
-        const double total = c3 + quad_bcast<3>(run);
+        const double total = c3 + quad_bcast<3>(last);
         const double before = ql == 0 ? 0.0 : ql == 1 ? c1 : ql == 2 ? c2 : c3;
-        const double lim = U * total - before;
+        double lim = (rev ? 1.0 - U : U) * total - before;
+        if (rev) {
+            // the largest double below lim (finite): one step of its representation toward -inf
+            const int64_t b = (int64_t)__double_as_longlong(lim);
+            lim = __longlong_as_double(b > 0 ? b - 1 : b == 0 ? (long long)0x8000000000000001ull : b + 1);
+        }
 #pragma unroll
         for (int i = 0; i < kR; ++i) below += w[i] <= lim ? 1u : 0u;
+        below = quad_sum<uint32_t>(below);
+        if (rev) below = below < W32 ? W32 - 1u - below : 0u;
     } else {
         double carry = 0.0;
         walk_step<0, kR>(w, ql, carry);
@@ -277,8 +277,8 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
         const double thr = U * carry;   // carry: the sum of all W weights, C at the last value
 #pragma unroll
         for (int i = 0; i < kR; ++i) below += w[i] <= thr ? 1u : 0u;
+        below = quad_sum<uint32_t>(below);
     }
-    below = quad_sum<uint32_t>(below) - skip;
     return lo + (int64_t)(below < W32 ? below : W32 - 1u);
 }
 
