@@ -44,6 +44,11 @@ __device__ __forceinline__ double quad_bcast(double x) {
     return __longlong_as_double((long long)qperm64<kQ * 0x55>((uint64_t)__double_as_longlong(x)));
 }
 
+// every lane of a quad takes lane q's value (q a constant after unrolling)
+__device__ __forceinline__ double quad_bcast_n(double x, int q) {
+    return q == 0 ? quad_bcast<0>(x) : q == 1 ? quad_bcast<1>(x) : q == 2 ? quad_bcast<2>(x) : quad_bcast<3>(x);
+}
+
 template <typename Acc>
 __device__ __forceinline__ Acc quad_sum(Acc x) {
     if (sizeof(Acc) == 4) {
@@ -97,6 +102,7 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
     const bool linear = kMaxE == 1 || linear_in;
     double w[kR];
     bool rev = false;    // the weights run in distance order from the top of the range down
+    bool summed = false; // w already holds the lane's running sums
     if (linear) {
         // dE(v) = a1 (v - z_k): its minimum is at an end of the range, and dE_v - dE_min is |a1|
         // times the distance of v from that end (an exact integer, converted to double with one
@@ -174,31 +180,42 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
         }
         // Factored weights (kFact: every variable of the launch has the same width W, kR >= 16 and
         // nd = 4 kR - W <= kR / 4).  The weight at distance d from the minimising end is e^(-c d),
-        // c = beta |a1|, and d = D + t splits it into e^(-c D) e^(-c t): per lane, one exponential
-        // per group of 8 places (its base distance D) and the 8 shared e^(-c t), t = 0..7 (two per
-        // lane of the quad), then one product per place.  The layout is by distance in both
-        // orientations: lane q holds distances q kR .. q kR + kR - 1, so the places past the range
-        // are the last nd of lane 3 (left out of the total below), and a minimum at the top makes
-        // the walk run from the top of the range down.  A product rounds once more than the direct
-        // exponential of the oracle, and the two exponents are rounded apart: a draw can differ only
-        // where U C_u falls within a few ulp of a cumulative weight.
+        // c = beta |a1|.  The layout is by distance in both orientations: lane q holds distances
+        // q kR .. q kR + kR - 1 (the places past the range are the last nd of lane 3, left out of
+        // the total below), and a minimum at the top makes the walk run from the top of the range
+        // down.  Place i = 8m + t of lane q is at distance q kR + 8m + t, and its weight is the
+        // product G_q H_m E_t of e^(-c q kR) (the lane's own), e^(-c 8m) and e^(-c t) (shared by
+        // the quad, each evaluated by one of its lanes): four exponentials per lane for kR values.
+        // The products are accumulated with fused multiply-adds into the running sums.  The
+        // weights are rounded apart from the oracle's direct exponentials (three factors), so a
+        // draw can differ only where U C_u falls within a few ulp of a cumulative weight.
         if constexpr (kFact) {
-            const uint32_t a = (uint32_t)ql * (uint32_t)kR;   // the lane's smallest distance
+            constexpr int kG = kR / 8, kRest = kR % 8;
+            // the shared group bases: 8m for m = 1 .. kG - 1, then the base of the kR mod 8 places
+            // after the whole groups, which take E_t for t = 8 - kR % 8 + r
+            constexpr int kH = kG - 1 + (kRest ? 1 : 0);
+            static_assert(kH <= 4, "one shared group base per lane of the quad");
+            const uint32_t hd = ql < kG - 1 ? 8u * (uint32_t)(ql + 1)
+                                            : (kRest && ql == kG - 1) ? (uint32_t)(8 * kG - 8 + kRest) : 0u;
             auto wexp = [&](uint32_t d) { return exp_nonpos(-(beta * (slope_d * (double)d))); };
             const double e0 = wexp(2u * (uint32_t)ql), e1 = wexp(2u * (uint32_t)ql + 1u);
+            const double G = wexp((uint32_t)ql * (uint32_t)kR);
+            const double h = wexp(hd);
             const double E[8] = {quad_bcast<0>(e0), quad_bcast<0>(e1), quad_bcast<1>(e0), quad_bcast<1>(e1),
                                  quad_bcast<2>(e0), quad_bcast<2>(e1), quad_bcast<3>(e0), quad_bcast<3>(e1)};
-            // group m (places 8m .. 8m + 7) starts at distance a + 8m; the kR mod 8 places after the
-            // whole groups take E[8 - kR % 8 + r] with a base chosen to match
-            constexpr int kG = kR / 8, kRest = kR % 8;
             double F[kG + 1];
+            F[0] = G;
 #pragma unroll
-            for (int m = 0; m < kG; ++m) F[m] = wexp(a + (uint32_t)(8 * m));
-            if (kRest) F[kG] = wexp(a + (uint32_t)(8 * kG - 8 + kRest));
+            for (int m = 1; m < kG; ++m) F[m] = G * quad_bcast_n(h, m - 1);
+            if (kRest) F[kG] = G * quad_bcast_n(h, kG - 1);
+            double run = 0.0;
 #pragma unroll
-            for (int i = 0; i < kR; ++i)
-                w[i] = i < 8 * kG ? F[i / 8] * E[i % 8] : F[kG] * E[8 - kRest + (i - 8 * kG)];
+            for (int i = 0; i < kR; ++i) {
+                run = i < 8 * kG ? fma(F[i / 8], E[i % 8], run) : fma(F[kG], E[8 - kRest + (i - 8 * kG)], run);
+                w[i] = run;
+            }
             rev = from_top;
+            summed = true;
         } else {
             // |a1| times the distance: one rounding of the exact product, as the oracle's conversion of
             // the integer difference (slope * (W - 1) is exact in double: W <= 128)
@@ -244,12 +261,15 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
         // cumulative weight from the top R_d stands for C: v_j is drawn for the first d = W - 1 - j
         // with R_d >= (1 - U) S, so j = W - 1 - #{d : R_d < (1 - U) S}, counted as run <= the
         // next double below the limit.
-        double run = 0.0;
+        if (!summed) {
+            double run = 0.0;
 #pragma unroll
-        for (int i = 0; i < kR; ++i) {
-            run += w[i];
-            w[i] = run;
+            for (int i = 0; i < kR; ++i) {
+                run += w[i];
+                w[i] = run;
+            }
         }
+        const double run = w[kR - 1];
         const uint32_t nd = 4u * (uint32_t)kR - Wu;
         double last = run;
 #pragma unroll
