@@ -44,11 +44,6 @@ __device__ __forceinline__ double quad_bcast(double x) {
     return __longlong_as_double((long long)qperm64<kQ * 0x55>((uint64_t)__double_as_longlong(x)));
 }
 
-// every lane of a quad takes lane q's value (q a constant after unrolling)
-__device__ __forceinline__ double quad_bcast_n(double x, int q) {
-    return q == 0 ? quad_bcast<0>(x) : q == 1 ? quad_bcast<1>(x) : q == 2 ? quad_bcast<2>(x) : quad_bcast<3>(x);
-}
-
 template <typename Acc>
 __device__ __forceinline__ Acc quad_sum(Acc x) {
     if (sizeof(Acc) == 4) {
@@ -184,30 +179,38 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
         // q kR .. q kR + kR - 1 (the places past the range are the last nd of lane 3, left out of
         // the total below), and a minimum at the top makes the walk run from the top of the range
         // down.  Place i = 8m + t of lane q is at distance q kR + 8m + t, and its weight is the
-        // product G_q H_m E_t of e^(-c q kR) (the lane's own), e^(-c 8m) and e^(-c t) (shared by
-        // the quad, each evaluated by one of its lanes): four exponentials per lane for kR values.
-        // The products are accumulated with fused multiply-adds into the running sums.  The
-        // weights are rounded apart from the oracle's direct exponentials (three factors), so a
-        // draw can differ only where U C_u falls within a few ulp of a cumulative weight.
+        // product G_q H_m E_t of e^(-c q kR), e^(-8 c m) and e^(-c t): G_q is one exponential, and
+        // E_t and H_m are powers of another, e^(-c), formed by repeated products (at most 3 + kR / 8
+        // deep).  The products are accumulated with fused multiply-adds into the running sums.  The
+        // weights are rounded apart from the oracle's direct exponentials, by some ulp per product
+        // level, so a draw can differ only where U C_u falls within some tens of ulp of a
+        // cumulative weight.
         if constexpr (kFact) {
             constexpr int kG = kR / 8, kRest = kR % 8;
-            // the shared group bases: 8m for m = 1 .. kG - 1, then the base of the kR mod 8 places
-            // after the whole groups, which take E_t for t = 8 - kR % 8 + r
-            constexpr int kH = kG - 1 + (kRest ? 1 : 0);
-            static_assert(kH <= 4, "one shared group base per lane of the quad");
-            const uint32_t hd = ql < kG - 1 ? 8u * (uint32_t)(ql + 1)
-                                            : (kRest && ql == kG - 1) ? (uint32_t)(8 * kG - 8 + kRest) : 0u;
             auto wexp = [&](uint32_t d) { return exp_nonpos(-(beta * (slope_d * (double)d))); };
-            const double e0 = wexp(2u * (uint32_t)ql), e1 = wexp(2u * (uint32_t)ql + 1u);
+            const double e1 = wexp(1u);
             const double G = wexp((uint32_t)ql * (uint32_t)kR);
-            const double h = wexp(hd);
-            const double E[8] = {quad_bcast<0>(e0), quad_bcast<0>(e1), quad_bcast<1>(e0), quad_bcast<1>(e1),
-                                 quad_bcast<2>(e0), quad_bcast<2>(e1), quad_bcast<3>(e0), quad_bcast<3>(e1)};
+            double E[8];
+            E[0] = 1.0;
+            E[1] = e1;
+            E[2] = e1 * e1;
+            E[3] = E[2] * e1;
+            E[4] = E[2] * E[2];
+            E[5] = E[4] * e1;
+            E[6] = E[4] * E[2];
+            E[7] = E[4] * E[3];
+            const double H8 = E[4] * E[4];
+            // group m (places 8m .. 8m + 7) takes F_m = G_q H_m; the kR mod 8 places after the whole
+            // groups start at distance 8 kG - 8 + kR mod 8 and take E_t for t = 8 - kR % 8 + r
             double F[kG + 1];
             F[0] = G;
+            double Hm = 1.0;
 #pragma unroll
-            for (int m = 1; m < kG; ++m) F[m] = G * quad_bcast_n(h, m - 1);
-            if (kRest) F[kG] = G * quad_bcast_n(h, kG - 1);
+            for (int m = 1; m < kG; ++m) {
+                Hm = m == 1 ? H8 : Hm * H8;
+                F[m] = G * Hm;
+            }
+            if (kRest) F[kG] = G * (Hm * E[kRest]);
             double run = 0.0;
 #pragma unroll
             for (int i = 0; i < kR; ++i) {
@@ -252,7 +255,7 @@ __device__ __forceinline__ int64_t quad_heat_bath(const Coeffs<kMaxE, Acc> &C, i
     }
     uint32_t below = 0;
     if constexpr (kFact) {
-        // Blocked sums (the factored weights already differ from the oracle's in the last bits):
+        // Blocked sums (the factored weights already differ from the oracle's by rounding):
         // every lane forms the running sums of its own values at once, the quad adds the lanes'
         // totals in walk order, and a lane counts its places with run <= U S - (the sum of the
         // earlier lanes' weights).  Lane 3's last nd places lie past the range (nd the same for
