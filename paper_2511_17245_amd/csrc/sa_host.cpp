@@ -441,6 +441,7 @@ int pack(const Canonical &c, Packed &p, std::string &err) {
                     p.pair.push_back(PairRec{p.inc[q].o[0], (int32_t)p.inc_coef[q]});
             }
             p.pair_deg[k] = (int32_t)p.pair.size() - p.pair_row[k];
+            while ((p.pair.size() - (size_t)p.pair_row[k]) % kPairBlock) p.pair.push_back(PairRec{0, 0});
             compact = h >= INT32_MIN && h <= INT32_MAX;
             p.pair_h[k] = (int32_t)h;
         }

@@ -65,6 +65,8 @@ struct PairRec {
     int32_t j;
     int32_t J;
 };
+// a variable's pair records are padded with zero records to a multiple of this many
+constexpr int32_t kPairBlock = 16;
 
 // Host-side packed image of a plan (uploaded as one device allocation).
 struct Packed {
@@ -91,7 +93,8 @@ struct Packed {
     std::vector<int64_t> h, d;
     int64_t n_pairs = 0;
     // compact form of a multilinear QUIO whose coefficients fit int32 (empty otherwise): per
-    // variable its pair records (row pair_row[k], pair_deg[k] of them) and its linear coefficient
+    // variable its pair records (row pair_row[k], pair_deg[k] of them, followed by zero records
+    // {0, 0} up to a multiple of kPairBlock) and its linear coefficient
     std::vector<PairRec> pair;
     std::vector<int32_t> pair_row, pair_deg, pair_h;
 };

@@ -328,18 +328,17 @@ __device__ __forceinline__ void quad_coeffs(const DevProblem &P, const int32_t *
 
 // a_k^(1) of variable k from its compact pair records (multilinear QUIO): h_k + sum_j J_kj z_j.
 // Lane q takes records q, q + 4, ...; sixteen records of the row are loaded before any is used,
-// so a typical row costs one round trip to memory and one to LDS.
+// so a typical row costs one round trip to memory and one to LDS.  Rows are padded with zero
+// records (J = 0, j = 0) to a multiple of sixteen, so every load lies inside the array.
 template <typename Acc>
 __device__ __forceinline__ Acc quad_a1_pairs(const DevProblem &P, const int32_t *z, int32_t row, int32_t deg,
                                              int32_t h, int ql) {
+    static_assert(kPairBlock == 16, "one pass loads sixteen records");
     Acc part = ql == 0 ? (Acc)(int64_t)h : (Acc)0;
     for (int32_t c0 = 0; c0 < deg; c0 += 16) {
         PairRec pr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int32_t i = c0 + 4 * u + ql;
-            pr[u] = i < deg ? P.pair[row + i] : PairRec{0, 0};   // J = 0 past the row
-        }
+        for (int u = 0; u < 4; ++u) pr[u] = P.pair[row + c0 + 4 * u + ql];
 #pragma unroll
         for (int u = 0; u < 4; ++u) part += (Acc)(int64_t)pr[u].J * (Acc)(int64_t)z[pr[u].j];
     }
