@@ -36,8 +36,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        const uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
-        const uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+        // both words of each product from one 32 x 32 -> 64-bit multiply
+        const uint64_t p0 = (uint64_t)m0 * c0, p1 = (uint64_t)m1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;

@@ -442,7 +442,11 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
             for (int32_t batch = b0; batch < b1; batch += 4 * kQuads) {
                 const SchedRec ms = slot_of(batch, b1);
                 uint32_t y0 = (uint32_t)ms.k, y1 = (uint32_t)s, y2 = (uint32_t)read, y3 = A.instance_id;
-                philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
+                // the round keys are formed again at each draw (scalar adds) rather than held in
+                // registers across the sweep
+                uint32_t k0 = A.key0, k1 = A.key1;
+                asm volatile("" : "+s"(k0), "+s"(k1));
+                philox4x32_10(y0, y1, y2, y3, k0, k1);
                 for (int q = 0; q < 4; ++q) {
                     const int32_t idx = batch + q * kQuads + qid;
                     if (batch + q * kQuads >= b1) break;   // uniform: the level has no round q here
