@@ -564,22 +564,21 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
     // Weights are taken relative to the minimum energy difference.  Linear dE(v) = a1 (v - z_k)
     // has it at an end of the range, and dE(v) - dE_min = |a1| times the distance of v from that
     // end, the same integer as the difference of the two energy differences.
-    int64_t dmin = 0;
+    int64_t dmin = 0, dlane = INT64_MAX;   // dlane: the smallest dE of this lane's values
     Acc slope = 0;
     bool from_top = false;
     if (linear) {
         from_top = to_i64<Acc>(C.a[1]) < 0;
         slope = from_top ? (Acc)0 - C.a[1] : C.a[1];
     } else {
-        dmin = INT64_MAX;
         for (uint32_t i = 0; i < c; ++i) {
             const uint32_t j = j0 + i;
             if (j < W32) {
                 const int64_t d = poly_delta(C, zk, lo + (int64_t)j);
-                dmin = d < dmin ? d : dmin;
+                dlane = d < dlane ? d : dlane;
             }
         }
-        dmin = wave_min_i64(dmin);
+        dmin = wave_min_i64(dlane);
     }
     // kRegChunk = 0 evaluates the weights in groups of kGroup independent exponentials (their
     // latencies overlap); they are still added one by one in value order
@@ -635,6 +634,65 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             lane_sum = i == 0 ? w[0] : lane_sum + w[i];
         }
     } else {
+        // Cold draws over wide ranges: a lane whose smallest x gives beta x >= 746 holds only
+        // weights of exactly 0 (its other values have larger x, and the rounded products beta x
+        // do not decrease), as R37 uses.  When the lanes holding a nonzero weight are contiguous
+        // and hold at most kColdPasses * 64 values, only those values are evaluated, one per lane
+        // and 64 at a time, with the same weights: the values outside add nothing to any
+        // cumulative sum, so the first value whose cumulative weight exceeds U * total is the same
+        // one up to the order of the additions (here the DPP scan of each pass, then the passes).
+        constexpr uint32_t kColdPasses = 4;
+        bool live = false;
+        if (j0 < W32) {
+            double xl;
+            if (linear) {
+                // the lane's value nearest the minimising end
+                const uint32_t jn = from_top ? (j0 + c - 1u < W32 ? j0 + c - 1u : W32 - 1u) : j0;
+                const Acc g = slope * (Acc)(from_top ? W32 - 1u - jn : jn);
+                xl = sizeof(Acc) == 4 ? (double)(uint32_t)g : (double)(int64_t)g;
+            } else {
+                xl = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)dlane - (uint32_t)dmin) : (double)(dlane - dmin);
+            }
+            live = !(beta * xl >= 746.0);   // a NaN product counts as live
+        }
+        const uint64_t lmask = __ballot(live);
+        if (lmask != 0) {
+            const int first = __ffsll((unsigned long long)lmask) - 1;
+            const uint64_t runs = lmask >> first;
+            const uint32_t nlive = (uint32_t)__popcll(lmask);
+            const uint32_t jA = (uint32_t)first * c;
+            const uint32_t jE = jA + nlive * c < W32 ? jA + nlive * c : W32;
+            if ((runs & (runs + 1)) == 0 && jE - jA <= kColdPasses * (uint32_t)kWave) {   // uniform
+                double incl[kColdPasses], ptot[kColdPasses];
+#pragma unroll
+                for (uint32_t p = 0; p < kColdPasses; ++p) {
+                    incl[p] = 0.0;
+                    ptot[p] = 0.0;
+                    if (jA + p * kWave < jE) {   // uniform
+                        const uint32_t j = jA + p * kWave + (uint32_t)lane;
+                        const double wv = weight(j < jE ? j : jE - 1u);
+                        incl[p] = wave_scan_rows(j < jE ? wv : 0.0, cy);
+                        ptot[p] = __longlong_as_double(
+                            (long long)lane_read64((uint64_t)__double_as_longlong(incl[p]), kWave - 1));
+                    }
+                }
+                double total = 0.0;
+#pragma unroll
+                for (uint32_t p = 0; p < kColdPasses; ++p) total += ptot[p];
+                const double thr = U * total;
+                double carry = 0.0;
+#pragma unroll
+                for (uint32_t p = 0; p < kColdPasses; ++p) {
+                    if (jA + p * kWave < jE) {
+                        const uint32_t j = jA + p * kWave + (uint32_t)lane;
+                        const uint64_t hm = __ballot(j < jE && carry + incl[p] > thr);
+                        if (hm) return lo + (int64_t)(jA + p * kWave) + (int64_t)(__ffsll((unsigned long long)hm) - 1);
+                        carry += ptot[p];
+                    }
+                }
+                return lo + W - 1;   // rounding left no value past the threshold
+            }
+        }
         for (uint32_t i = 0; i < c; i += kGroup) {
             double wv[kGroup];
 #pragma unroll

@@ -114,6 +114,9 @@ def small_cases():
     yield "hub_rows_over_256", I.from_terms(400, hub_terms, -6, 6), 40, 32, RULES
     # coefficients above 2^31 (|z| <= 2000, degree 4): the 64-bit kernels' full 64-bit path
     yield "huio_wide_64bit_coefs", I.random_huio(60, 240, [1, 2, 3, 4], -2000, 2000, 5, r), 10, 8, RULES
+    # the serving stream's dense heat-bath shape (width 2001, squared variables) over a longer
+    # schedule: most late draws have only a few lanes of nonzero weight
+    yield "dense_w2001_cold", I.dense_quio(48, -1000, 1000, 10, 10, r), 40, 8, [sa.HEAT_BATH]
 
 
 @pytest.mark.parametrize("case", list(small_cases()), ids=lambda c: c[0])

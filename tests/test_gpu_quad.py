@@ -110,6 +110,10 @@ def cases():
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
     yield "hub_rows", hub_huio(r), 20, 16
     yield "uneven_widths", uneven(I.erdos_renyi_quio(300, 5.0, -4, 4, 6, 6, r))
+    # the factored weights with no place past the range (104 of 104) and at the most places the
+    # 32-value class allows (120 of 128)
+    yield "er_w104", I.erdos_renyi_quio(600, 5.0, -52, 51, 9, 9, r), 25, 32
+    yield "er_w120", I.erdos_renyi_quio(500, 5.0, -60, 59, 8, 8, r), 25, 32
 
 
 @pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
