@@ -570,6 +570,32 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
     if (linear) {
         from_top = to_i64<Acc>(C.a[1]) < 0;
         slope = from_top ? (Acc)0 - C.a[1] : C.a[1];
+    } else if (kMaxE == 2 && c > 8) {
+        // dE(v) = a2 v^2 + a1 v + const: over the lane's values its minimum is at an end or at an
+        // integer next to the vertex v = -a1 / (2 a2) (a2 > 0).  The vertex's index, computed in
+        // double, is within one of the exact one, so the integers floor(t) - 1 .. floor(t) + 2 hold
+        // the minimisers; every candidate is evaluated exactly.
+        if (j0 < W32) {
+            const uint32_t jh = j0 + c - 1u < W32 ? j0 + c - 1u : W32 - 1u;
+            const int64_t dl = poly_delta(C, zk, lo + (int64_t)j0), dh = poly_delta(C, zk, lo + (int64_t)jh);
+            dlane = dl < dh ? dl : dh;
+            const int64_t a1 = to_i64<Acc>(C.a[1]), a2 = to_i64<Acc>(C.a[kMaxE >= 2 ? 2 : 1]);
+            if (a2 > 0) {
+                const double t = -(double)a1 / (2.0 * (double)a2) - (double)lo;
+                if (t > (double)j0 - 2.0 && t < (double)jh + 2.0) {
+                    const int64_t f = (int64_t)__builtin_floor(t);
+#pragma unroll
+                    for (int e = -1; e <= 2; ++e) {
+                        const int64_t j = f + e;
+                        if (j >= (int64_t)j0 && j <= (int64_t)jh) {
+                            const int64_t d = poly_delta(C, zk, lo + j);
+                            dlane = d < dlane ? d : dlane;
+                        }
+                    }
+                }
+            }
+        }
+        dmin = wave_min_i64(dlane);
     } else {
         for (uint32_t i = 0; i < c; ++i) {
             const uint32_t j = j0 + i;
@@ -594,6 +620,69 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             x = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)d - (uint32_t)dmin) : (double)(d - dmin);
         }
         return exp_nonpos(-(beta * x));
+    };
+
+    // Cold draws over wide ranges: a lane whose smallest x gives beta x >= 746 holds only weights
+    // of exactly 0 (its other values have larger x, and the rounded products beta x do not
+    // decrease), as R37 uses.  When the lanes holding a nonzero weight are contiguous and hold at
+    // most kColdPasses * 64 values, only those values are evaluated, one per lane and 64 at a time,
+    // with the same weights: the values outside add nothing to any cumulative sum, so the first
+    // value whose cumulative weight exceeds U * total is the same one up to the order of the
+    // additions (here the DPP scan of each pass, then the passes).  Returns false otherwise.
+    constexpr uint32_t kColdPasses = 4;
+    auto cold_draw = [&](int64_t &v) -> bool {
+        bool live = false;
+        if (j0 < W32) {
+            double xl;
+            if (linear) {
+                // the lane's value nearest the minimising end
+                const uint32_t jn = from_top ? (j0 + c - 1u < W32 ? j0 + c - 1u : W32 - 1u) : j0;
+                const Acc g = slope * (Acc)(from_top ? W32 - 1u - jn : jn);
+                xl = sizeof(Acc) == 4 ? (double)(uint32_t)g : (double)(int64_t)g;
+            } else {
+                xl = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)dlane - (uint32_t)dmin) : (double)(dlane - dmin);
+            }
+            live = !(beta * xl >= 746.0);   // a NaN product counts as live
+        }
+        const uint64_t lmask = __ballot(live);
+        if (lmask == 0) return false;
+        const int first = __ffsll((unsigned long long)lmask) - 1;
+        const uint64_t runs = lmask >> first;
+        const uint32_t nlive = (uint32_t)__popcll(lmask);
+        const uint32_t jA = (uint32_t)first * c;
+        const uint32_t jE = jA + nlive * c < W32 ? jA + nlive * c : W32;
+        if ((runs & (runs + 1)) != 0 || jE - jA > kColdPasses * (uint32_t)kWave) return false;   // uniform
+        double incl[kColdPasses], ptot[kColdPasses];
+#pragma unroll
+        for (uint32_t p = 0; p < kColdPasses; ++p) {
+            incl[p] = 0.0;
+            ptot[p] = 0.0;
+            if (jA + p * kWave < jE) {   // uniform
+                const uint32_t j = jA + p * kWave + (uint32_t)lane;
+                const double wv = weight(j < jE ? j : jE - 1u);
+                incl[p] = wave_scan_rows(j < jE ? wv : 0.0, cy);
+                ptot[p] = __longlong_as_double((long long)lane_read64((uint64_t)__double_as_longlong(incl[p]), kWave - 1));
+            }
+        }
+        double total = 0.0;
+#pragma unroll
+        for (uint32_t p = 0; p < kColdPasses; ++p) total += ptot[p];
+        const double thr = U * total;
+        double carry = 0.0;
+#pragma unroll
+        for (uint32_t p = 0; p < kColdPasses; ++p) {
+            if (jA + p * kWave < jE) {
+                const uint32_t j = jA + p * kWave + (uint32_t)lane;
+                const uint64_t hm = __ballot(j < jE && carry + incl[p] > thr);
+                if (hm) {
+                    v = lo + (int64_t)(jA + p * kWave) + (int64_t)(__ffsll((unsigned long long)hm) - 1);
+                    return true;
+                }
+                carry += ptot[p];
+            }
+        }
+        v = lo + W - 1;   // rounding left no value past the threshold
+        return true;
     };
 
     constexpr int kR = kRegChunk > 0 ? kRegChunk : 1;
@@ -624,6 +713,10 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             lane_sum = i == 0 ? w[0] : lane_sum + w[i];
         }
     } else if (kRegChunk > 0) {
+        if constexpr (kRegChunk >= 8) {
+            int64_t vc;
+            if (cold_draw(vc)) return vc;
+        }
 #pragma unroll
         for (int i = 0; i < kR; ++i) {
             // evaluated for every slot (at a clamped index past the range) so that the exps of a
@@ -634,65 +727,8 @@ __device__ __forceinline__ int64_t heat_bath_pick(const Coeffs<kMaxE, Acc> &C, i
             lane_sum = i == 0 ? w[0] : lane_sum + w[i];
         }
     } else {
-        // Cold draws over wide ranges: a lane whose smallest x gives beta x >= 746 holds only
-        // weights of exactly 0 (its other values have larger x, and the rounded products beta x
-        // do not decrease), as R37 uses.  When the lanes holding a nonzero weight are contiguous
-        // and hold at most kColdPasses * 64 values, only those values are evaluated, one per lane
-        // and 64 at a time, with the same weights: the values outside add nothing to any
-        // cumulative sum, so the first value whose cumulative weight exceeds U * total is the same
-        // one up to the order of the additions (here the DPP scan of each pass, then the passes).
-        constexpr uint32_t kColdPasses = 4;
-        bool live = false;
-        if (j0 < W32) {
-            double xl;
-            if (linear) {
-                // the lane's value nearest the minimising end
-                const uint32_t jn = from_top ? (j0 + c - 1u < W32 ? j0 + c - 1u : W32 - 1u) : j0;
-                const Acc g = slope * (Acc)(from_top ? W32 - 1u - jn : jn);
-                xl = sizeof(Acc) == 4 ? (double)(uint32_t)g : (double)(int64_t)g;
-            } else {
-                xl = sizeof(Acc) == 4 ? (double)(int32_t)((uint32_t)dlane - (uint32_t)dmin) : (double)(dlane - dmin);
-            }
-            live = !(beta * xl >= 746.0);   // a NaN product counts as live
-        }
-        const uint64_t lmask = __ballot(live);
-        if (lmask != 0) {
-            const int first = __ffsll((unsigned long long)lmask) - 1;
-            const uint64_t runs = lmask >> first;
-            const uint32_t nlive = (uint32_t)__popcll(lmask);
-            const uint32_t jA = (uint32_t)first * c;
-            const uint32_t jE = jA + nlive * c < W32 ? jA + nlive * c : W32;
-            if ((runs & (runs + 1)) == 0 && jE - jA <= kColdPasses * (uint32_t)kWave) {   // uniform
-                double incl[kColdPasses], ptot[kColdPasses];
-#pragma unroll
-                for (uint32_t p = 0; p < kColdPasses; ++p) {
-                    incl[p] = 0.0;
-                    ptot[p] = 0.0;
-                    if (jA + p * kWave < jE) {   // uniform
-                        const uint32_t j = jA + p * kWave + (uint32_t)lane;
-                        const double wv = weight(j < jE ? j : jE - 1u);
-                        incl[p] = wave_scan_rows(j < jE ? wv : 0.0, cy);
-                        ptot[p] = __longlong_as_double(
-                            (long long)lane_read64((uint64_t)__double_as_longlong(incl[p]), kWave - 1));
-                    }
-                }
-                double total = 0.0;
-#pragma unroll
-                for (uint32_t p = 0; p < kColdPasses; ++p) total += ptot[p];
-                const double thr = U * total;
-                double carry = 0.0;
-#pragma unroll
-                for (uint32_t p = 0; p < kColdPasses; ++p) {
-                    if (jA + p * kWave < jE) {
-                        const uint32_t j = jA + p * kWave + (uint32_t)lane;
-                        const uint64_t hm = __ballot(j < jE && carry + incl[p] > thr);
-                        if (hm) return lo + (int64_t)(jA + p * kWave) + (int64_t)(__ffsll((unsigned long long)hm) - 1);
-                        carry += ptot[p];
-                    }
-                }
-                return lo + W - 1;   // rounding left no value past the threshold
-            }
-        }
+        int64_t vc;
+        if (cold_draw(vc)) return vc;
         for (uint32_t i = 0; i < c; i += kGroup) {
             double wv[kGroup];
 #pragma unroll
