@@ -369,6 +369,40 @@ __device__ __forceinline__ int64_t quad_argmin(const Coeffs<kMaxE, Acc> &C, int6
     return quad_min_i64(best == dbest ? bv : INT64_MAX);
 }
 
+// The same optimal transition for a variable whose dE holds only the exponents 1 and 2:
+// dE(v) = a2 v^2 + a1 v + const.  Its smallest value over the range is at an end, or (a2 > 0) at
+// an integer next to the vertex -a1 / (2 a2); the vertex's computed value is within one of the
+// exact one, so floor(t) - 1 .. floor(t) + 2 hold those integers.  With z_k (dE = 0) added, the
+// seven candidates hold every value of smallest dE that the enumeration's lowest-value rule can
+// pick; each is evaluated exactly, two per lane, ties to the lowest value.
+template <int kMaxE, typename Acc>
+__device__ __forceinline__ int64_t quad_argmin_quadratic(const Coeffs<kMaxE, Acc> &C, int64_t lo, int64_t W,
+                                                         int64_t zk, int ql, int64_t &dbest) {
+    const int64_t hi = lo + W - 1;
+    const int64_t a1 = to_i64<Acc>(C.a[1]), a2 = to_i64<Acc>(C.a[kMaxE >= 2 ? 2 : 1]);
+    int64_t f = lo;
+    if (kMaxE >= 2 && a2 > 0) {
+        const double t = -(double)a1 / (2.0 * (double)a2);
+        f = t < (double)lo ? lo : t > (double)hi ? hi : (int64_t)__builtin_floor(t);
+    }
+    int64_t best = INT64_MAX, bv = INT64_MAX;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = ql + 4 * u;   // candidates 0..6: lo, hi, z_k, f - 1 .. f + 2
+        if (i < 7) {
+            int64_t v = i == 0 ? lo : i == 1 ? hi : i == 2 ? zk : f + (int64_t)(i - 4);
+            v = v < lo ? lo : v > hi ? hi : v;
+            const int64_t d = poly_delta(C, zk, v);
+            if (d < best || (d == best && v < bv)) {
+                best = d;
+                bv = v;
+            }
+        }
+    }
+    dbest = quad_min_i64(best);
+    return quad_min_i64(best == dbest ? bv : INT64_MAX);
+}
+
 // kRule: SA_HEAT_BATH, or SA_HEAT_BATH_CLOSED (the O(1) draw of Sec. 3.3.2 for variables whose
 // energy difference is linear, the enumeration for the others).  kR: values per lane (W <= 4 kR).
 // kFact: the factored weights of linear variables (quad_heat_bath), for launches whose variables

@@ -208,7 +208,8 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
                         v = to_i64<Acc>(C.a[1]) >= 0 ? lo : lo + W - 1;
                         d = to_i64<Acc>(C.a[1] * (Acc)(v - zk));
                     } else {
-                        v = quad_argmin<kR, kMaxE, Acc>(C, lo, W, zk, ql, d);
+                        v = (emask & ~6u) == 0 ? quad_argmin_quadratic<kMaxE, Acc>(C, lo, W, zk, ql, d)
+                                               : quad_argmin<kR, kMaxE, Acc>(C, lo, W, zk, ql, d);
                     }
                 } else {
                     v = lo + (int64_t)(((uint64_t)x1 * (uint64_t)(W - 1)) >> 32);
