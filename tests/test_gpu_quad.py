@@ -142,6 +142,9 @@ def mo_cases():
     yield "single_variable", I.from_terms(1, [(3, [0, 0]), (-7, [0])], -5, 6), 30, 8
     yield "hub_rows", hub_huio(r), 20, 16
     yield "uneven_widths", uneven(I.random_huio(300, 1200, [1, 2, 3], -4, 4, 5, r)), 20, 16
+    # squared terms with coefficients in {-1, 0, 1}: many values share the smallest dE, so the
+    # optimal transition's lowest-value rule decides often (the argmin from the vertex's neighbours)
+    yield "squares_ties_w61", I.random_huio(400, 1200, [1, 2], -30, 30, 1, r), 25, 32
 
 
 @pytest.mark.parametrize("case", list(mo_cases()), ids=lambda c: c[0])
