@@ -17,8 +17,9 @@
 // sums of the plain sequential definition; the drawn value is the first v with C_v > U * C_u,
 // i.e. the number of C_v <= U * C_u (C never decreases), summed over the quad.  The factored
 // variant (every variable of the launch has one width) forms a linear variable's weights as
-// products of two exponentials and adds them in lane blocks (quad_heat_bath): its sums differ
-// from the sequential ones in the last bits.
+// products of an exponential and powers of another, in order of distance from the minimising
+// end, and adds them in lane blocks (quad_heat_bath): its sums differ from the sequential ones
+// by rounding.
 #pragma once
 
 #include "sa_device.h"
