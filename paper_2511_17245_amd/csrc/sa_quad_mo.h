@@ -176,7 +176,9 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
                 Part a[kMaxE + 1];
 #pragma unroll
                 for (int m = 0; m <= kMaxE; ++m) a[m] = 0;
-                add_records<kMaxE, Part, kNarrow>(z, cur, deg, a, __ballot(!linear) == 0);
+                // no quad of the wave has a term with z_k to a power above one (uniform)
+                const bool all_linear = kMaxE == 1 || __ballot(!linear) == 0;
+                add_records<kMaxE, Part, kNarrow>(z, cur, deg, a, all_linear);
                 if (__ballot(rest != 0) != 0) {
                     // records with more than three other factors, and rows longer than the copy
                     // covers: one by one from the incidence records
@@ -214,7 +216,8 @@ __global__ void __launch_bounds__(kWave) quad_mo_kernel(QuadArgs A) {
                 } else {
                     v = lo + (int64_t)(((uint64_t)x1 * (uint64_t)(W - 1)) >> 32);
                     if (v >= zk) v += 1;
-                    d = poly_delta(C, zk, v);
+                    // a linear variable's a_k^(m), m >= 2, are zero: dE = a1 (v - z_k), the same ring value
+                    d = all_linear ? to_i64<Acc>(C.a[1] * (Acc)(v - zk)) : poly_delta(C, zk, v);
                 }
                 if (valid && v != zk && metropolis_accept(d, beta, U)) {
                     z[k] = (int32_t)v;   // the quad's four lanes store the same value
