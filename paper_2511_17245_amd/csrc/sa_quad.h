@@ -485,6 +485,9 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                 for (int q = 0; q < 4; ++q) {
                     const int32_t idx = batch + q * kQuads + qid;
                     if (batch + q * kQuads >= b1) break;   // uniform: the level has no round q here
+                    // the round's reads go out at a raised wave priority, so that they start under
+                    // the other waves' arithmetic; the arithmetic runs at the normal priority
+                    __builtin_amdgcn_s_setprio(2);
                     const int src = ((lane & ~3) | q) << 2;
                     auto from_q = [&](uint32_t v) { return (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)v); };
                     const int32_t k = (int32_t)from_q((uint32_t)ms.k);
@@ -505,6 +508,7 @@ __global__ void __launch_bounds__(kWaves * 64) quad_kernel(QuadArgs A) {
                         } else {
                             quad_coeffs<kMaxE, Acc>(P, z, row, deg, emask, ql, C);
                         }
+                        __builtin_amdgcn_s_setprio(0);
                         const bool linear = kMaxE == 1 || (emask & ~2u) == 0;
                         int64_t v;
                         if (kRule == SA_HEAT_BATH_CLOSED && linear) {
